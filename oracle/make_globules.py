@@ -1,0 +1,160 @@
+"""Write compact-globule starting dihedrals to ``data/globule_m<m>.npy``.
+
+Input preparation only (never timed).  The chain is grown one residue at a
+time inside a sphere of radius sqrt(5/3) * Rg_target (a filled ball of that
+radius has radius of gyration Rg_target), with Rg_target = 2.2 m^0.38 A.  For
+each residue K (phi, psi) candidates are drawn around the Ramachandran basins;
+the candidate with the fewest contacts closer than ``clash`` A to earlier
+non-excluded atoms (then the least excursion beyond the sphere) is kept.
+Positions come from the oracle's forward kinematics only.  The radius is
+rescaled until the final Rg is within 5 % of the target.
+
+Usage: python -m oracle.make_globules 1000 10000
+"""
+from __future__ import annotations
+
+import os
+import sys
+
+import numpy as np
+from scipy.spatial import cKDTree
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import oracle  # noqa: E402
+import synth  # noqa: E402
+
+BASINS = np.radians(np.array([  # (phi, psi, spread) of the broad Ramachandran regions
+    [-63.0, -43.0, 15.0],
+    [-120.0, 130.0, 20.0],
+    [-75.0, 145.0, 15.0],
+    [60.0, 45.0, 15.0],
+]))
+
+
+def _excluded_pairs(ch):
+    """(slot_prev, slot_cur) pairs of adjacent residues within three bonds."""
+    ex = np.zeros((10, 10), dtype=bool)
+    for a in range(10):
+        for b in range(10):
+            ex[a, b] = ch.bond_path(10 + a, 20 + b) <= 3
+    return ex
+
+
+def grow(m: int, radius: float, seed: int, K: int = 24, clash: float = 2.0):
+    types = synth.residue_types()
+    ch = oracle.OracleChain(np.zeros(m, np.int32), types)
+    ex_prev = _excluded_pairs(oracle.OracleChain(np.zeros(4, np.int32), types))
+    rng = np.random.default_rng(seed)
+    theta = np.full(2 * m, np.pi)
+    cell = clash
+    span = int(np.ceil(2 * (radius + 20.0) / cell)) + 4
+    off = span // 2
+    grid = np.full((span, span, span, 8), -1, dtype=np.int32)
+    slot_of = np.full((10 * m, 4), -1, dtype=np.int32)  # cell (3) + slot of each placed atom
+    pos = np.zeros((10 * m, 3))
+    nbr = np.array([(i, j, k) for i in (-1, 0, 1) for j in (-1, 0, 1) for k in (-1, 0, 1)])
+
+    def cells(p):
+        return np.clip(np.floor(p / cell).astype(int) + off, 1, span - 2)
+
+    def insert(a):
+        g = cells(pos[a][None])[0]
+        free = np.nonzero(grid[g[0], g[1], g[2]] < 0)[0]
+        if free.size == 0:
+            raise RuntimeError("grid cell overflow")
+        grid[g[0], g[1], g[2], free[0]] = a
+        slot_of[a] = (g[0], g[1], g[2], free[0])
+
+    def remove(a):
+        g = slot_of[a]
+        if g[0] >= 0:
+            grid[g[0], g[1], g[2], g[3]] = -1
+            slot_of[a] = -1
+
+    def clashes(k, new):
+        cc = cells(new)[:, None, :] + nbr[None]
+        ids = grid[cc[..., 0], cc[..., 1], cc[..., 2]].reshape(10, -1)
+        bad = 0
+        for a in range(10):
+            js = ids[a][ids[a] >= 0]
+            if js.size == 0:
+                continue
+            close = np.linalg.norm(pos[js] - new[a], axis=1) < clash
+            if k > 0:
+                close &= ~((js // 10 == k - 1) & ex_prev[js % 10, a])
+            bad += int(close.sum())
+        return bad
+
+    fails = np.zeros(m, dtype=np.int64)
+    k = 0
+    while k < m:
+        best, best_key = None, None
+        for width in (K, 4 * K):
+            b = BASINS[rng.integers(0, len(BASINS), width)]
+            cand = b[:, :2] + rng.normal(size=(width, 2)) * b[:, 2:3]
+            for c in range(width):
+                theta[2 * k: 2 * k + 2] = cand[c]
+                r = oracle.fk_prefix(ch, theta, min(k + 2, m))
+                new = r[10 * k: 10 * k + 10]
+                tip = r[10 * (k + 1)] if k + 1 < m else r[10 * k + 8]  # N_{k+1} moves with phi_k and psi_k
+                key = (clashes(k, new), max(0.0, np.linalg.norm(tip) - radius))
+                if best_key is None or key < best_key:
+                    best, best_key = cand[c].copy(), key
+            if best_key[0] == 0:
+                break
+        if best_key[0] > 0:
+            fails[k] += 1
+            if fails[k] > 50:
+                raise RuntimeError(f"stuck at residue {k}")
+            back = min(k, 1 + int(fails[k]) // 3)
+            for kk in range(k - back, k):
+                for a in range(10 * kk, 10 * kk + 10):
+                    remove(a)
+            k -= back
+            continue
+        theta[2 * k: 2 * k + 2] = best
+        r = oracle.fk_prefix(ch, theta, k + 1)
+        pos[10 * k: 10 * k + 10] = r[10 * k: 10 * k + 10]
+        for a in range(10 * k, 10 * k + 10):
+            insert(a)
+        k += 1
+    return theta, pos, ch
+
+
+def min_nonexcluded_distance(ch, pos, limit=2.5):
+    tree = cKDTree(pos)
+    pairs = tree.query_pairs(limit, output_type="ndarray")
+    best = np.inf
+    for a, b in pairs:
+        if abs(a // 10 - b // 10) <= 1 and ch.bond_path(int(a), int(b)) <= 3:
+            continue
+        best = min(best, float(np.linalg.norm(pos[a] - pos[b])))
+    return best
+
+
+def make(m: int, seed: int = 0):
+    target = 2.2 * m ** 0.38
+    radius = np.sqrt(5.0 / 3.0) * target
+    for attempt in range(6):
+        theta, pos, ch = grow(m, radius, seed + attempt)
+        rg = float(np.sqrt(((pos - pos.mean(0)) ** 2).sum(1).mean()))
+        dmin = min_nonexcluded_distance(ch, pos)
+        print(f"m={m} radius={radius:.2f} Rg={rg:.2f} target={target:.2f} min_d={dmin:.3f}", flush=True)
+        if abs(rg / target - 1.0) < 0.05 and dmin > 1.5:
+            break
+        radius *= target / rg
+    else:
+        raise RuntimeError(f"no acceptable globule for m={m}")
+    theta = (theta + np.pi) % (2 * np.pi) - np.pi
+    theta[theta <= -np.pi] += 2 * np.pi
+    out = os.path.join(ROOT, "data", f"globule_m{m}.npy")
+    np.save(out, theta)
+    print("wrote", out, flush=True)
+
+
+if __name__ == "__main__":
+    for arg in sys.argv[1:] or ["1000"]:
+        make(int(arg))

@@ -284,3 +284,11 @@ def iterate(chain: OracleChain, theta, pp: PairParams = PairParams(), sp: SasaPa
 
 def threads() -> int:
     return int(_load().or_threads())
+
+
+def fk_prefix(chain: OracleChain, theta, k: int):
+    """Positions of the first k residues (they depend on theta[:2k] only)."""
+    th = np.ascontiguousarray(theta[: 2 * k], dtype=np.float64)
+    r = np.zeros((APR * k, 3))
+    _load().or_fk(int(k), np.ascontiguousarray(chain.r0[: APR * k]), th, r, None, None)
+    return r
