@@ -1,0 +1,194 @@
+/*
+ * kcm.h -- C ABI of libkcm, the gfx950 (MI355X) implementation of one
+ * iteration of the kinetostatic compliance method (KCM) of Protofold II
+ * (Tavousi, Behandish, Ilies, Kazerounian): forward kinematics, a cell list,
+ * Coulomb + Lennard-Jones + SASA-enumeration solvation forces, Jacobian-
+ * transpose joint torques and the compliance step.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  * Units: Angstrom, elementary charge, kcal/mol, radian.  Torque is in
+ *    kcal/mol per radian, kappa in radian per (kcal/mol).
+ *  * A chain of m residues has n = 10 m atoms, J = 2 m joints and 2 m + 1
+ *    links.  Atom 10 i + s is slot s of residue i, slots in the order
+ *    N, H, CA, HA, CB, HB1, HB2, HB3, C, O.  Joint 2 i is phi_i (axis N_i->CA_i),
+ *    joint 2 i + 1 is psi_i (axis CA_i->C_i); joint j turns every atom of the
+ *    links after it (Sec. 2.1, Table 2).  omega is fixed at 180 degrees.
+ *  * Angles theta are the dihedrals phi/psi themselves, in (-pi, pi]; the zero
+ *    position (ZP) of the paper's ZRPD convention is phi = psi = 180 degrees.
+ *  * Host pointers are read during the call and not kept.  Device memory is
+ *    owned by the caller: kcm_build_chain lays a chain out inside the block it
+ *    is given and never frees it.  Host-side handles are owned by the library
+ *    (kcm_chain_free).  hip_stream is a hipStream_t (NULL = default stream);
+ *    work is queued asynchronously unless a function says it synchronises.
+ *  * Every function returns a kcm_status; no exception crosses the ABI.  The
+ *    calling thread's last error message is available from kcm_last_error().
+ *  * A numeric failure (NaN/Inf in forces or torques) marks only the chain it
+ *    occurs in: its theta is left unchanged, its report carries
+ *    KCM_E_NUMERIC, and the other chains of a batched call continue.
+ */
+#ifndef KCM_H
+#define KCM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    KCM_OK = 0,
+    KCM_E_INVAL = -1,    /* bad argument */
+    KCM_E_NOMEM = -2,    /* the given device block is too small */
+    KCM_E_DEVICE = -3,   /* a HIP runtime call failed */
+    KCM_E_NUMERIC = -4,  /* NaN/Inf in this chain's forces or torques */
+    KCM_E_STATE = -5,    /* call not valid in the handle's current state */
+    KCM_E_CAPACITY = -6  /* a per-atom neighbour list overflowed its fixed capacity */
+} kcm_status;
+
+enum { KCM_STEP_CAPPED = 0, KCM_STEP_PAPER = 1, KCM_STEP_LINEAR = 2 };
+enum { KCM_FP64 = 0, KCM_MIXED = 1 };
+enum { KCM_TERM_ELEC = 1, KCM_TERM_VDW = 2, KCM_TERM_CAV = 4, KCM_TERM_ALL = 7 };
+
+/* Force-field inputs of one residue type, per atom slot (slot order above). */
+typedef struct {
+    double q[10];          /* partial charge, e */
+    double sigma[10];      /* Lennard-Jones sigma, A; vdW radius R = 2^(1/6) sigma / 2 */
+    double eps[10];        /* Lennard-Jones well depth, kcal/mol */
+    double hydrophobicity; /* residue hydrophobicity; gamma = g_hydro * hydrophobicity */
+} kcm_residue_type;
+
+/* What defines one chain (the paper's Fig. 5 steps 1-3 and user options). */
+typedef struct {
+    int32_t n_res;                  /* m >= 1 */
+    const int32_t *res_type;        /* [m], values in 0 .. n_types-1 */
+    const kcm_residue_type *types;  /* [n_types] */
+    int32_t n_types;
+    const double *theta0;           /* [2m] initial phi_1, psi_1, ...; NULL = ZP */
+    const uint8_t *joint_mask;      /* [2m] 0 = joint held fixed (Sec. 4.1 options); NULL = all free */
+} kcm_chain_desc;
+
+/* Method parameters.  kcm_default_params() fills the defaults listed here. */
+typedef struct {
+    double cutoff;      /* 10.0  Coulomb and LJ cutoff, pairs with d <= cutoff count (eqs 02_2, 03_2) */
+    double kappa;       /* 1e-3  compliance, rad per kcal/mol (eq KCM_07) */
+    double max_step;    /* 1e-3  s: the largest joint step of the PAPER and CAPPED rules, rad */
+    int32_t step_rule;  /* KCM_STEP_CAPPED: kappa tau min(1, s/(kappa |tau|max));
+                           KCM_STEP_PAPER: s tau/|tau|max (eq KCM_07); KCM_STEP_LINEAR: kappa tau */
+    int32_t precision;  /* KCM_FP64, or KCM_MIXED: FP32 pair and sample tests (FP64 recheck near
+                           ties), FP64 kinematics, torques and step */
+    int32_t terms;      /* KCM_TERM_* bitmask; ELEC and VDW go together */
+    int32_t n_orbits;   /* 14 -> N = 250 samples per offset sphere (Sec. 3.4) */
+    double diel_k;      /* 4.0   distance-dependent dielectric eps = diel_k * d (Sec. 2.2) */
+    double w13;         /* 0.0   weight of 1-3 pairs (1-2 pairs are always 0) (eqs 03_8, 03_9) */
+    double w14_elec;    /* 1/1.2 Coulomb weight of 1-4 pairs */
+    double w14_vdw;     /* 0.5   LJ weight of 1-4 pairs */
+    double delta_r;     /* 0.05  finite difference of eq (finitediff), A */
+    double r_probe;     /* 1.4   water probe radius added to R (Sec. 2.2) */
+    double g_hydro;     /* 0.025 kcal/mol/A^2 per unit hydrophobicity */
+    double cell_size;   /* 0 = automatic (cutoff / 2, coarsened when the grid exceeds its capacity) */
+} kcm_params;
+
+/* Per chain, after a kcm_step call: values of the chain's last iteration. */
+typedef struct {
+    double e_elec, e_vdw, e_cav; /* energies of the conformation the forces were taken at */
+    double max_tau;              /* max |tau| over free joints */
+    double max_dtheta;           /* max |dtheta| applied */
+    int64_t iterations;          /* iterations applied to this chain since it was built */
+    int32_t status;              /* KCM_OK, KCM_E_NUMERIC or KCM_E_CAPACITY */
+    int32_t converged;           /* 1 once max|dtheta| < tol under kcm_fold */
+} kcm_step_report;
+
+typedef struct {
+    int64_t iterations;  /* iterations run by this call */
+    int32_t converged;   /* max|dtheta| < tol reached */
+    int32_t status;
+    double seconds;      /* wall time of the call */
+} kcm_fold_result;
+
+typedef struct kcm_chain kcm_chain;
+
+/* Fill *p with the defaults above. */
+void kcm_default_params(kcm_params *p);
+
+/* Bytes of caller-owned device memory a chain needs (256-byte aligned block).
+ * Depends on n_res and params->n_orbits only. */
+kcm_status kcm_chain_bytes(const kcm_chain_desc *desc, const kcm_params *params, size_t *bytes);
+
+/* Build a chain (Fig. 5 steps 1-3): zero-position geometry from the residue
+ * template, bond-path interaction classes (Sec. 3.3), per-atom parameters, the
+ * offset-sphere sample set, and theta0.  Lays everything out in dev_mem (at
+ * least kcm_chain_bytes bytes, device memory of the current device) with
+ * asynchronous copies on hip_stream and returns a host handle in *out.
+ * Errors: KCM_E_INVAL (bad desc/params), KCM_E_NOMEM (bytes too small),
+ * KCM_E_DEVICE. */
+kcm_status kcm_build_chain(const kcm_chain_desc *desc, const kcm_params *params, void *dev_mem,
+                           size_t bytes, void *hip_stream, kcm_chain **out);
+
+/* Run n_iter KCM iterations on each of n_chains chains (Fig. 5 steps 4-8):
+ * forward kinematics (eqs kin_02-kin_04, r1), cell list (Sec. 3.2), pair and
+ * solvation forces (eqs 02-04_3, G_cav_patch, F_cav_patch, finitediff,
+ * Algorithm 1), link wrenches and joint torques (eqs KCM_01-KCM_06, row scan
+ * of eq 04_9), and the compliance step (eq KCM_07).  All chains of one call
+ * must share precision and live on the current device; the chains are
+ * processed together in one set of launches per iteration.  Chains already
+ * converged under kcm_fold are skipped.  If reports != NULL the call
+ * synchronises hip_stream and fills reports[n_chains]; otherwise it only
+ * queues work.  Returns KCM_E_NUMERIC / KCM_E_CAPACITY if any chain reported
+ * it (the other chains are still advanced). */
+kcm_status kcm_step(kcm_chain *const *chains, int n_chains, int n_iter, void *hip_stream,
+                    kcm_step_report *reports);
+
+/* Iterate every chain until max|dtheta| < tol_dtheta or max_iter iterations
+ * (Fig. 5 step 9); convergence is polled every check_every iterations (>= 1).
+ * Synchronises hip_stream.  results[n_chains] may be NULL. */
+kcm_status kcm_fold(kcm_chain *const *chains, int n_chains, double tol_dtheta, int max_iter,
+                    int check_every, void *hip_stream, kcm_fold_result *results);
+
+/* Copy a chain's state to host arrays (any pointer may be NULL); synchronises
+ * hip_stream.  theta[J] and dtheta[J] (last applied step); xyz[n][3] and
+ * force[n][3] (total) at the conformation of the last force evaluation;
+ * tau[J]. */
+kcm_status kcm_get_state(const kcm_chain *chain, void *hip_stream, double *theta, double *xyz,
+                         double *force, double *tau, double *dtheta);
+
+/* Per-term forces of the last evaluation: pair (Coulomb + LJ) and solvation,
+ * host arrays [n][3]; synchronises hip_stream. */
+kcm_status kcm_get_forces(const kcm_chain *chain, void *hip_stream, double *f_pair, double *f_cav);
+
+/* Replace a chain's theta (host array [J]), e.g. to resume from a checkpoint
+ * or to re-synchronise with a reference; clears its converged flag. */
+kcm_status kcm_set_theta(kcm_chain *chain, const double *theta, void *hip_stream);
+
+/* The cell list of the last evaluation (Sec. 3.2): dims[3] cells per axis,
+ * *cell_size (A), origin[3] (grid corner), order[n] (atom index of each
+ * sorted slot), cell_start[dims0*dims1*dims2 + 1].  Any pointer may be NULL;
+ * *n_cells receives the cell count.  Synchronises hip_stream. */
+kcm_status kcm_get_cells(const kcm_chain *chain, void *hip_stream, int32_t *dims, double *cell_size,
+                         double *origin, int32_t *n_cells, int32_t *order, int32_t *cell_start,
+                         int32_t cell_start_capacity);
+
+/* Sizes of a built chain. */
+kcm_status kcm_chain_info(const kcm_chain *chain, int32_t *n_atoms, int32_t *n_joints,
+                          int32_t *n_samples, int32_t *precision);
+
+/* Optional per-kernel timing with hipEvents on the launch stream: when on,
+ * kcm_step records an event pair around every force-kernel launch.
+ * kcm_get_timing returns the summed milliseconds and launch count of the
+ * force kernel and of the whole iteration since the last reset (synchronises
+ * every stream it recorded on). */
+kcm_status kcm_set_timing(int enable);
+kcm_status kcm_get_timing(double *force_ms, int64_t *force_launches, double *iter_ms,
+                          int64_t *iterations, int reset);
+
+/* Release a handle (not the device block). */
+kcm_status kcm_chain_free(kcm_chain *chain);
+
+/* Message of the calling thread's last failing call ("" if none). */
+const char *kcm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KCM_H */

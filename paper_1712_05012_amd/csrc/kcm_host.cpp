@@ -1,0 +1,818 @@
+// kcm_host.cpp -- host runtime of libkcm: chain construction, device block
+// layout, batch tables, launch sequencing and the C ABI declared in kcm.h.
+#include "../../include/kcm.h"
+#include "kcm_internal.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <mutex>
+#include <string>
+#include <vector>
+
+using namespace kcm;
+
+namespace {
+
+thread_local std::string g_err;
+
+kcm_status fail(kcm_status s, const std::string &msg)
+{
+    g_err = msg;
+    return s;
+}
+
+#define HIP_TRY(expr)                                                                         \
+    do {                                                                                      \
+        hipError_t e_ = (expr);                                                               \
+        if (e_ != hipSuccess)                                                                 \
+            return fail(KCM_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));     \
+    } while (0)
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kCoulomb = 332.0636;  // kcal A / (mol e^2)
+
+// ---------------------------------------------------------------------------
+// residue template and zero position (Sec. 2.1)
+// ---------------------------------------------------------------------------
+struct V3 {
+    double x, y, z;
+};
+V3 operator+(V3 a, V3 b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
+V3 operator-(V3 a, V3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+V3 operator*(V3 a, double s) { return {a.x * s, a.y * s, a.z * s}; }
+double dot(V3 a, V3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+V3 cross(V3 a, V3 b) { return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x}; }
+V3 unit(V3 a) { return a * (1.0 / std::sqrt(dot(a, a))); }
+
+// Atom d bonded to c with |cd| = len, angle b-c-d = ang, torsion a-b-c-d = tor (degrees).
+V3 nerf(V3 a, V3 b, V3 c, double len, double ang, double tor)
+{
+    const V3 e1 = unit(c - b);
+    const V3 nrm = unit(cross(b - a, e1));
+    const V3 e2 = cross(nrm, e1);
+    const double th = ang * kPi / 180.0, ph = tor * kPi / 180.0;
+    return c + e1 * (-len * std::cos(th)) + e2 * (len * std::sin(th) * std::cos(ph)) + nrm * (len * std::sin(th) * std::sin(ph));
+}
+
+enum Slot { N_ = 0, H_, CA_, HA_, CB_, HB1_, HB2_, HB3_, C_, O_ };
+
+// Ideal backbone (N-CA 1.458, CA-C 1.525, C-N 1.329 A; N-CA-C 111.2, CA-C-N 116.2,
+// C-N-CA 121.7, CA-C=O 120.8 deg), tetrahedral CA and CB, amide H in plane.
+// phi = psi = omega = 180 deg; N of residue 0 at the origin, CA on +x, C in the xy plane.
+std::vector<V3> zero_position(int m)
+{
+    std::vector<V3> at(APR * m);
+    auto A = [&](int i, int s) -> V3 & { return at[APR * i + s]; };
+    const double ang_nh = 0.5 * (360.0 - 121.7);
+    for (int i = 0; i < m; ++i) {
+        if (i == 0) {
+            A(0, N_) = {0.0, 0.0, 0.0};
+            A(0, CA_) = {1.458, 0.0, 0.0};
+            const double t = 111.2 * kPi / 180.0;
+            A(0, C_) = {1.458 - 1.525 * std::cos(t), 1.525 * std::sin(t), 0.0};
+        } else {
+            A(i, N_) = nerf(A(i - 1, N_), A(i - 1, CA_), A(i - 1, C_), 1.329, 116.2, 180.0);
+            A(i, CA_) = nerf(A(i - 1, CA_), A(i - 1, C_), A(i, N_), 1.458, 121.7, 180.0);
+            A(i, C_) = nerf(A(i - 1, C_), A(i, N_), A(i, CA_), 1.525, 111.2, 180.0);
+        }
+        A(i, H_) = nerf(A(i, C_), A(i, CA_), A(i, N_), 1.01, ang_nh, 0.0);
+        A(i, CB_) = nerf(A(i, C_), A(i, N_), A(i, CA_), 1.53, 109.5, -120.0);
+        A(i, HA_) = nerf(A(i, C_), A(i, N_), A(i, CA_), 1.09, 109.5, 120.0);
+        A(i, HB1_) = nerf(A(i, N_), A(i, CA_), A(i, CB_), 1.09, 109.5, 60.0);
+        A(i, HB2_) = nerf(A(i, N_), A(i, CA_), A(i, CB_), 1.09, 109.5, 180.0);
+        A(i, HB3_) = nerf(A(i, N_), A(i, CA_), A(i, CB_), 1.09, 109.5, -60.0);
+        A(i, O_) = nerf(A(i, N_), A(i, CA_), A(i, C_), 1.231, 120.8, 0.0);
+    }
+    return at;
+}
+
+// Interaction classes by bond-path length (Sec. 3.3), as bitmasks per slot of
+// the middle residue of a three-residue window: bit t marks window atom t
+// (t = 10 (dres + 1) + slot).  Paths of length <= 3 never leave the window, so
+// the same masks serve every residue of every chain.
+void bond_class_masks(uint32_t m12[APR], uint32_t m13[APR], uint32_t m14[APR])
+{
+    const int W = 3 * APR;
+    static const int intra[][2] = {{N_, H_},   {N_, CA_},  {CA_, HA_}, {CA_, CB_}, {CA_, C_},
+                                   {CB_, HB1_}, {CB_, HB2_}, {CB_, HB3_}, {C_, O_}};
+    std::vector<std::vector<int>> adj(W);
+    for (int r = 0; r < 3; ++r) {
+        for (auto &b : intra) {
+            adj[APR * r + b[0]].push_back(APR * r + b[1]);
+            adj[APR * r + b[1]].push_back(APR * r + b[0]);
+        }
+        if (r < 2) {
+            adj[APR * r + C_].push_back(APR * (r + 1) + N_);
+            adj[APR * (r + 1) + N_].push_back(APR * r + C_);
+        }
+    }
+    for (int s = 0; s < APR; ++s) {
+        std::vector<int> dist(W, -1), queue{APR + s};
+        dist[APR + s] = 0;
+        for (size_t h = 0; h < queue.size(); ++h)
+            for (int y : adj[queue[h]])
+                if (dist[y] < 0) {
+                    dist[y] = dist[queue[h]] + 1;
+                    queue.push_back(y);
+                }
+        m12[s] = m13[s] = m14[s] = 0;
+        for (int t = 0; t < W; ++t) {
+            if (dist[t] == 1) m12[s] |= 1u << t;
+            if (dist[t] == 2) m13[s] |= 1u << t;
+            if (dist[t] == 3) m14[s] |= 1u << t;
+        }
+    }
+}
+
+// Polar geodesic samples (Sec. 3.4): n_orb orbits at polar angles pi (o + 1/2) / n_orb,
+// round(2 n_orb sin) points on each (at least one), evenly spaced in azimuth,
+// odd orbits offset by half a step.
+std::vector<V3> sample_directions(int n_orb)
+{
+    std::vector<V3> q;
+    for (int o = 0; o < n_orb; ++o) {
+        const double polar = kPi * (o + 0.5) / n_orb;
+        const int cnt = std::max(1, (int)std::lround(2.0 * n_orb * std::sin(polar)));
+        for (int p = 0; p < cnt; ++p) {
+            const double az = 2.0 * kPi * (p + 0.5 * (o & 1)) / cnt;
+            q.push_back({std::sin(polar) * std::cos(az), std::sin(polar) * std::sin(az), std::cos(polar)});
+        }
+    }
+    return q;
+}
+
+// ---------------------------------------------------------------------------
+// device block layout
+// ---------------------------------------------------------------------------
+struct Layout {
+    size_t desc, stats, grid, theta, dtheta, tau, mask, joint0, jcur, xform, r0, r, aparam, g0, qfix;
+    size_t cell_key, cell_start, cell_fill, order, s_r, s_p, s_idx, s_cell, f_pair, f_cav, e_atom, q64, q32;
+    size_t total;
+    int n, J, L, N, cap;
+};
+
+Layout make_layout(int m, int n_orb)
+{
+    Layout l{};
+    l.n = APR * m;
+    l.J = 2 * m;
+    l.L = 2 * m + 1;
+    l.N = (int)sample_directions(n_orb).size();
+    l.cap = std::max(8192, 8 * l.n);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        off = (off + 255) & ~size_t(255);
+        const size_t o = off;
+        off += bytes;
+        return o;
+    };
+    const size_t n = l.n, J = l.J, L = l.L, N = l.N, cap = l.cap;
+    l.desc = take(sizeof(ChainDev));
+    l.stats = take(sizeof(ChainStats));
+    l.grid = take(sizeof(Grid));
+    l.theta = take(8 * J);
+    l.dtheta = take(8 * J);
+    l.tau = take(8 * J);
+    l.mask = take(J);
+    l.joint0 = take(64 * J);
+    l.jcur = take(64 * J);
+    l.xform = take(96 * L);
+    l.r0 = take(32 * n);
+    l.r = take(32 * n);
+    l.aparam = take(32 * n);
+    l.g0 = take(8 * n);
+    l.qfix = take(8 * n);
+    l.cell_key = take(4 * n);
+    l.cell_start = take(4 * (cap + 1));
+    l.cell_fill = take(4 * cap);
+    l.order = take(4 * n);
+    l.s_r = take(32 * n);
+    l.s_p = take(32 * n);
+    l.s_idx = take(4 * n);
+    l.s_cell = take(4 * n);
+    l.f_pair = take(32 * n);
+    l.f_cav = take(24 * n);
+    l.e_atom = take(32 * n);
+    l.q64 = take(32 * N);
+    l.q32 = take(16 * N);
+    l.total = (off + 255) & ~size_t(255);
+    return l;
+}
+
+kcm_status check_inputs(const kcm_chain_desc *d, const kcm_params *p)
+{
+    if (!d || !p) return fail(KCM_E_INVAL, "null desc or params");
+    if (d->n_res < 1 || d->n_res > (1 << 22)) return fail(KCM_E_INVAL, "n_res out of range");
+    if (!d->res_type || !d->types || d->n_types < 1) return fail(KCM_E_INVAL, "missing residue types");
+    for (int i = 0; i < d->n_res; ++i)
+        if (d->res_type[i] < 0 || d->res_type[i] >= d->n_types) return fail(KCM_E_INVAL, "res_type out of range");
+    if (!(p->cutoff > 0.0) || !(p->delta_r > 0.0) || !(p->r_probe >= 0.0) || !(p->kappa >= 0.0) || !(p->max_step > 0.0))
+        return fail(KCM_E_INVAL, "cutoff, delta_r, r_probe, kappa or max_step out of range");
+    if (p->n_orbits < 1 || p->n_orbits > 64) return fail(KCM_E_INVAL, "n_orbits must be in 1..64");
+    if ((int)sample_directions(p->n_orbits).size() > 65535) return fail(KCM_E_INVAL, "too many samples");
+    if (p->step_rule < 0 || p->step_rule > 2) return fail(KCM_E_INVAL, "bad step_rule");
+    if (p->precision != KCM_FP64 && p->precision != KCM_MIXED) return fail(KCM_E_INVAL, "bad precision");
+    if (p->terms < 0 || p->terms > KCM_TERM_ALL) return fail(KCM_E_INVAL, "bad terms");
+    if (!(p->diel_k > 0.0)) return fail(KCM_E_INVAL, "diel_k must be > 0");
+    if (!(p->cell_size >= 0.0)) return fail(KCM_E_INVAL, "cell_size must be >= 0");
+    return KCM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// batch tables: per (device, stream) a device array of chain descriptors and
+// the cumulative atom offsets the force kernel maps its workgroups with
+// ---------------------------------------------------------------------------
+struct Table {
+    int device = -1;
+    hipStream_t stream = nullptr;
+    std::vector<const kcm_chain *> chains;
+    void *dev = nullptr;
+    size_t cap = 0;
+    ChainDev **d_table = nullptr;
+    int32_t *d_off = nullptr;
+    int total_atoms = 0;
+};
+
+std::mutex g_mu;
+std::vector<Table> g_tables;
+
+struct TimedIter {
+    hipEvent_t it0, f0, f1, it1;
+};
+std::vector<TimedIter> g_timed;
+std::vector<hipEvent_t> g_event_pool;
+bool g_timing = false;
+double g_force_ms = 0.0, g_iter_ms = 0.0;
+int64_t g_force_n = 0, g_iter_n = 0;
+
+hipEvent_t pooled_event()
+{
+    if (!g_event_pool.empty()) {
+        hipEvent_t e = g_event_pool.back();
+        g_event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+}  // namespace
+
+struct kcm_chain {
+    ChainDev h;          // host copy of the device descriptor
+    ChainDev *d_desc;    // where it lives on the device
+    void *dev_mem;
+    size_t bytes;
+    int device;
+    int m, n, J, N;
+    std::vector<unsigned char> staging;  // host source of the build copies
+};
+
+namespace {
+
+kcm_status ensure_table(kcm_chain *const *chains, int n_chains, hipStream_t stream, Table **out)
+{
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    Table *t = nullptr;
+    for (auto &x : g_tables)
+        if (x.device == dev && x.stream == stream) t = &x;
+    if (!t) {
+        g_tables.emplace_back();
+        t = &g_tables.back();
+        t->device = dev;
+        t->stream = stream;
+    }
+    bool same = (int)t->chains.size() == n_chains;
+    for (int i = 0; same && i < n_chains; ++i) same = t->chains[i] == chains[i];
+    if (!same) {
+        const size_t need = sizeof(ChainDev *) * n_chains + 256 + sizeof(int32_t) * (n_chains + 1);
+        if (need > t->cap) {
+            if (t->dev) {
+                HIP_TRY(hipStreamSynchronize(stream));
+                HIP_TRY(hipFree(t->dev));
+                t->dev = nullptr;
+            }
+            const size_t cap = std::max(need * 2, size_t(4096));
+            HIP_TRY(hipMalloc(&t->dev, cap));
+            t->cap = cap;
+        }
+        std::vector<unsigned char> host(need);
+        ChainDev **tab = reinterpret_cast<ChainDev **>(host.data());
+        const size_t off_pos = (sizeof(ChainDev *) * n_chains + 255) & ~size_t(255);
+        int32_t *off = reinterpret_cast<int32_t *>(host.data() + off_pos);
+        long long total = 0;
+        for (int i = 0; i < n_chains; ++i) {
+            tab[i] = chains[i]->d_desc;
+            off[i] = (int32_t)total;
+            total += chains[i]->n;
+        }
+        if (total > std::numeric_limits<int32_t>::max()) return fail(KCM_E_INVAL, "too many atoms in one call");
+        off[n_chains] = (int32_t)total;
+        HIP_TRY(hipMemcpyAsync(t->dev, host.data(), off_pos + sizeof(int32_t) * (n_chains + 1), hipMemcpyHostToDevice, stream));
+        HIP_TRY(hipStreamSynchronize(stream));
+        t->d_table = reinterpret_cast<ChainDev **>(t->dev);
+        t->d_off = reinterpret_cast<int32_t *>(static_cast<unsigned char *>(t->dev) + off_pos);
+        t->chains.assign(chains, chains + n_chains);
+        t->total_atoms = (int)total;
+    }
+    *out = t;
+    return KCM_OK;
+}
+
+kcm_status read_stats(const kcm_chain *c, hipStream_t s, ChainStats *st)
+{
+    HIP_TRY(hipMemcpyAsync(st, c->h.stats, sizeof(ChainStats), hipMemcpyDeviceToHost, s));
+    return KCM_OK;
+}
+
+template <typename T>
+kcm_status write_field(T *dev_field, T value, hipStream_t s)
+{
+    HIP_TRY(hipMemcpyAsync(dev_field, &value, sizeof(T), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return KCM_OK;
+}
+
+kcm_status check_chains(kcm_chain *const *chains, int n_chains, int *precision)
+{
+    if (!chains || n_chains < 1) return fail(KCM_E_INVAL, "no chains");
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    for (int i = 0; i < n_chains; ++i) {
+        if (!chains[i]) return fail(KCM_E_INVAL, "null chain handle");
+        if (chains[i]->device != dev) return fail(KCM_E_INVAL, "chain lives on another device");
+        if (chains[i]->h.precision != chains[0]->h.precision) return fail(KCM_E_INVAL, "chains of one call must share precision");
+        for (int k = 0; k < i; ++k)
+            if (chains[k] == chains[i]) return fail(KCM_E_INVAL, "a chain appears twice in one call");
+    }
+    *precision = chains[0]->h.precision;
+    return KCM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void kcm_default_params(kcm_params *p)
+{
+    if (!p) return;
+    p->cutoff = 10.0;
+    p->kappa = 1e-3;
+    p->max_step = 1e-3;
+    p->step_rule = KCM_STEP_CAPPED;
+    p->precision = KCM_FP64;
+    p->terms = KCM_TERM_ALL;
+    p->n_orbits = 14;
+    p->diel_k = 4.0;
+    p->w13 = 0.0;
+    p->w14_elec = 1.0 / 1.2;
+    p->w14_vdw = 0.5;
+    p->delta_r = 0.05;
+    p->r_probe = 1.4;
+    p->g_hydro = 0.025;
+    p->cell_size = 0.0;
+}
+
+const char *kcm_last_error(void) { return g_err.c_str(); }
+
+kcm_status kcm_chain_bytes(const kcm_chain_desc *desc, const kcm_params *params, size_t *bytes)
+{
+    if (!bytes) return fail(KCM_E_INVAL, "null bytes");
+    kcm_status s = check_inputs(desc, params);
+    if (s != KCM_OK) return s;
+    *bytes = make_layout(desc->n_res, params->n_orbits).total;
+    return KCM_OK;
+}
+
+kcm_status kcm_build_chain(const kcm_chain_desc *desc, const kcm_params *params, void *dev_mem, size_t bytes,
+                           void *hip_stream, kcm_chain **out)
+{
+    if (!out) return fail(KCM_E_INVAL, "null out");
+    *out = nullptr;
+    kcm_status s = check_inputs(desc, params);
+    if (s != KCM_OK) return s;
+    if (!dev_mem || (reinterpret_cast<uintptr_t>(dev_mem) & 255)) return fail(KCM_E_INVAL, "dev_mem must be 256-byte aligned");
+    const int m = desc->n_res;
+    const Layout l = make_layout(m, params->n_orbits);
+    if (bytes < l.total) return fail(KCM_E_NOMEM, "device block smaller than kcm_chain_bytes");
+    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+
+    kcm_chain *c = new kcm_chain();
+    c->dev_mem = dev_mem;
+    c->bytes = bytes;
+    c->m = m;
+    c->n = l.n;
+    c->J = l.J;
+    c->N = l.N;
+    if (hipGetDevice(&c->device) != hipSuccess) c->device = 0;
+    unsigned char *base = static_cast<unsigned char *>(dev_mem);
+
+    ChainDev &h = c->h;
+    std::memset(&h, 0, sizeof h);
+    h.n_atoms = l.n;
+    h.n_joints = l.J;
+    h.n_links = l.L;
+    h.n_samples = l.N;
+    h.cap_cells = l.cap;
+    h.precision = params->precision;
+    h.terms = params->terms;
+    h.step_rule = params->step_rule;
+    h.cutoff = params->cutoff;
+    h.kappa = params->kappa;
+    h.max_step = params->max_step;
+    h.diel_k = params->diel_k;
+    h.coulomb = kCoulomb / params->diel_k;
+    h.w13 = params->w13;
+    h.w14e = params->w14_elec;
+    h.w14v = params->w14_vdw;
+    h.delta_r = params->delta_r;
+    h.r_probe = params->r_probe;
+    bond_class_masks(h.m12, h.m13, h.m14);
+
+    // per-atom inputs
+    const double k6 = std::pow(2.0, 1.0 / 6.0);
+    std::vector<double4> r0(l.n), apar(l.n);
+    std::vector<double> g0(l.n);
+    std::vector<long long> qfix(l.n);
+    const std::vector<V3> zp = zero_position(m);
+    double roff_max = 0.0;
+    for (int a = 0; a < l.n; ++a) {
+        const int i = a / APR, sl = a % APR;
+        const kcm_residue_type &t = desc->types[desc->res_type[i]];
+        const double R = 0.5 * k6 * t.sigma[sl];
+        const double roff = R + params->r_probe;
+        r0[a] = make_double4(zp[a].x, zp[a].y, zp[a].z, 0.0);
+        apar[a] = make_double4(t.q[sl], R, std::sqrt(t.eps[sl]), roff);
+        const double gamma = params->g_hydro * t.hydrophobicity;
+        g0[a] = 4.0 * kPi * gamma * roff * roff;
+        qfix[a] = std::llrint(g0[a] / (l.N * params->delta_r) * FIX_SCALE);
+        roff_max = std::max(roff_max, roff);
+        if (!(t.sigma[sl] > 0.0) || !(t.eps[sl] >= 0.0) || !std::isfinite(t.q[sl]) || !std::isfinite(t.hydrophobicity)) {
+            delete c;
+            return fail(KCM_E_INVAL, "residue-type parameters out of range");
+        }
+    }
+    h.roff_max = roff_max;
+    const double reach_len = std::max(params->cutoff, 2.0 * roff_max + params->delta_r) + 1e-7;
+    h.cell_min = params->cell_size > 0.0 ? params->cell_size : 0.5 * reach_len;
+
+    // joints: zero-position axis u0 and point p0 (phi_i: N_i -> CA_i; psi_i: CA_i -> C_i)
+    std::vector<double4> joint0(2 * l.J);
+    for (int j = 0; j < l.J; ++j) {
+        const int i = j / 2;
+        const V3 a = zp[APR * i + (j % 2 ? CA_ : N_)], b = zp[APR * i + (j % 2 ? C_ : CA_)];
+        const V3 u = unit(b - a);
+        joint0[2 * j] = make_double4(u.x, u.y, u.z, 0.0);
+        joint0[2 * j + 1] = make_double4(a.x, a.y, a.z, 0.0);
+    }
+    std::vector<double> theta(l.J);
+    std::vector<uint8_t> mask(l.J);
+    for (int j = 0; j < l.J; ++j) {
+        double t = desc->theta0 ? desc->theta0[j] : kPi;
+        if (!std::isfinite(t)) {
+            delete c;
+            return fail(KCM_E_INVAL, "theta0 not finite");
+        }
+        t = std::remainder(t, 2.0 * kPi);
+        if (t <= -kPi) t += 2.0 * kPi;
+        theta[j] = t;
+        mask[j] = desc->joint_mask ? (desc->joint_mask[j] ? 1 : 0) : 1;
+    }
+    const std::vector<V3> qd = sample_directions(params->n_orbits);
+    std::vector<double4> q64(l.N);
+    std::vector<float4> q32(l.N);
+    for (int k = 0; k < l.N; ++k) {
+        q64[k] = make_double4(qd[k].x, qd[k].y, qd[k].z, 0.0);
+        q32[k] = make_float4((float)qd[k].x, (float)qd[k].y, (float)qd[k].z, 0.0f);
+    }
+    ChainStats st{};
+    st.tol = 0.0;
+    st.iter_limit = std::numeric_limits<int64_t>::max();
+    st.active = 1;
+
+#define PTR(field, type) h.field = reinterpret_cast<type>(base + l.field)
+    PTR(theta, double *);
+    PTR(dtheta, double *);
+    PTR(tau, double *);
+    PTR(mask, uint8_t *);
+    PTR(joint0, double4 *);
+    PTR(jcur, double4 *);
+    PTR(xform, double *);
+    PTR(r0, double4 *);
+    PTR(r, double4 *);
+    PTR(aparam, double4 *);
+    PTR(g0, double *);
+    PTR(qfix, long long *);
+    PTR(cell_key, int32_t *);
+    PTR(cell_start, int32_t *);
+    PTR(cell_fill, int32_t *);
+    PTR(order, int32_t *);
+    PTR(s_r, double4 *);
+    PTR(s_p, double4 *);
+    PTR(s_idx, int32_t *);
+    PTR(s_cell, int32_t *);
+    PTR(f_pair, double4 *);
+    PTR(f_cav, long long *);
+    PTR(e_atom, double4 *);
+    PTR(q64, double4 *);
+    PTR(q32, float4 *);
+    PTR(grid, Grid *);
+    PTR(stats, ChainStats *);
+#undef PTR
+    c->d_desc = reinterpret_cast<ChainDev *>(base + l.desc);
+
+    // one host staging image of every initialised region, copied in one go
+    const size_t img = l.q32 + 16 * (size_t)l.N;
+    c->staging.assign(img, 0);
+    auto put = [&](size_t off, const void *src, size_t nbytes) { std::memcpy(c->staging.data() + off, src, nbytes); };
+    put(l.desc, &h, sizeof h);
+    put(l.stats, &st, sizeof st);
+    put(l.theta, theta.data(), 8 * l.J);
+    put(l.mask, mask.data(), l.J);
+    put(l.joint0, joint0.data(), 32 * joint0.size());
+    put(l.r0, r0.data(), 32 * (size_t)l.n);
+    put(l.aparam, apar.data(), 32 * (size_t)l.n);
+    put(l.g0, g0.data(), 8 * (size_t)l.n);
+    put(l.qfix, qfix.data(), 8 * (size_t)l.n);
+    put(l.q64, q64.data(), 32 * (size_t)l.N);
+    put(l.q32, q32.data(), 16 * (size_t)l.N);
+    hipError_t e = hipMemsetAsync(dev_mem, 0, l.total, stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(dev_mem, c->staging.data(), img, hipMemcpyHostToDevice, stream);
+    if (e != hipSuccess) {
+        delete c;
+        return fail(KCM_E_DEVICE, std::string("build copy: ") + hipGetErrorString(e));
+    }
+    *out = c;
+    return KCM_OK;
+}
+
+kcm_status kcm_chain_info(const kcm_chain *c, int32_t *n_atoms, int32_t *n_joints, int32_t *n_samples, int32_t *precision)
+{
+    if (!c) return fail(KCM_E_INVAL, "null chain");
+    if (n_atoms) *n_atoms = c->n;
+    if (n_joints) *n_joints = c->J;
+    if (n_samples) *n_samples = c->N;
+    if (precision) *precision = c->h.precision;
+    return KCM_OK;
+}
+
+kcm_status kcm_step(kcm_chain *const *chains, int n_chains, int n_iter, void *hip_stream, kcm_step_report *reports)
+{
+    if (n_iter < 0) return fail(KCM_E_INVAL, "n_iter < 0");
+    int prec = 0;
+    kcm_status s = check_chains(chains, n_chains, &prec);
+    if (s != KCM_OK) return s;
+    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    std::lock_guard<std::mutex> lock(g_mu);
+    Table *t = nullptr;
+    s = ensure_table(chains, n_chains, stream, &t);
+    if (s != KCM_OK) return s;
+    for (int it = 0; it < n_iter; ++it) {
+        TimedIter ti{};
+        if (g_timing) {
+            ti = {pooled_event(), pooled_event(), pooled_event(), pooled_event()};
+            HIP_TRY(hipEventRecord(ti.it0, stream));
+        }
+        HIP_TRY(launch_chain_pre(t->d_table, n_chains, stream));
+        if (g_timing) HIP_TRY(hipEventRecord(ti.f0, stream));
+        HIP_TRY(launch_force(t->d_table, t->d_off, n_chains, t->total_atoms, prec, stream));
+        if (g_timing) HIP_TRY(hipEventRecord(ti.f1, stream));
+        HIP_TRY(launch_chain_post(t->d_table, n_chains, stream));
+        if (g_timing) {
+            HIP_TRY(hipEventRecord(ti.it1, stream));
+            g_timed.push_back(ti);
+        }
+    }
+    if (!reports) return KCM_OK;
+    std::vector<ChainStats> st(n_chains);
+    for (int i = 0; i < n_chains; ++i) {
+        s = read_stats(chains[i], stream, &st[i]);
+        if (s != KCM_OK) return s;
+    }
+    HIP_TRY(hipStreamSynchronize(stream));
+    kcm_status worst = KCM_OK;
+    for (int i = 0; i < n_chains; ++i) {
+        kcm_step_report &r = reports[i];
+        r.e_elec = st[i].e_elec;
+        r.e_vdw = st[i].e_vdw;
+        r.e_cav = st[i].e_cav;
+        r.max_tau = st[i].max_tau;
+        r.max_dtheta = st[i].max_dtheta;
+        r.iterations = st[i].iterations;
+        r.status = st[i].status;
+        r.converged = st[i].converged;
+        if (st[i].status != 0 && worst == KCM_OK) worst = (kcm_status)st[i].status;
+    }
+    if (worst != KCM_OK) g_err = "a chain reported a failure status";
+    return worst;
+}
+
+kcm_status kcm_fold(kcm_chain *const *chains, int n_chains, double tol_dtheta, int max_iter, int check_every,
+                    void *hip_stream, kcm_fold_result *results)
+{
+    int prec = 0;
+    kcm_status s = check_chains(chains, n_chains, &prec);
+    if (s != KCM_OK) return s;
+    if (max_iter < 0 || check_every < 1) return fail(KCM_E_INVAL, "max_iter < 0 or check_every < 1");
+    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    const auto t0 = std::chrono::steady_clock::now();
+    std::vector<ChainStats> st(n_chains);
+    std::vector<int64_t> start(n_chains);
+    for (int i = 0; i < n_chains; ++i) {
+        s = read_stats(chains[i], stream, &st[i]);
+        if (s != KCM_OK) return s;
+    }
+    HIP_TRY(hipStreamSynchronize(stream));
+    for (int i = 0; i < n_chains; ++i) {
+        ChainStats *d = chains[i]->h.stats;
+        start[i] = st[i].iterations;
+        const int act = st[i].status == 0 ? 1 : 0;
+        if ((s = write_field(&d->tol, tol_dtheta, stream)) != KCM_OK) return s;
+        if ((s = write_field(&d->iter_limit, st[i].iterations + (int64_t)max_iter, stream)) != KCM_OK) return s;
+        if ((s = write_field(&d->converged, 0, stream)) != KCM_OK) return s;
+        if ((s = write_field(&d->active, max_iter > 0 ? act : 0, stream)) != KCM_OK) return s;
+    }
+    int done = 0;
+    while (done < max_iter) {
+        const int k = std::min(check_every, max_iter - done);
+        s = kcm_step(chains, n_chains, k, hip_stream, nullptr);
+        if (s != KCM_OK) return s;
+        done += k;
+        bool any = false;
+        for (int i = 0; i < n_chains; ++i)
+            if ((s = read_stats(chains[i], stream, &st[i])) != KCM_OK) return s;
+        HIP_TRY(hipStreamSynchronize(stream));
+        for (int i = 0; i < n_chains; ++i) any = any || st[i].active;
+        if (!any) break;
+    }
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    kcm_status worst = KCM_OK;
+    for (int i = 0; i < n_chains; ++i) {
+        // leave the chain steppable again by kcm_step
+        ChainStats *d = chains[i]->h.stats;
+        if ((s = write_field(&d->tol, 0.0, stream)) != KCM_OK) return s;
+        if ((s = write_field(&d->iter_limit, std::numeric_limits<int64_t>::max(), stream)) != KCM_OK) return s;
+        if ((s = write_field(&d->active, st[i].status == 0 && !st[i].converged ? 1 : 0, stream)) != KCM_OK) return s;
+        if (results) {
+            results[i].iterations = st[i].iterations - start[i];
+            results[i].converged = st[i].converged;
+            results[i].status = st[i].status;
+            results[i].seconds = secs;
+        }
+        if (st[i].status != 0 && worst == KCM_OK) worst = (kcm_status)st[i].status;
+    }
+    return worst;
+}
+
+kcm_status kcm_get_state(const kcm_chain *c, void *hip_stream, double *theta, double *xyz, double *force, double *tau,
+                         double *dtheta)
+{
+    if (!c) return fail(KCM_E_INVAL, "null chain");
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    HIP_TRY(hipStreamSynchronize(s));
+    if (theta) HIP_TRY(hipMemcpy(theta, c->h.theta, 8 * c->J, hipMemcpyDeviceToHost));
+    if (tau) HIP_TRY(hipMemcpy(tau, c->h.tau, 8 * c->J, hipMemcpyDeviceToHost));
+    if (dtheta) HIP_TRY(hipMemcpy(dtheta, c->h.dtheta, 8 * c->J, hipMemcpyDeviceToHost));
+    if (xyz) {
+        std::vector<double4> r(c->n);
+        HIP_TRY(hipMemcpy(r.data(), c->h.r, 32 * (size_t)c->n, hipMemcpyDeviceToHost));
+        for (int a = 0; a < c->n; ++a) {
+            xyz[3 * a] = r[a].x;
+            xyz[3 * a + 1] = r[a].y;
+            xyz[3 * a + 2] = r[a].z;
+        }
+    }
+    if (force) {
+        std::vector<double4> fp(c->n);
+        std::vector<long long> fc(3 * (size_t)c->n);
+        HIP_TRY(hipMemcpy(fp.data(), c->h.f_pair, 32 * (size_t)c->n, hipMemcpyDeviceToHost));
+        HIP_TRY(hipMemcpy(fc.data(), c->h.f_cav, 24 * (size_t)c->n, hipMemcpyDeviceToHost));
+        for (int a = 0; a < c->n; ++a) {
+            force[3 * a] = fp[a].x + (double)fc[3 * a] / FIX_SCALE;
+            force[3 * a + 1] = fp[a].y + (double)fc[3 * a + 1] / FIX_SCALE;
+            force[3 * a + 2] = fp[a].z + (double)fc[3 * a + 2] / FIX_SCALE;
+        }
+    }
+    return KCM_OK;
+}
+
+kcm_status kcm_get_forces(const kcm_chain *c, void *hip_stream, double *f_pair, double *f_cav)
+{
+    if (!c) return fail(KCM_E_INVAL, "null chain");
+    HIP_TRY(hipStreamSynchronize(static_cast<hipStream_t>(hip_stream)));
+    if (f_pair) {
+        std::vector<double4> fp(c->n);
+        HIP_TRY(hipMemcpy(fp.data(), c->h.f_pair, 32 * (size_t)c->n, hipMemcpyDeviceToHost));
+        for (int a = 0; a < c->n; ++a) {
+            f_pair[3 * a] = fp[a].x;
+            f_pair[3 * a + 1] = fp[a].y;
+            f_pair[3 * a + 2] = fp[a].z;
+        }
+    }
+    if (f_cav) {
+        std::vector<long long> fc(3 * (size_t)c->n);
+        HIP_TRY(hipMemcpy(fc.data(), c->h.f_cav, 24 * (size_t)c->n, hipMemcpyDeviceToHost));
+        for (size_t k = 0; k < fc.size(); ++k) f_cav[k] = (double)fc[k] / FIX_SCALE;
+    }
+    return KCM_OK;
+}
+
+kcm_status kcm_set_theta(kcm_chain *c, const double *theta, void *hip_stream)
+{
+    if (!c || !theta) return fail(KCM_E_INVAL, "null chain or theta");
+    std::vector<double> t(c->J);
+    for (int j = 0; j < c->J; ++j) {
+        if (!std::isfinite(theta[j])) return fail(KCM_E_INVAL, "theta not finite");
+        double v = std::remainder(theta[j], 2.0 * kPi);
+        if (v <= -kPi) v += 2.0 * kPi;
+        t[j] = v;
+    }
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    HIP_TRY(hipMemcpyAsync(c->h.theta, t.data(), 8 * c->J, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    kcm_status st;
+    if ((st = write_field(&c->h.stats->converged, 0, s)) != KCM_OK) return st;
+    if ((st = write_field(&c->h.stats->status, 0, s)) != KCM_OK) return st;
+    if ((st = write_field(&c->h.stats->nbr_overflow, 0, s)) != KCM_OK) return st;
+    return write_field(&c->h.stats->active, 1, s);
+}
+
+kcm_status kcm_get_cells(const kcm_chain *c, void *hip_stream, int32_t *dims, double *cell_size, double *origin,
+                         int32_t *n_cells, int32_t *order, int32_t *cell_start, int32_t cell_start_capacity)
+{
+    if (!c) return fail(KCM_E_INVAL, "null chain");
+    HIP_TRY(hipStreamSynchronize(static_cast<hipStream_t>(hip_stream)));
+    Grid g;
+    HIP_TRY(hipMemcpy(&g, c->h.grid, sizeof g, hipMemcpyDeviceToHost));
+    if (dims) for (int k = 0; k < 3; ++k) dims[k] = g.dims[k];
+    if (cell_size) *cell_size = g.cell;
+    if (origin) for (int k = 0; k < 3; ++k) origin[k] = g.origin[k];
+    if (n_cells) *n_cells = g.n_cells;
+    if (order) HIP_TRY(hipMemcpy(order, c->h.order, 4 * (size_t)c->n, hipMemcpyDeviceToHost));
+    if (cell_start) {
+        if (cell_start_capacity < g.n_cells + 1) return fail(KCM_E_INVAL, "cell_start_capacity too small");
+        HIP_TRY(hipMemcpy(cell_start, c->h.cell_start, 4 * ((size_t)g.n_cells + 1), hipMemcpyDeviceToHost));
+    }
+    return KCM_OK;
+}
+
+kcm_status kcm_set_timing(int enable)
+{
+    std::lock_guard<std::mutex> lock(g_mu);
+    g_timing = enable != 0;
+    return KCM_OK;
+}
+
+kcm_status kcm_get_timing(double *force_ms, int64_t *force_launches, double *iter_ms, int64_t *iterations, int reset)
+{
+    std::lock_guard<std::mutex> lock(g_mu);
+    for (auto &t : g_timed) {
+        HIP_TRY(hipEventSynchronize(t.it1));
+        float a = 0.f, b = 0.f;
+        HIP_TRY(hipEventElapsedTime(&a, t.f0, t.f1));
+        HIP_TRY(hipEventElapsedTime(&b, t.it0, t.it1));
+        g_force_ms += a;
+        g_iter_ms += b;
+        g_force_n += 1;
+        g_iter_n += 1;
+        g_event_pool.push_back(t.it0);
+        g_event_pool.push_back(t.f0);
+        g_event_pool.push_back(t.f1);
+        g_event_pool.push_back(t.it1);
+    }
+    g_timed.clear();
+    if (force_ms) *force_ms = g_force_ms;
+    if (force_launches) *force_launches = g_force_n;
+    if (iter_ms) *iter_ms = g_iter_ms;
+    if (iterations) *iterations = g_iter_n;
+    if (reset) {
+        g_force_ms = g_iter_ms = 0.0;
+        g_force_n = g_iter_n = 0;
+    }
+    return KCM_OK;
+}
+
+kcm_status kcm_chain_free(kcm_chain *c)
+{
+    if (!c) return fail(KCM_E_INVAL, "null chain");
+    std::lock_guard<std::mutex> lock(g_mu);
+    for (auto &t : g_tables) {
+        for (auto *x : t.chains)
+            if (x == c) {
+                t.chains.clear();  // forces a rebuild of this table on next use
+                break;
+            }
+    }
+    delete c;
+    return KCM_OK;
+}
+
+}  // extern "C"

