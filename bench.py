@@ -1,0 +1,228 @@
+#!/usr/bin/env python3
+"""Throughput of KCM iterations (atom-steps/s) on one MI355X.
+
+One step is one full KCM iteration of the chain (forward kinematics, cell
+list, Coulomb + LJ + SASA solvation forces, torques, compliance step) on the
+single 1000-residue chain (10,000 atoms) in a compact-globule start, 10 A
+cutoff, 250 samples per offset sphere.  Inputs are built once and stay in
+HBM; the timed region covers exactly --steps iterations between two device
+synchronisations.  Prints one JSON line.
+
+Roofline of the dominant kernel (the force kernel): algorithmic FP work per
+launch = 40 flops per unordered pair within the cutoff + 9 flops per
+(sample, solvation neighbour) coverage test + 9 flops per (exposed sample,
+neighbour) pair for the three displaced tests, divided by the kernel's mean
+launch time from HIP events recorded on its launch stream.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_TFLOPS = {"mixed": 157.3, "fp64": 78.6}  # MI355X vector FP32 / FP64
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "force_kernel_traffic.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_1712_05012_amd", "csrc", "kcm_kernels.hip")
+
+
+def workload(m: int = 1000):
+    import synth
+
+    T = synth.residue_types()
+    seq = synth.sequence(m, synth.config_seed(2))
+    th = synth.load_globule(m)
+    return T, seq, th
+
+
+def algorithmic_units(xyz, T, seq, p, n_exposed, n_samples):
+    """Unit counts of one force evaluation at positions xyz."""
+    import numpy as np
+    from scipy.spatial import cKDTree
+
+    tree = cKDTree(xyz)
+    n_pairs = len(tree.query_pairs(p.cutoff, output_type="ndarray"))
+    sig = np.asarray(T.sigma)[seq].reshape(-1)
+    roff = 0.5 * 2.0 ** (1.0 / 6.0) * sig + p.r_probe
+    cand = tree.query_pairs(2 * roff.max() + p.delta_r, output_type="ndarray")
+    d = np.linalg.norm(xyz[cand[:, 0]] - xyz[cand[:, 1]], axis=1)
+    keep = cand[d <= roff[cand[:, 0]] + roff[cand[:, 1]] + p.delta_r]
+    nbr = np.bincount(keep.reshape(-1), minlength=xyz.shape[0])
+    tests1 = int(n_samples) * int(nbr.sum())
+    tests2 = int((np.asarray(n_exposed, dtype=np.int64) * nbr).sum())
+    flops = 40.0 * n_pairs + 9.0 * tests1 + 9.0 * tests2
+    return {"pairs_within_cutoff": int(n_pairs), "sasa_neighbours_mean": float(nbr.mean()),
+            "coverage_tests": tests1, "exposed_sample_neighbour_pairs": tests2,
+            "exposed_fraction": float(np.mean(n_exposed) / n_samples), "flops": flops}
+
+
+def run_gpu(precision: str, steps: int, warmup: int, m: int):
+    import torch
+
+    from paper_1712_05012_amd import kcm
+
+    T, seq, th = workload(m)
+    prec = kcm.KCM_MIXED if precision == "mixed" else kcm.KCM_FP64
+    p = kcm.kcm_default_params(precision=prec)
+    chain = kcm.Chain(seq, T, p, theta0=th)
+    stream = torch.cuda.current_stream()
+    kcm.kcm_step([chain], warmup, stream, report=False)
+    torch.cuda.synchronize()
+    kcm.kcm_get_timing(reset=True)
+    kcm.kcm_set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    kcm.kcm_step([chain], steps, stream, report=False)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kcm.kcm_set_timing(False)
+    tm = kcm.kcm_get_timing(reset=True)
+    _, reps = kcm.kcm_step([chain], 0, stream, report=True, check=False)
+    st = chain.state()
+    terms = chain.atom_terms()
+    units = algorithmic_units(st["xyz"], T, seq, p, terms["n_exposed"], chain.n_samples)
+    secs = t1 - t0
+    out = {
+        "n_atoms": chain.n_atoms,
+        "seconds": secs,
+        "ms_per_step": 1e3 * secs / steps,
+        "value": chain.n_atoms * steps / secs,
+        "force_ms_mean": tm["force_ms"] / max(tm["force_launches"], 1),
+        "iter_ms_mean": tm["iter_ms"] / max(tm["iterations"], 1),
+        "units": units,
+        "status": reps[0].status,
+        "energies": [reps[0].e_elec, reps[0].e_vdw, reps[0].e_cav],
+        "n_samples": chain.n_samples,
+    }
+    chain.free()
+    return out
+
+
+def traffic_for(precision: str):
+    """HBM bytes per force launch from committed rocprofv3 counters, if still current."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    try:
+        rec = json.load(open(TRAFFIC_FILE))
+        sha = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+        entry = rec.get(precision)
+        if not entry or rec.get("kernel_sha256") != sha:
+            return None
+        return float(entry["bytes_per_launch"])
+    except Exception:
+        return None
+
+
+def cpu_baseline(seconds: float, m: int):
+    """The FP64 oracle as it stands, on the host cores, over a bounded sample."""
+    import oracle
+
+    T, seq, th = workload(m)
+    ch = oracle.OracleChain(seq, T)
+    iters = 0
+    t0 = time.perf_counter()
+    while True:
+        o = oracle.iterate(ch, th)
+        th = o["theta"]
+        iters += 1
+        if time.perf_counter() - t0 >= seconds:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": ch.n * iters / dt, "unit": "atom-steps/s", "cores": oracle.threads(), "kind": "oracle",
+            "sample": f"{iters} FP64 KCM iterations of the 1000-residue globule ({ch.n} atoms), {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed")
+    ap.add_argument("--residues", type=int, default=1000)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-companion", action="store_true", help="skip the other precision's measurement")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="first run a plain device copy of MIB MiB (calibrates HBM byte counters)")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build runs a chain on a single MI355X "
+              "(how chains would shard over several GPUs is described in the design notes); "
+              "run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+    if args.residues != 1000:
+        print("note: non-default --residues needs a stored globule for that length", file=sys.stderr)
+
+    import torch
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    if args.copy_probe > 0:
+        src = torch.empty(args.copy_probe << 18, dtype=torch.float32, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
+    main_run = run_gpu(args.precision, args.steps, args.warmup, args.residues)
+    other = "fp64" if args.precision == "mixed" else "mixed"
+    companion = None if args.no_companion else run_gpu(other, args.steps, args.warmup, args.residues)
+
+    u = main_run["units"]
+    achieved = u["flops"] / (main_run["force_ms_mean"] * 1e-3) / 1e12
+    peak = PEAK_TFLOPS[args.precision]
+    line = {
+        "metric": "atom-steps/s per KCM iteration",
+        "value": main_run["value"],
+        "unit": "atom-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": main_run["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64" if args.precision == "mixed" else "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "single chain, 1000 residues (10,000 atoms), compact random globule, "
+                        "10 A cutoff, 250 samples per offset sphere, 1 KCM iteration per step",
+            "precision": args.precision,
+            "n_atoms": main_run["n_atoms"],
+            "n_samples": main_run["n_samples"],
+        },
+        "roofline": {
+            "bound": "alu",
+            "achieved": achieved,
+            "peak": peak,
+            "unit": "TFLOP/s",
+            "frac": achieved / peak,
+            "traffic": traffic_for(args.precision),
+        },
+        "kernel_ms": {"force": main_run["force_ms_mean"],
+                      "iteration": main_run["iter_ms_mean"],
+                      "chain_kernels": main_run["iter_ms_mean"] - main_run["force_ms_mean"]},
+        "units_per_step": u,
+        "status": main_run["status"],
+    }
+    if companion is not None:
+        line[other] = {"value": companion["value"], "ms_per_step": companion["ms_per_step"],
+                       "force_ms": companion["force_ms_mean"],
+                       "frac": companion["units"]["flops"] / (companion["force_ms_mean"] * 1e-3) / 1e12
+                       / PEAK_TFLOPS[other]}
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(args.cpu_seconds, args.residues)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -157,6 +157,13 @@ kcm_status kcm_get_state(const kcm_chain *chain, void *hip_stream, double *theta
  * host arrays [n][3]; synchronises hip_stream. */
 kcm_status kcm_get_forces(const kcm_chain *chain, void *hip_stream, double *f_pair, double *f_cav);
 
+/* Per-atom terms of the last evaluation, host arrays [n] (any may be NULL):
+ * Coulomb and LJ energy (half of every pair the atom is in), solvation energy
+ * G0_i f_i (eq G_cav_patch) and the number of exposed samples N f_i (-1 when
+ * the solvation term is off).  Synchronises hip_stream. */
+kcm_status kcm_get_atom_terms(const kcm_chain *chain, void *hip_stream, double *e_elec, double *e_vdw,
+                              double *e_cav, int32_t *n_exposed);
+
 /* Replace a chain's theta (host array [J]), e.g. to resume from a checkpoint
  * or to re-synchronise with a reference; clears its converged flag. */
 kcm_status kcm_set_theta(kcm_chain *chain, const double *theta, void *hip_stream);

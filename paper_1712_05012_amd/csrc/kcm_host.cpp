@@ -152,7 +152,8 @@ std::vector<V3> sample_directions(int n_orb)
 // ---------------------------------------------------------------------------
 struct Layout {
     size_t desc, stats, grid, theta, dtheta, tau, mask, joint0, jcur, xform, r0, r, aparam, g0, qfix;
-    size_t cell_key, cell_start, cell_fill, order, s_r, s_p, s_idx, s_cell, f_pair, f_cav, e_atom, q64, q32;
+    size_t cell_key, cell_count, cell_start, cell_cursor, bbox_acc, s_r, s_p, s_idx, s_cell, f_pair, f_cav, e_atom;
+    size_t q64, q32;
     size_t total;
     int n, J, L, N, cap;
 };
@@ -189,9 +190,10 @@ Layout make_layout(int m, int n_orb)
     l.g0 = take(8 * n);
     l.qfix = take(8 * n);
     l.cell_key = take(4 * n);
+    l.cell_count = take(4 * cap);
     l.cell_start = take(4 * (cap + 1));
-    l.cell_fill = take(4 * cap);
-    l.order = take(4 * n);
+    l.cell_cursor = take(4 * cap);
+    l.bbox_acc = take(8 * 6);
     l.s_r = take(32 * n);
     l.s_p = take(32 * n);
     l.s_idx = take(4 * n);
@@ -234,9 +236,7 @@ struct Table {
     std::vector<const kcm_chain *> chains;
     void *dev = nullptr;
     size_t cap = 0;
-    ChainDev **d_table = nullptr;
-    int32_t *d_off = nullptr;
-    int total_atoms = 0;
+    Batch batch{};
 };
 
 std::mutex g_mu;
@@ -293,7 +293,9 @@ kcm_status ensure_table(kcm_chain *const *chains, int n_chains, hipStream_t stre
     bool same = (int)t->chains.size() == n_chains;
     for (int i = 0; same && i < n_chains; ++i) same = t->chains[i] == chains[i];
     if (!same) {
-        const size_t need = sizeof(ChainDev *) * n_chains + 256 + sizeof(int32_t) * (n_chains + 1);
+        const size_t off_pos = (sizeof(ChainDev *) * n_chains + 255) & ~size_t(255);
+        const size_t blk_pos = off_pos + ((sizeof(int32_t) * (n_chains + 1) + 255) & ~size_t(255));
+        const size_t need = blk_pos + sizeof(int32_t) * (n_chains + 1);
         if (need > t->cap) {
             if (t->dev) {
                 HIP_TRY(hipStreamSynchronize(stream));
@@ -306,22 +308,29 @@ kcm_status ensure_table(kcm_chain *const *chains, int n_chains, hipStream_t stre
         }
         std::vector<unsigned char> host(need);
         ChainDev **tab = reinterpret_cast<ChainDev **>(host.data());
-        const size_t off_pos = (sizeof(ChainDev *) * n_chains + 255) & ~size_t(255);
         int32_t *off = reinterpret_cast<int32_t *>(host.data() + off_pos);
-        long long total = 0;
+        int32_t *blk = reinterpret_cast<int32_t *>(host.data() + blk_pos);
+        long long total = 0, blocks = 0;
         for (int i = 0; i < n_chains; ++i) {
             tab[i] = chains[i]->d_desc;
             off[i] = (int32_t)total;
+            blk[i] = (int32_t)blocks;
             total += chains[i]->n;
+            blocks += (chains[i]->n + ATOM_BLOCK - 1) / ATOM_BLOCK;
         }
         if (total > std::numeric_limits<int32_t>::max()) return fail(KCM_E_INVAL, "too many atoms in one call");
         off[n_chains] = (int32_t)total;
-        HIP_TRY(hipMemcpyAsync(t->dev, host.data(), off_pos + sizeof(int32_t) * (n_chains + 1), hipMemcpyHostToDevice, stream));
+        blk[n_chains] = (int32_t)blocks;
+        HIP_TRY(hipMemcpyAsync(t->dev, host.data(), need, hipMemcpyHostToDevice, stream));
         HIP_TRY(hipStreamSynchronize(stream));
-        t->d_table = reinterpret_cast<ChainDev **>(t->dev);
-        t->d_off = reinterpret_cast<int32_t *>(static_cast<unsigned char *>(t->dev) + off_pos);
+        unsigned char *d = static_cast<unsigned char *>(t->dev);
+        t->batch.table = reinterpret_cast<ChainDev *const *>(d);
+        t->batch.atom_off = reinterpret_cast<const int32_t *>(d + off_pos);
+        t->batch.blk_off = reinterpret_cast<const int32_t *>(d + blk_pos);
+        t->batch.n_chains = n_chains;
+        t->batch.total_atoms = (int)total;
+        t->batch.total_blocks = (int)blocks;
         t->chains.assign(chains, chains + n_chains);
-        t->total_atoms = (int)total;
     }
     *out = t;
     return KCM_OK;
@@ -497,6 +506,7 @@ kcm_status kcm_build_chain(const kcm_chain_desc *desc, const kcm_params *params,
     st.tol = 0.0;
     st.iter_limit = std::numeric_limits<int64_t>::max();
     st.active = 1;
+    st.need_grid = 1;
 
 #define PTR(field, type) h.field = reinterpret_cast<type>(base + l.field)
     PTR(theta, double *);
@@ -512,9 +522,10 @@ kcm_status kcm_build_chain(const kcm_chain_desc *desc, const kcm_params *params,
     PTR(g0, double *);
     PTR(qfix, long long *);
     PTR(cell_key, int32_t *);
+    PTR(cell_count, int32_t *);
     PTR(cell_start, int32_t *);
-    PTR(cell_fill, int32_t *);
-    PTR(order, int32_t *);
+    PTR(cell_cursor, int32_t *);
+    PTR(bbox_acc, unsigned long long *);
     PTR(s_r, double4 *);
     PTR(s_p, double4 *);
     PTR(s_idx, int32_t *);
@@ -575,22 +586,28 @@ kcm_status kcm_step(kcm_chain *const *chains, int n_chains, int n_iter, void *hi
     Table *t = nullptr;
     s = ensure_table(chains, n_chains, stream, &t);
     if (s != KCM_OK) return s;
+    const Batch &bt = t->batch;
     for (int it = 0; it < n_iter; ++it) {
         TimedIter ti{};
         if (g_timing) {
             ti = {pooled_event(), pooled_event(), pooled_event(), pooled_event()};
             HIP_TRY(hipEventRecord(ti.it0, stream));
         }
-        HIP_TRY(launch_chain_pre(t->d_table, n_chains, stream));
+        // post phase of the previous iteration (if any) + kinematics and grid of this one
+        HIP_TRY(launch_chain(bt, it > 0 ? 1 : 0, 1, stream));
+        HIP_TRY(launch_place(bt, stream));
+        HIP_TRY(launch_cellscan(bt, stream));
+        HIP_TRY(launch_scatter(bt, stream));
+        HIP_TRY(launch_cellsort(bt, stream));
         if (g_timing) HIP_TRY(hipEventRecord(ti.f0, stream));
-        HIP_TRY(launch_force(t->d_table, t->d_off, n_chains, t->total_atoms, prec, stream));
-        if (g_timing) HIP_TRY(hipEventRecord(ti.f1, stream));
-        HIP_TRY(launch_chain_post(t->d_table, n_chains, stream));
+        HIP_TRY(launch_force(bt, prec, stream));
         if (g_timing) {
+            HIP_TRY(hipEventRecord(ti.f1, stream));
             HIP_TRY(hipEventRecord(ti.it1, stream));
             g_timed.push_back(ti);
         }
     }
+    if (n_iter > 0) HIP_TRY(launch_chain(bt, 1, 0, stream));  // post phase of the last iteration
     if (!reports) return KCM_OK;
     std::vector<ChainStats> st(n_chains);
     for (int i = 0; i < n_chains; ++i) {
@@ -725,6 +742,22 @@ kcm_status kcm_get_forces(const kcm_chain *c, void *hip_stream, double *f_pair, 
     return KCM_OK;
 }
 
+kcm_status kcm_get_atom_terms(const kcm_chain *c, void *hip_stream, double *e_elec, double *e_vdw, double *e_cav,
+                              int32_t *n_exposed)
+{
+    if (!c) return fail(KCM_E_INVAL, "null chain");
+    HIP_TRY(hipStreamSynchronize(static_cast<hipStream_t>(hip_stream)));
+    std::vector<double4> e(c->n);
+    HIP_TRY(hipMemcpy(e.data(), c->h.e_atom, 32 * (size_t)c->n, hipMemcpyDeviceToHost));
+    for (int a = 0; a < c->n; ++a) {
+        if (e_elec) e_elec[a] = e[a].x;
+        if (e_vdw) e_vdw[a] = e[a].y;
+        if (e_cav) e_cav[a] = e[a].z;
+        if (n_exposed) n_exposed[a] = (int32_t)e[a].w;
+    }
+    return KCM_OK;
+}
+
 kcm_status kcm_set_theta(kcm_chain *c, const double *theta, void *hip_stream)
 {
     if (!c || !theta) return fail(KCM_E_INVAL, "null chain or theta");
@@ -742,6 +775,7 @@ kcm_status kcm_set_theta(kcm_chain *c, const double *theta, void *hip_stream)
     if ((st = write_field(&c->h.stats->converged, 0, s)) != KCM_OK) return st;
     if ((st = write_field(&c->h.stats->status, 0, s)) != KCM_OK) return st;
     if ((st = write_field(&c->h.stats->nbr_overflow, 0, s)) != KCM_OK) return st;
+    if ((st = write_field(&c->h.stats->need_grid, 1, s)) != KCM_OK) return st;
     return write_field(&c->h.stats->active, 1, s);
 }
 
@@ -756,7 +790,7 @@ kcm_status kcm_get_cells(const kcm_chain *c, void *hip_stream, int32_t *dims, do
     if (cell_size) *cell_size = g.cell;
     if (origin) for (int k = 0; k < 3; ++k) origin[k] = g.origin[k];
     if (n_cells) *n_cells = g.n_cells;
-    if (order) HIP_TRY(hipMemcpy(order, c->h.order, 4 * (size_t)c->n, hipMemcpyDeviceToHost));
+    if (order) HIP_TRY(hipMemcpy(order, c->h.s_idx, 4 * (size_t)c->n, hipMemcpyDeviceToHost));
     if (cell_start) {
         if (cell_start_capacity < g.n_cells + 1) return fail(KCM_E_INVAL, "cell_start_capacity too small");
         HIP_TRY(hipMemcpy(cell_start, c->h.cell_start, 4 * ((size_t)g.n_cells + 1), hipMemcpyDeviceToHost));

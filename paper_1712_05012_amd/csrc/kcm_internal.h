@@ -26,6 +26,8 @@ struct ChainStats {
     int32_t converged;
     int32_t active;                // 0: the kernels skip this chain
     int32_t nbr_overflow;          // set by the force kernel, folded into status
+    int32_t need_grid;             // 1: no bounding box of the current conformation yet
+    int32_t pad;
 };
 
 // Cell grid of the current iteration (written by the chain kernel).
@@ -59,27 +61,45 @@ struct ChainDev {
     double *g0;          // [n] 4 pi gamma R_off^2
     long long *qfix;     // [n] event quantum G0/(N dr) in fixed point
     int32_t *cell_key;   // [n] cell of each atom
+    int32_t *cell_count; // [cap] atoms per cell
     int32_t *cell_start; // [cap+1]
-    int32_t *cell_fill;  // [cap]
-    int32_t *order;      // [n] sorted slot -> atom
+    int32_t *cell_cursor;// [cap]
+    unsigned long long *bbox_acc;  // [6] order-preserving encoded min xyz, max xyz
     double4 *s_r;        // [n] positions in cell order
     double4 *s_p;        // [n] parameters in cell order
-    int32_t *s_idx;      // [n] atom of each sorted slot
+    int32_t *s_idx;      // [n] atom of each sorted slot (the cell order)
     int32_t *s_cell;     // [n] cell of each sorted slot
     double4 *f_pair;     // [n] Coulomb + LJ force
     long long *f_cav;    // [3n] solvation force, fixed point
-    double4 *e_atom;     // [n] (elec, vdw, cav) per atom
+    double4 *e_atom;     // [n] (elec, vdw, cav, exposed samples) per atom
     double4 *q64;        // [N] unit sample directions
     float4 *q32;         // [N]
     Grid *grid;
     ChainStats *stats;
 };
 
-// Launchers (kcm_kernels.hip).  table: device array of device descriptors;
-// atom_off: device array [n_chains+1] of cumulative atom counts.
-hipError_t launch_chain_pre(ChainDev *const *table, int n_chains, hipStream_t s);
-hipError_t launch_force(ChainDev *const *table, const int32_t *atom_off, int n_chains,
-                        int total_atoms, int precision, hipStream_t s);
-hipError_t launch_chain_post(ChainDev *const *table, int n_chains, hipStream_t s);
+// The chains of one call.  table: device array of device descriptors;
+// atom_off / blk_off: device arrays [n_chains+1] of cumulative atom counts and
+// of cumulative per-atom workgroup counts (ATOM_BLOCK atoms per workgroup).
+constexpr int ATOM_BLOCK = 256;
+struct Batch {
+    ChainDev *const *table;
+    const int32_t *atom_off;
+    const int32_t *blk_off;
+    int n_chains;
+    int total_atoms;
+    int total_blocks;
+};
+
+// Launchers (kcm_kernels.hip).  One iteration is
+//   chain(post of the previous iteration if any, then kinematics + grid),
+//   place, cellscan, scatter, cellsort, force;
+// a call ends with chain(post only).
+hipError_t launch_chain(const Batch &b, int do_post, int do_fk, hipStream_t s);
+hipError_t launch_place(const Batch &b, hipStream_t s);
+hipError_t launch_cellscan(const Batch &b, hipStream_t s);
+hipError_t launch_scatter(const Batch &b, hipStream_t s);
+hipError_t launch_cellsort(const Batch &b, hipStream_t s);
+hipError_t launch_force(const Batch &b, int precision, hipStream_t s);
 
 }  // namespace kcm

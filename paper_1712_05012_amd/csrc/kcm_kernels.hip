@@ -1,21 +1,30 @@
 // kcm_kernels.hip -- gfx950 kernels of one KCM iteration.
 //
-//   k_chain_pre   one workgroup per chain: forward kinematics as an ordered
-//                 prefix scan of rigid transforms (eqs kin_02-kin_04, r1; the
-//                 prefix computation of Sec. 3.5 item 1), atom placement, the
-//                 bounding box and the cell list (Sec. 3.2) as a counting
-//                 radix sort on the cell key with a per-cell order fix-up so
-//                 that the sorted order is deterministic.
-//   k_force       one workgroup per atom, atoms taken in cell order: gathers
-//                 the stencil candidates in FP64, evaluates Coulomb + LJ
-//                 (eqs 02-03_9) over the full pair list, keeps the solvation
-//                 neighbours in LDS and runs the SASA enumeration of
-//                 Algorithm 1 with the C-state rules (Sec. 3.4), one sample
-//                 per lane; solvation events are scattered as fixed-point
-//                 integers so every sum is order independent.
-//   k_chain_post  one workgroup per chain: link wrenches and the suffix (row)
-//                 scan of eq 04_9 giving tau_k = u_k . (T_k - p_k x F_k)
-//                 (eqs KCM_01-KCM_06), then the compliance step (eq KCM_07).
+//   k_chain     one workgroup per chain.  Post phase of the previous
+//               iteration: link wrenches and the suffix (row) scan of eq 04_9
+//               giving tau_k = u_k . (T_k - p_k x F_k) (eqs KCM_01-KCM_06),
+//               then the compliance step (eq KCM_07).  Then forward
+//               kinematics of the new angles as an ordered prefix scan of
+//               rigid transforms (eqs kin_02-kin_04, r1; prefix computation
+//               item 1 of Sec. 3.5) and the cell grid of Sec. 3.2, sized from
+//               the previous bounding box plus a margin (atoms outside it are
+//               clamped to the border cells, which keeps every neighbour
+//               within the stencil).
+//   k_place     one thread per atom: r_a = G_link(a) r0_a, cell key, cell
+//               count, bounding box of the new positions.
+//   k_cellscan  one workgroup per chain: cell starts by an exclusive scan.
+//   k_scatter   one thread per atom: counting-sort scatter by cell key.
+//   k_cellsort  one thread per cell: restores atom order inside the cell
+//               (the sort is then stable, so everything downstream is
+//               deterministic) and gathers positions/parameters in cell order.
+//   k_force     one workgroup per atom, atoms in cell order: stencil
+//               candidates in FP64, Coulomb + LJ (eqs 02-03_9) over the full
+//               pair list, solvation neighbours in LDS, and the SASA
+//               enumeration of Algorithm 1 with the C-state rules (Sec. 3.4):
+//               coverage counts with one sample per lane, then the displaced
+//               tests for the compacted exposed samples only.  Solvation
+//               events are scattered as fixed-point integers, so every sum is
+//               order independent.
 #include "kcm_internal.h"
 
 #include <float.h>
@@ -197,29 +206,187 @@ __device__ int block_excl_scan(int v, int *scratch, int *total)
     return base + x - v;
 }
 
-__device__ __forceinline__ int load_counter(int *p)
+
+__device__ __forceinline__ int find_block_owner(const int32_t *off, int n, int b)
 {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    int lo = 0, hi = n;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (off[mid] <= b) lo = mid; else hi = mid;
+    }
+    return lo;
 }
 
-// ---------------------------------------------------------------------------
-// k_chain_pre: forward kinematics + cell list
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(CHAIN_THREADS) void k_chain_pre(ChainDev *const *table)
+// order-preserving map of doubles to unsigned 64-bit integers (for atomic min/max)
+__device__ __forceinline__ unsigned long long enc_d(double x)
 {
-    ChainDev *cd = table[blockIdx.x];
+    const unsigned long long u = (unsigned long long)__double_as_longlong(x);
+    return (u >> 63) ? ~u : (u | 0x8000000000000000ull);
+}
+__device__ __forceinline__ double dec_d(unsigned long long e)
+{
+    const unsigned long long u = (e >> 63) ? (e & 0x7FFFFFFFFFFFFFFFull) : ~e;
+    return __longlong_as_double((long long)u);
+}
+
+__device__ __forceinline__ double4 place_atom(const ChainDev *cd, int a)
+{
+    const double *L = cd->xform + 12 * link_of_atom(a);
+    const double4 q = cd->r0[a];
+    double4 r;
+    r.x = L[0] * q.x + L[1] * q.y + L[2] * q.z + L[9];
+    r.y = L[3] * q.x + L[4] * q.y + L[5] * q.z + L[10];
+    r.z = L[6] * q.x + L[7] * q.y + L[8] * q.z + L[11];
+    r.w = 0.0;
+    return r;
+}
+
+__device__ __forceinline__ int cell_of(const Grid &g, const double4 &r)
+{
+    int cx = (int)floor((r.x - g.origin[0]) * g.inv_cell);
+    int cy = (int)floor((r.y - g.origin[1]) * g.inv_cell);
+    int cz = (int)floor((r.z - g.origin[2]) * g.inv_cell);
+    cx = min(max(cx, 0), g.dims[0] - 1);
+    cy = min(max(cy, 0), g.dims[1] - 1);
+    cz = min(max(cz, 0), g.dims[2] - 1);
+    return (cz * g.dims[1] + cy) * g.dims[0] + cx;
+}
+
+constexpr double GRID_MARGIN = 2.0;  // A added around the previous bounding box
+
+// ---------------------------------------------------------------------------
+// k_chain: post phase of the previous iteration, then kinematics and grid
+// ---------------------------------------------------------------------------
+__device__ void post_phase(ChainDev *cd, int *s_flag, double *s_red, double (*s_w)[6])
+{
     ChainStats *st = cd->stats;
-    if (!st->active) return;
     const int J = cd->n_joints, n = cd->n_atoms;
     const int tid = threadIdx.x, nt = blockDim.x, lane = tid & (WAVE - 1), w = tid / WAVE, nw = nt / WAVE;
+    const double inv_fix = 1.0 / FIX_SCALE;
 
-    __shared__ double s_x[CHAIN_THREADS / WAVE][12];
-    __shared__ double s_red[CHAIN_THREADS / WAVE * 6];
-    __shared__ int s_int[CHAIN_THREADS / WAVE];
-    __shared__ Grid s_g;
-    __shared__ int s_ok;
+    const int chunk = (n + nt - 1) / nt;
+    const int a0 = min(n, tid * chunk), a1 = min(n, a0 + chunk);
+    double W[6] = {0, 0, 0, 0, 0, 0};
+    double E[4] = {0, 0, 0, 0};
+    for (int a = a0; a < a1; ++a) {
+        const double4 fp = cd->f_pair[a];
+        const double Fx = fp.x + (double)cd->f_cav[3 * a] * inv_fix;
+        const double Fy = fp.y + (double)cd->f_cav[3 * a + 1] * inv_fix;
+        const double Fz = fp.z + (double)cd->f_cav[3 * a + 2] * inv_fix;
+        const double4 r = cd->r[a];
+        W[0] += Fx; W[1] += Fy; W[2] += Fz;
+        W[3] += r.y * Fz - r.z * Fy; W[4] += r.z * Fx - r.x * Fz; W[5] += r.x * Fy - r.y * Fx;
+        const double4 e = cd->e_atom[a];
+        E[0] += e.x; E[1] += e.y; E[2] += e.z;
+        if (!(isfinite(Fx) && isfinite(Fy) && isfinite(Fz))) E[3] = 1.0;
+    }
+    // exclusive suffix over threads: the wrench of every later chunk
+    double S[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) S[k] = W[k];
+#pragma unroll
+    for (int d = 1; d < WAVE; d <<= 1) {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            const double y = __shfl_down(S[k], d, WAVE);
+            if (lane + d < WAVE) S[k] += y;
+        }
+    }
+    if (lane == 0)
+        for (int k = 0; k < 6; ++k) s_w[w][k] = S[k];
+    __syncthreads();
+    if (tid == 0) {
+        double acc[6] = {0, 0, 0, 0, 0, 0};
+        for (int i = nw - 1; i >= 0; --i)
+            for (int k = 0; k < 6; ++k) {
+                const double t = s_w[i][k];
+                s_w[i][k] = acc[k];
+                acc[k] += t;
+            }
+    }
+    __syncthreads();
+    double X[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        const double nxt = __shfl_down(S[k], 1, WAVE);
+        X[k] = s_w[w][k] + (lane < WAVE - 1 ? nxt : 0.0);
+    }
+    // walk the chunk backwards; at the first atom of link l >= 1 emit tau_{l-1}
+    for (int a = a1 - 1; a >= a0; --a) {
+        const double4 fp = cd->f_pair[a];
+        const double Fx = fp.x + (double)cd->f_cav[3 * a] * inv_fix;
+        const double Fy = fp.y + (double)cd->f_cav[3 * a + 1] * inv_fix;
+        const double Fz = fp.z + (double)cd->f_cav[3 * a + 2] * inv_fix;
+        const double4 r = cd->r[a];
+        X[0] += Fx; X[1] += Fy; X[2] += Fz;
+        X[3] += r.y * Fz - r.z * Fy; X[4] += r.z * Fx - r.x * Fz; X[5] += r.x * Fy - r.y * Fx;
+        const int res = a / APR, slot = a - res * APR;
+        if (slot == 2 || slot == 8) {
+            const int j = 2 * res + (slot == 8 ? 1 : 0);
+            const double4 u = cd->jcur[2 * j], p = cd->jcur[2 * j + 1];
+            const double mx = X[3] - (p.y * X[2] - p.z * X[1]);
+            const double my = X[4] - (p.z * X[0] - p.x * X[2]);
+            const double mz = X[5] - (p.x * X[1] - p.y * X[0]);
+            cd->tau[j] = u.x * mx + u.y * my + u.z * mz;
+        }
+    }
+    block_sum<4>(E, s_red);
 
-    // 1. ordered scan of joint transforms: G_j = T_0 o T_1 o ... o T_j
+    double tmax = 0.0;
+    bool tbad = false;
+    for (int j = tid; j < J; j += nt) {
+        const double t = cd->tau[j];
+        if (!isfinite(t)) tbad = true;
+        if (cd->mask[j]) tmax = fmax(tmax, fabs(t));
+    }
+    tmax = block_max(tmax, s_red);
+    const double anybad = block_max(tbad ? 1.0 : 0.0, s_red);
+    if (E[3] > 0.0 || anybad > 0.0) {
+        if (tid == 0) {
+            st->e_elec = E[0]; st->e_vdw = E[1]; st->e_cav = E[2];
+            st->status = -4;
+            st->active = 0;
+            *s_flag = 0;
+        }
+        __syncthreads();
+        return;
+    }
+    const double kappa = cd->kappa, s = cd->max_step;
+    double scale;
+    if (cd->step_rule == 1) scale = tmax > 0.0 ? s / tmax : 0.0;
+    else if (cd->step_rule == 2) scale = kappa;
+    else scale = (kappa * tmax > s) ? s / tmax : kappa;
+    double mxd = 0.0;
+    for (int j = tid; j < J; j += nt) {
+        const double d = cd->mask[j] ? scale * cd->tau[j] : 0.0;
+        cd->dtheta[j] = d;
+        mxd = fmax(mxd, fabs(d));
+        double t = cd->theta[j] + d;
+        if (t > PI_D) t -= 2.0 * PI_D;
+        if (t <= -PI_D) t += 2.0 * PI_D;
+        cd->theta[j] = t;
+    }
+    mxd = block_max(mxd, s_red);
+    if (tid == 0) {
+        st->e_elec = E[0]; st->e_vdw = E[1]; st->e_cav = E[2];
+        st->max_tau = tmax;
+        st->max_dtheta = mxd;
+        st->iterations += 1;
+        if (st->nbr_overflow) st->status = -6;
+        if (st->tol > 0.0 && mxd < st->tol) {
+            st->converged = 1;
+            st->active = 0;
+        }
+        if (st->iterations >= st->iter_limit) st->active = 0;
+        *s_flag = st->active;
+    }
+    __syncthreads();
+}
+
+__device__ void fk_phase(ChainDev *cd, double (*s_x)[12])
+{
+    const int J = cd->n_joints;
+    const int tid = threadIdx.x, nt = blockDim.x, lane = tid & (WAVE - 1), w = tid / WAVE, nw = nt / WAVE;
     const int chunk = (J + nt - 1) / nt;
     const int j0 = min(J, tid * chunk), j1 = min(J, j0 + chunk);
     Xf x = xf_identity();
@@ -261,45 +428,70 @@ __global__ __launch_bounds__(CHAIN_THREADS) void k_chain_pre(ChainDev *const *ta
     }
     if (tid == 0) xf_store(cd->xform, xf_identity());
     __syncthreads();
+}
 
-    // 2. atom placement r_a = G_link(a) r0_a and bounding box
-    double lo[3] = {DBL_MAX, DBL_MAX, DBL_MAX}, hi[3] = {-DBL_MAX, -DBL_MAX, -DBL_MAX};
-    bool finite = true;
-    for (int a = tid; a < n; a += nt) {
-        const Xf L = xf_load(cd->xform + 12 * link_of_atom(a));
-        const double4 q = cd->r0[a];
-        double4 r;
-        r.x = L.r[0] * q.x + L.r[1] * q.y + L.r[2] * q.z + L.t[0];
-        r.y = L.r[3] * q.x + L.r[4] * q.y + L.r[5] * q.z + L.t[1];
-        r.z = L.r[6] * q.x + L.r[7] * q.y + L.r[8] * q.z + L.t[2];
-        r.w = 0.0;
-        cd->r[a] = r;
-        finite = finite && isfinite(r.x) && isfinite(r.y) && isfinite(r.z);
-        lo[0] = fmin(lo[0], r.x); lo[1] = fmin(lo[1], r.y); lo[2] = fmin(lo[2], r.z);
-        hi[0] = fmax(hi[0], r.x); hi[1] = fmax(hi[1], r.y); hi[2] = fmax(hi[2], r.z);
-    }
+__global__ __launch_bounds__(CHAIN_THREADS) void k_chain(Batch bt, int do_post, int do_fk)
+{
+    ChainDev *cd = bt.table[blockIdx.x];
+    ChainStats *st = cd->stats;
+    if (!st->active) return;
+    __shared__ double s_x[CHAIN_THREADS / WAVE][12];
+    __shared__ double s_w[CHAIN_THREADS / WAVE][6];
+    __shared__ double s_red[CHAIN_THREADS / WAVE * 6];
+    __shared__ int s_flag;
+    __shared__ double s_bb[6];
+    const int tid = threadIdx.x, nt = blockDim.x, lane = tid & (WAVE - 1), w = tid / WAVE, nw = nt / WAVE;
+    if (tid == 0) s_flag = 1;
+    __syncthreads();
+    if (do_post) post_phase(cd, &s_flag, s_red, s_w);
+    if (!do_fk || !s_flag) return;
+    fk_phase(cd, s_x);
+
+    // bounding box that sizes this iteration's grid
+    const int n = cd->n_atoms;
+    if (st->need_grid) {
+        double lo[3] = {DBL_MAX, DBL_MAX, DBL_MAX}, hi[3] = {-DBL_MAX, -DBL_MAX, -DBL_MAX};
+        bool finite = true;
+        for (int a = tid; a < n; a += nt) {
+            const double4 r = place_atom(cd, a);
+            finite = finite && isfinite(r.x) && isfinite(r.y) && isfinite(r.z);
+            lo[0] = fmin(lo[0], r.x); lo[1] = fmin(lo[1], r.y); lo[2] = fmin(lo[2], r.z);
+            hi[0] = fmax(hi[0], r.x); hi[1] = fmax(hi[1], r.y); hi[2] = fmax(hi[2], r.z);
+        }
 #pragma unroll
-    for (int k = 0; k < 3; ++k) { lo[k] = wave_min(lo[k]); hi[k] = wave_max(hi[k]); }
-    const int bad_w = __any(!finite);
-    if (tid == 0) s_ok = 1;
-    __syncthreads();
-    if (lane == 0) {
-        for (int k = 0; k < 3; ++k) { s_red[w * 6 + k] = lo[k]; s_red[w * 6 + 3 + k] = hi[k]; }
-        if (bad_w) s_ok = 0;
+        for (int k = 0; k < 3; ++k) { lo[k] = wave_min(lo[k]); hi[k] = wave_max(hi[k]); }
+        const int bad_w = __any(!finite);
+        if (lane == 0) {
+            for (int k = 0; k < 3; ++k) { s_red[w * 6 + k] = lo[k]; s_red[w * 6 + 3 + k] = hi[k]; }
+            if (bad_w) s_flag = 0;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            for (int k = 0; k < 3; ++k) { s_bb[k] = DBL_MAX; s_bb[3 + k] = -DBL_MAX; }
+            for (int i = 0; i < nw; ++i)
+                for (int k = 0; k < 3; ++k) {
+                    s_bb[k] = fmin(s_bb[k], s_red[i * 6 + k]);
+                    s_bb[3 + k] = fmax(s_bb[3 + k], s_red[i * 6 + 3 + k]);
+                }
+            if (!s_flag) s_bb[0] = NAN;
+            st->need_grid = 0;
+        }
+    } else if (tid == 0) {
+        for (int k = 0; k < 6; ++k) s_bb[k] = dec_d(cd->bbox_acc[k]);
     }
     __syncthreads();
 
-    // 3. grid: cubic cells of edge >= cell_min; coarsened until it fits cap_cells
     if (tid == 0) {
-        double L3[3], H3[3];
-        for (int k = 0; k < 3; ++k) { L3[k] = DBL_MAX; H3[k] = -DBL_MAX; }
-        for (int i = 0; i < nw; ++i)
-            for (int k = 0; k < 3; ++k) { L3[k] = fmin(L3[k], s_red[i * 6 + k]); H3[k] = fmax(H3[k], s_red[i * 6 + 3 + k]); }
         const double reach_len = fmax(cd->cutoff, 2.0 * cd->roff_max + cd->delta_r) + 1e-7;
+        double L3[3], H3[3];
+        bool ok = true;
+        for (int k = 0; k < 3; ++k) {
+            L3[k] = s_bb[k] - GRID_MARGIN;
+            H3[k] = s_bb[3 + k] + GRID_MARGIN;
+            ok = ok && isfinite(L3[k]) && isfinite(H3[k]) && H3[k] >= L3[k] && (H3[k] - L3[k]) < 1e7;
+        }
         double cell = fmax(cd->cell_min, reach_len / MAX_REACH);
         long long dims[3] = {1, 1, 1};
-        bool ok = s_ok != 0;
-        for (int k = 0; k < 3 && ok; ++k) ok = isfinite(L3[k]) && isfinite(H3[k]) && (H3[k] - L3[k]) < 1e7;
         for (int it = 0; ok && it < 200; ++it) {
             for (int k = 0; k < 3; ++k) dims[k] = (long long)floor((H3[k] - L3[k]) / cell) + 1;
             if (dims[0] * dims[1] * dims[2] <= cd->cap_cells) break;
@@ -307,92 +499,132 @@ __global__ __launch_bounds__(CHAIN_THREADS) void k_chain_pre(ChainDev *const *ta
         }
         ok = ok && dims[0] * dims[1] * dims[2] <= cd->cap_cells;
         Grid g;
-        for (int k = 0; k < 3; ++k) { g.origin[k] = L3[k]; g.dims[k] = (int)dims[k]; }
+        for (int k = 0; k < 3; ++k) { g.origin[k] = ok ? L3[k] : 0.0; g.dims[k] = ok ? (int)dims[k] : 1; }
         g.cell = cell;
         g.inv_cell = 1.0 / cell;
-        g.reach = (int)ceil(reach_len / cell - 1e-9);
-        if (g.reach < 1) g.reach = 1;
+        g.reach = max(1, (int)ceil(reach_len / cell - 1e-9));
         g.n_cells = ok ? (int)(dims[0] * dims[1] * dims[2]) : 0;
         g.pad = 0;
-        s_g = g;
         *cd->grid = g;
-        s_ok = ok ? 1 : 0;
+        s_flag = ok ? g.n_cells : 0;
         if (!ok) {
             st->status = -4;
             st->active = 0;
         }
-    }
-    __syncthreads();
-    if (!s_ok) return;
-    const Grid g = s_g;
-    const int nc = g.n_cells;
-
-    // 4. cell keys and counts
-    for (int c = tid; c < nc; c += nt) cd->cell_fill[c] = 0;
-    __syncthreads();
-    for (int a = tid; a < n; a += nt) {
-        const double4 r = cd->r[a];
-        int cx = (int)floor((r.x - g.origin[0]) * g.inv_cell);
-        int cy = (int)floor((r.y - g.origin[1]) * g.inv_cell);
-        int cz = (int)floor((r.z - g.origin[2]) * g.inv_cell);
-        cx = min(max(cx, 0), g.dims[0] - 1);
-        cy = min(max(cy, 0), g.dims[1] - 1);
-        cz = min(max(cz, 0), g.dims[2] - 1);
-        const int key = (cz * g.dims[1] + cy) * g.dims[0] + cx;
-        cd->cell_key[a] = key;
-        atomicAdd(&cd->cell_fill[key], 1);
-    }
-    __syncthreads();
-
-    // 5. exclusive scan of the counts -> cell_start
-    {
-        const int cch = (nc + nt - 1) / nt;
-        const int c0 = min(nc, tid * cch), c1 = min(nc, c0 + cch);
-        int loc = 0;
-        for (int c = c0; c < c1; ++c) loc += load_counter(&cd->cell_fill[c]);
-        int total = 0;
-        int run = block_excl_scan(loc, s_int, &total);
-        for (int c = c0; c < c1; ++c) {
-            const int k = load_counter(&cd->cell_fill[c]);
-            cd->cell_start[c] = run;
-            run += k;
+        for (int k = 0; k < 3; ++k) {
+            cd->bbox_acc[k] = enc_d(DBL_MAX);
+            cd->bbox_acc[3 + k] = enc_d(-DBL_MAX);
         }
-        if (tid == 0) cd->cell_start[nc] = total;
     }
     __syncthreads();
-    for (int c = tid; c < nc; c += nt) cd->cell_fill[c] = 0;
-    __syncthreads();
+    const int nc = s_flag;
+    for (int c = tid; c < nc; c += nt) cd->cell_count[c] = 0;
+}
 
-    // 6. scatter, then 7. restore atom order inside every cell (stable result)
-    for (int a = tid; a < n; a += nt) {
-        const int key = cd->cell_key[a];
-        const int pos = cd->cell_start[key] + atomicAdd(&cd->cell_fill[key], 1);
-        cd->order[pos] = a;
+// ---------------------------------------------------------------------------
+// k_place: positions, cell keys, cell counts, bounding box
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(ATOM_BLOCK) void k_place(Batch bt)
+{
+    const int c = find_block_owner(bt.blk_off, bt.n_chains, blockIdx.x);
+    ChainDev *cd = bt.table[c];
+    if (!cd->stats->active) return;
+    const int a = (blockIdx.x - bt.blk_off[c]) * ATOM_BLOCK + threadIdx.x;
+    const int n = cd->n_atoms;
+    double lo[3] = {DBL_MAX, DBL_MAX, DBL_MAX}, hi[3] = {-DBL_MAX, -DBL_MAX, -DBL_MAX};
+    if (a < n) {
+        const Grid g = *cd->grid;
+        const double4 r = place_atom(cd, a);
+        cd->r[a] = r;
+        const int key = cell_of(g, r);
+        cd->cell_key[a] = key;
+        atomicAdd(&cd->cell_count[key], 1);
+        cd->f_cav[3 * a] = 0;
+        cd->f_cav[3 * a + 1] = 0;
+        cd->f_cav[3 * a + 2] = 0;
+        lo[0] = r.x; lo[1] = r.y; lo[2] = r.z;
+        hi[0] = r.x; hi[1] = r.y; hi[2] = r.z;
     }
-    __syncthreads();
-    for (int c = tid; c < nc; c += nt) {
-        const int b = cd->cell_start[c], e = cd->cell_start[c + 1];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) { lo[k] = wave_min(lo[k]); hi[k] = wave_max(hi[k]); }
+    if ((threadIdx.x & (WAVE - 1)) == 0 && lo[0] <= hi[0]) {
+        for (int k = 0; k < 3; ++k) {
+            atomicMin(&cd->bbox_acc[k], enc_d(lo[k]));
+            atomicMax(&cd->bbox_acc[3 + k], enc_d(hi[k]));
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_cellscan: cell_start = exclusive scan of the counts
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(CHAIN_THREADS) void k_cellscan(Batch bt)
+{
+    ChainDev *cd = bt.table[blockIdx.x];
+    if (!cd->stats->active) return;
+    __shared__ int s_int[CHAIN_THREADS / WAVE];
+    const int nc = cd->grid->n_cells;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int cch = (nc + nt - 1) / nt;
+    const int c0 = min(nc, tid * cch), c1 = min(nc, c0 + cch);
+    int loc = 0;
+    for (int c = c0; c < c1; ++c) loc += cd->cell_count[c];
+    int total = 0;
+    int run = block_excl_scan(loc, s_int, &total);
+    for (int c = c0; c < c1; ++c) {
+        const int k = cd->cell_count[c];
+        cd->cell_start[c] = run;
+        cd->cell_cursor[c] = 0;
+        run += k;
+    }
+    if (tid == 0) cd->cell_start[nc] = total;
+}
+
+// ---------------------------------------------------------------------------
+// k_scatter: counting-sort scatter (order inside a cell fixed by k_cellsort)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(ATOM_BLOCK) void k_scatter(Batch bt)
+{
+    const int c = find_block_owner(bt.blk_off, bt.n_chains, blockIdx.x);
+    ChainDev *cd = bt.table[c];
+    if (!cd->stats->active) return;
+    const int a = (blockIdx.x - bt.blk_off[c]) * ATOM_BLOCK + threadIdx.x;
+    if (a >= cd->n_atoms) return;
+    const int key = cd->cell_key[a];
+    const int pos = cd->cell_start[key] + atomicAdd(&cd->cell_cursor[key], 1);
+    cd->s_idx[pos] = a;
+}
+
+// ---------------------------------------------------------------------------
+// k_cellsort: atom order inside each cell, then gather in cell order
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(ATOM_BLOCK) void k_cellsort(Batch bt)
+{
+    const int c = find_block_owner(bt.blk_off, bt.n_chains, blockIdx.x);
+    ChainDev *cd = bt.table[c];
+    if (!cd->stats->active) return;
+    const int nblk = bt.blk_off[c + 1] - bt.blk_off[c];
+    const int nc = cd->grid->n_cells;
+    for (int cell = (blockIdx.x - bt.blk_off[c]) * ATOM_BLOCK + threadIdx.x; cell < nc; cell += nblk * ATOM_BLOCK) {
+        const int b = cd->cell_start[cell], e = cd->cell_start[cell + 1];
+        if (b == e) continue;
+        int *o = cd->s_idx;
         for (int i = b + 1; i < e; ++i) {
-            const int v = cd->order[i];
+            const int v = o[i];
             int k = i - 1;
-            while (k >= b && cd->order[k] > v) {
-                cd->order[k + 1] = cd->order[k];
+            while (k >= b && o[k] > v) {
+                o[k + 1] = o[k];
                 --k;
             }
-            cd->order[k + 1] = v;
+            o[k + 1] = v;
+        }
+        for (int s = b; s < e; ++s) {
+            const int a = o[s];
+            cd->s_r[s] = cd->r[a];
+            cd->s_p[s] = cd->aparam[a];
+            cd->s_cell[s] = cell;
         }
     }
-    __syncthreads();
-
-    // 8. gather into cell order; clear the fixed-point solvation accumulators
-    for (int s = tid; s < n; s += nt) {
-        const int a = cd->order[s];
-        cd->s_r[s] = cd->r[a];
-        cd->s_p[s] = cd->aparam[a];
-        cd->s_idx[s] = a;
-        cd->s_cell[s] = cd->cell_key[a];
-    }
-    for (int k = tid; k < 3 * n; k += nt) cd->f_cav[k] = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -403,13 +635,6 @@ struct NbrEntry {
     Real ax, ay, az, c0;   // offset a = r_j - r_i and the covering threshold
     Real cx, cy, cz, pad;  // thresholds of the three displaced copies of j
 };
-
-template <typename Real>
-struct Vec4T;
-template <>
-struct Vec4T<float> { using type = float4; };
-template <>
-struct Vec4T<double> { using type = double4; };
 
 // FP64 decision in absolute coordinates: is sample k of atom i covered by the
 // offset sphere of sorted atom sj, shifted by delta_r along axis s (s < 0: not
@@ -428,18 +653,30 @@ __device__ __forceinline__ bool cover_exact(const ChainDev *cd, const double4 &r
 }
 
 template <typename Real, bool MIXED>
-__device__ __forceinline__ bool test_cover(Real dot, Real thr, const ChainDev *cd, const double4 &ri, double roff_i, int k,
+__device__ __forceinline__ bool test_cover(Real v, Real thr, const ChainDev *cd, const double4 &ri, double roff_i, int k,
                                            int sj, int s)
 {
-    bool hit = dot >= thr;
+    bool hit = v >= thr;
     if (MIXED) {
-        if (fabsf((float)(dot - thr)) <= MIXED_BAND) hit = cover_exact(cd, ri, roff_i, k, sj, s);
+        if (fabsf((float)(v - thr)) <= MIXED_BAND) hit = cover_exact(cd, ri, roff_i, k, sj, s);
     }
     return hit;
 }
 
 template <typename Real>
-__global__ __launch_bounds__(FORCE_THREADS) void k_force(ChainDev *const *table, const int32_t *atom_off, int n_chains)
+__device__ __forceinline__ void load_q(const ChainDev *cd, int k, Real &x, Real &y, Real &z)
+{
+    if (sizeof(Real) == 4) {
+        const float4 q = cd->q32[k];
+        x = (Real)q.x; y = (Real)q.y; z = (Real)q.z;
+    } else {
+        const double4 q = cd->q64[k];
+        x = (Real)q.x; y = (Real)q.y; z = (Real)q.z;
+    }
+}
+
+template <typename Real>
+__global__ __launch_bounds__(FORCE_THREADS) void k_force(Batch bt)
 {
     constexpr bool MIXED = sizeof(Real) == 4;
     constexpr int MAX_ROWS = (2 * MAX_REACH + 1) * (2 * MAX_REACH + 1);
@@ -448,19 +685,15 @@ __global__ __launch_bounds__(FORCE_THREADS) void k_force(ChainDev *const *table,
     __shared__ int s_ev[MAX_NBR * 3];
     __shared__ int s_row_beg[MAX_ROWS];
     __shared__ int s_row_off[MAX_ROWS + 1];
+    __shared__ int s_exp[FORCE_THREADS];
     __shared__ double s_red[(FORCE_THREADS / WAVE) * 5];
-    __shared__ int s_nn, s_ncov;
+    __shared__ int s_nn, s_ncov, s_nexp;
     __shared__ unsigned long long s_own[3];
 
-    const int b = blockIdx.x;
-    int lo = 0, hi = n_chains;
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (atom_off[mid] <= b) lo = mid; else hi = mid;
-    }
-    ChainDev *cd = table[lo];
+    const int c = find_block_owner(bt.atom_off, bt.n_chains, blockIdx.x);
+    ChainDev *cd = bt.table[c];
     if (!cd->stats->active) return;
-    const int si = b - atom_off[lo];
+    const int si = blockIdx.x - bt.atom_off[c];
     const int tid = threadIdx.x, nt = blockDim.x;
 
     const Grid g = *cd->grid;
@@ -489,15 +722,16 @@ __global__ __launch_bounds__(FORCE_THREADS) void k_force(ChainDev *const *table,
     if (tid == 0) {
         s_nn = 0;
         s_ncov = 0;
+        s_nexp = 0;
         s_own[0] = s_own[1] = s_own[2] = 0ull;
     }
     __syncthreads();
     if (tid == 0) {
         int run = 0;
         for (int t = 0; t < nrows; ++t) {
-            const int c = s_row_off[t];
+            const int cnt = s_row_off[t];
             s_row_off[t] = run;
-            run += c;
+            run += cnt;
         }
         s_row_off[nrows] = run;
     }
@@ -586,58 +820,68 @@ __global__ __launch_bounds__(FORCE_THREADS) void k_force(ChainDev *const *table,
     double pv[5] = {(double)fx, (double)fy, (double)fz, ee, evw};
     block_sum<5>(pv, s_red);
 
-    // SASA enumeration (Algorithm 1, C-state rules), one sample per lane
-    double e_cav = 0.0;
+    double e_cav = 0.0, n_exp = -1.0;
     if (do_cav) {
         const int nn_all = s_nn;
         const int nn = min(nn_all, MAX_NBR);
         if (nn_all > MAX_NBR && tid == 0) cd->stats->nbr_overflow = 1;
         const int N = cd->n_samples;
+        const Real drr = (Real)dr;
         int ncov = 0;
-        for (int k = tid; k < N; k += nt) {
-            Real Qx, Qy, Qz;
-            if (MIXED) {
-                const float4 q = cd->q32[k];
-                Qx = q.x; Qy = q.y; Qz = q.z;
-            } else {
-                const double4 q = cd->q64[k];
-                Qx = (Real)q.x; Qy = (Real)q.y; Qz = (Real)q.z;
+        for (int k0 = 0; k0 < N; k0 += nt) {
+            if (k0 > 0) {
+                if (tid == 0) s_nexp = 0;
+                __syncthreads();
             }
-            const Real dqx = (Real)dr * Qx, dqy = (Real)dr * Qy, dqz = (Real)dr * Qz;
-            // step 1: count covering neighbours; acc = 65536 * count + sum of their slots,
-            // so acc >> 16 == 1 identifies the single overlapper in the low bits
-            int acc = 0;
-            bool amb = false;
-            for (int u = 0; u < nn; ++u) {
-                const NbrEntry<Real> e = s_nbr[u];
-                const Real t = Qx * e.ax + Qy * e.ay + Qz * e.az - e.c0;
-                acc += (t >= (Real)0) ? (65536 + u) : 0;
-                if (MIXED) amb = amb || (fabsf((float)t) <= MIXED_BAND);
-            }
-            if (MIXED && amb) {
-                acc = 0;
-                for (int u = 0; u < nn; ++u)
-                    if (cover_exact(cd, ri, roff_i, k, s_nbr_j[u], -1)) acc += 65536 + u;
-            }
-            const int C = acc >> 16;
-            // step 2: critical neighbours along +e_s
-            if (C == 0) {
+            const int k = k0 + tid;
+            if (k < N) {
+                Real Qx, Qy, Qz;
+                load_q<Real>(cd, k, Qx, Qy, Qz);
+                // step 1: acc = 65536 * (covering neighbours) + (sum of their slots), so
+                // acc >> 16 == 1 leaves the single overlapper in the low bits
+                int acc = 0;
+                bool amb = false;
                 for (int u = 0; u < nn; ++u) {
                     const NbrEntry<Real> e = s_nbr[u];
-                    const Real dot = Qx * e.ax + Qy * e.ay + Qz * e.az;
-                    if (test_cover<Real, MIXED>(dot + dqx, e.cx, cd, ri, roff_i, k, s_nbr_j[u], 0)) atomicAdd(&s_ev[3 * u + 0], -1);
-                    if (test_cover<Real, MIXED>(dot + dqy, e.cy, cd, ri, roff_i, k, s_nbr_j[u], 1)) atomicAdd(&s_ev[3 * u + 1], -1);
-                    if (test_cover<Real, MIXED>(dot + dqz, e.cz, cd, ri, roff_i, k, s_nbr_j[u], 2)) atomicAdd(&s_ev[3 * u + 2], -1);
+                    const Real t = Qx * e.ax + Qy * e.ay + Qz * e.az - e.c0;
+                    acc += (t >= (Real)0) ? (65536 + u) : 0;
+                    if (MIXED) amb = amb || (fabsf((float)t) <= MIXED_BAND);
                 }
-            } else if (C == 1) {
-                const int u = acc & 0xFFFF;
+                if (MIXED && amb) {
+                    acc = 0;
+                    for (int u = 0; u < nn; ++u)
+                        if (cover_exact(cd, ri, roff_i, k, s_nbr_j[u], -1)) acc += 65536 + u;
+                }
+                const int C = acc >> 16;
+                if (C == 0) {
+                    s_exp[atomicAdd(&s_nexp, 1)] = k;
+                } else if (C == 1) {
+                    // critically overlapped: only the overlapper's shifted copies can expose it
+                    const int u = acc & 0xFFFF;
+                    const NbrEntry<Real> e = s_nbr[u];
+                    const Real dot = Qx * e.ax + Qy * e.ay + Qz * e.az;
+                    if (!test_cover<Real, MIXED>(dot + drr * Qx, e.cx, cd, ri, roff_i, k, s_nbr_j[u], 0)) atomicAdd(&s_ev[3 * u + 0], 1);
+                    if (!test_cover<Real, MIXED>(dot + drr * Qy, e.cy, cd, ri, roff_i, k, s_nbr_j[u], 1)) atomicAdd(&s_ev[3 * u + 1], 1);
+                    if (!test_cover<Real, MIXED>(dot + drr * Qz, e.cz, cd, ri, roff_i, k, s_nbr_j[u], 2)) atomicAdd(&s_ev[3 * u + 2], 1);
+                }
+                if (C >= 1) ++ncov;
+            }
+            __syncthreads();
+            // step 2 for the exposed samples of this batch: every (sample, neighbour) pair
+            const int nexp = s_nexp;
+            const int work = nexp * nn;
+            for (int wi = tid; wi < work; wi += nt) {
+                const int e_i = wi / nn, u = wi - e_i * nn;
+                const int k = s_exp[e_i];
+                Real Qx, Qy, Qz;
+                load_q<Real>(cd, k, Qx, Qy, Qz);
                 const NbrEntry<Real> e = s_nbr[u];
                 const Real dot = Qx * e.ax + Qy * e.ay + Qz * e.az;
-                if (!test_cover<Real, MIXED>(dot + dqx, e.cx, cd, ri, roff_i, k, s_nbr_j[u], 0)) atomicAdd(&s_ev[3 * u + 0], 1);
-                if (!test_cover<Real, MIXED>(dot + dqy, e.cy, cd, ri, roff_i, k, s_nbr_j[u], 1)) atomicAdd(&s_ev[3 * u + 1], 1);
-                if (!test_cover<Real, MIXED>(dot + dqz, e.cz, cd, ri, roff_i, k, s_nbr_j[u], 2)) atomicAdd(&s_ev[3 * u + 2], 1);
+                if (test_cover<Real, MIXED>(dot + drr * Qx, e.cx, cd, ri, roff_i, k, s_nbr_j[u], 0)) atomicAdd(&s_ev[3 * u + 0], -1);
+                if (test_cover<Real, MIXED>(dot + drr * Qy, e.cy, cd, ri, roff_i, k, s_nbr_j[u], 1)) atomicAdd(&s_ev[3 * u + 1], -1);
+                if (test_cover<Real, MIXED>(dot + drr * Qz, e.cz, cd, ri, roff_i, k, s_nbr_j[u], 2)) atomicAdd(&s_ev[3 * u + 2], -1);
             }
-            ncov += (C >= 1) ? 1 : 0;
+            __syncthreads();
         }
         ncov = wave_sum_i(ncov);
         if ((tid & (WAVE - 1)) == 0) atomicAdd(&s_ncov, ncov);
@@ -647,8 +891,9 @@ __global__ __launch_bounds__(FORCE_THREADS) void k_force(ChainDev *const *table,
         const long long qf = cd->qfix[ai];
         long long own0 = 0, own1 = 0, own2 = 0;
         for (int u = tid; u < nn; u += nt) {
-            const int aj = cd->s_idx[s_nbr_j[u]];
             const int e0 = s_ev[3 * u], e1 = s_ev[3 * u + 1], e2 = s_ev[3 * u + 2];
+            if (!(e0 | e1 | e2)) continue;
+            const int aj = cd->s_idx[s_nbr_j[u]];
             if (e0) { const long long v = (long long)e0 * qf; own0 += v; atomicAdd((unsigned long long *)&cd->f_cav[3 * aj + 0], (unsigned long long)(-v)); }
             if (e1) { const long long v = (long long)e1 * qf; own1 += v; atomicAdd((unsigned long long *)&cd->f_cav[3 * aj + 1], (unsigned long long)(-v)); }
             if (e2) { const long long v = (long long)e2 * qf; own2 += v; atomicAdd((unsigned long long *)&cd->f_cav[3 * aj + 2], (unsigned long long)(-v)); }
@@ -661,173 +906,60 @@ __global__ __launch_bounds__(FORCE_THREADS) void k_force(ChainDev *const *table,
             for (int s = 0; s < 3; ++s)
                 if (s_own[s]) atomicAdd((unsigned long long *)&cd->f_cav[3 * ai + s], s_own[s]);
             e_cav = cd->g0[ai] * (double)(N - s_ncov) / (double)N;  // eq G_cav_patch
+            n_exp = (double)(N - s_ncov);
         }
     }
     if (tid == 0) {
         cd->f_pair[ai] = make_double4(pv[0], pv[1], pv[2], 0.0);
-        cd->e_atom[ai] = make_double4(0.5 * pv[3], 0.5 * pv[4], e_cav, 0.0);
-    }
-}
-
-// ---------------------------------------------------------------------------
-// k_chain_post: wrenches, suffix scan, torques, compliance step
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(CHAIN_THREADS) void k_chain_post(ChainDev *const *table)
-{
-    ChainDev *cd = table[blockIdx.x];
-    ChainStats *st = cd->stats;
-    if (!st->active) return;
-    const int J = cd->n_joints, n = cd->n_atoms;
-    const int tid = threadIdx.x, nt = blockDim.x, lane = tid & (WAVE - 1), w = tid / WAVE, nw = nt / WAVE;
-    __shared__ double s_w[CHAIN_THREADS / WAVE][6];
-    __shared__ double s_red[CHAIN_THREADS / WAVE * 4];
-    const double inv_fix = 1.0 / FIX_SCALE;
-
-    const int chunk = (n + nt - 1) / nt;
-    const int a0 = min(n, tid * chunk), a1 = min(n, a0 + chunk);
-    double W[6] = {0, 0, 0, 0, 0, 0};
-    double E[4] = {0, 0, 0, 0};
-    for (int a = a0; a < a1; ++a) {
-        const double4 fp = cd->f_pair[a];
-        const double Fx = fp.x + (double)cd->f_cav[3 * a] * inv_fix;
-        const double Fy = fp.y + (double)cd->f_cav[3 * a + 1] * inv_fix;
-        const double Fz = fp.z + (double)cd->f_cav[3 * a + 2] * inv_fix;
-        const double4 r = cd->r[a];
-        W[0] += Fx; W[1] += Fy; W[2] += Fz;
-        W[3] += r.y * Fz - r.z * Fy; W[4] += r.z * Fx - r.x * Fz; W[5] += r.x * Fy - r.y * Fx;
-        const double4 e = cd->e_atom[a];
-        E[0] += e.x; E[1] += e.y; E[2] += e.z;
-        if (!(isfinite(Fx) && isfinite(Fy) && isfinite(Fz))) E[3] = 1.0;
-    }
-    // exclusive suffix over threads: sum of the wrenches of all later chunks
-    double S[6];
-#pragma unroll
-    for (int k = 0; k < 6; ++k) S[k] = W[k];
-#pragma unroll
-    for (int d = 1; d < WAVE; d <<= 1) {
-#pragma unroll
-        for (int k = 0; k < 6; ++k) {
-            const double y = __shfl_down(S[k], d, WAVE);
-            if (lane + d < WAVE) S[k] += y;
-        }
-    }
-    if (lane == 0)
-        for (int k = 0; k < 6; ++k) s_w[w][k] = S[k];
-    __syncthreads();
-    if (tid == 0) {
-        double acc[6] = {0, 0, 0, 0, 0, 0};
-        for (int i = nw - 1; i >= 0; --i)
-            for (int k = 0; k < 6; ++k) {
-                const double t = s_w[i][k];
-                s_w[i][k] = acc[k];
-                acc[k] += t;
-            }
-    }
-    __syncthreads();
-    double X[6];
-#pragma unroll
-    for (int k = 0; k < 6; ++k) {
-        const double nxt = __shfl_down(S[k], 1, WAVE);
-        X[k] = s_w[w][k] + (lane < WAVE - 1 ? nxt : 0.0);
-    }
-    // walk the chunk backwards; at the first atom of link l >= 1 emit tau_{l-1}
-    for (int a = a1 - 1; a >= a0; --a) {
-        const double4 fp = cd->f_pair[a];
-        const double Fx = fp.x + (double)cd->f_cav[3 * a] * inv_fix;
-        const double Fy = fp.y + (double)cd->f_cav[3 * a + 1] * inv_fix;
-        const double Fz = fp.z + (double)cd->f_cav[3 * a + 2] * inv_fix;
-        const double4 r = cd->r[a];
-        X[0] += Fx; X[1] += Fy; X[2] += Fz;
-        X[3] += r.y * Fz - r.z * Fy; X[4] += r.z * Fx - r.x * Fz; X[5] += r.x * Fy - r.y * Fx;
-        const int res = a / APR, slot = a - res * APR;
-        if (slot == 2 || slot == 8) {
-            const int j = 2 * res + (slot == 8 ? 1 : 0);
-            const double4 u = cd->jcur[2 * j], p = cd->jcur[2 * j + 1];
-            // T - p x F, projected on u
-            const double mx = X[3] - (p.y * X[2] - p.z * X[1]);
-            const double my = X[4] - (p.z * X[0] - p.x * X[2]);
-            const double mz = X[5] - (p.x * X[1] - p.y * X[0]);
-            cd->tau[j] = u.x * mx + u.y * my + u.z * mz;
-        }
-    }
-    block_sum<4>(E, s_red);
-    __syncthreads();
-
-    // |tau|_max over free joints
-    double tmax = 0.0;
-    bool tbad = false;
-    for (int j = tid; j < J; j += nt) {
-        const double t = cd->tau[j];
-        if (!isfinite(t)) tbad = true;
-        if (cd->mask[j]) tmax = fmax(tmax, fabs(t));
-    }
-    tmax = block_max(tmax, s_red);
-    const double anybad = block_max(tbad ? 1.0 : 0.0, s_red);
-    if (E[3] > 0.0 || anybad > 0.0) {
-        if (tid == 0) {
-            st->e_elec = E[0]; st->e_vdw = E[1]; st->e_cav = E[2];
-            st->status = -4;
-            st->active = 0;
-        }
-        return;
-    }
-
-    // eq KCM_07 and the angle update, wrapped to (-pi, pi]
-    const double kappa = cd->kappa, s = cd->max_step;
-    double scale;
-    if (cd->step_rule == 1) scale = tmax > 0.0 ? s / tmax : 0.0;
-    else if (cd->step_rule == 2) scale = kappa;
-    else scale = (kappa * tmax > s) ? s / tmax : kappa;
-    double mxd = 0.0;
-    for (int j = tid; j < J; j += nt) {
-        const double d = cd->mask[j] ? scale * cd->tau[j] : 0.0;
-        cd->dtheta[j] = d;
-        mxd = fmax(mxd, fabs(d));
-        double t = cd->theta[j] + d;
-        if (t > PI_D) t -= 2.0 * PI_D;
-        if (t <= -PI_D) t += 2.0 * PI_D;
-        cd->theta[j] = t;
-    }
-    mxd = block_max(mxd, s_red);
-    if (tid == 0) {
-        st->e_elec = E[0]; st->e_vdw = E[1]; st->e_cav = E[2];
-        st->max_tau = tmax;
-        st->max_dtheta = mxd;
-        st->iterations += 1;
-        if (st->nbr_overflow) st->status = -6;
-        if (st->tol > 0.0 && mxd < st->tol) {
-            st->converged = 1;
-            st->active = 0;
-        }
-        if (st->iterations >= st->iter_limit) st->active = 0;
+        cd->e_atom[ai] = make_double4(0.5 * pv[3], 0.5 * pv[4], e_cav, n_exp);
     }
 }
 
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-hipError_t launch_chain_pre(ChainDev *const *table, int n_chains, hipStream_t s)
+hipError_t launch_chain(const Batch &b, int do_post, int do_fk, hipStream_t s)
 {
-    if (n_chains <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_chain_pre, dim3(n_chains), dim3(CHAIN_THREADS), 0, s, table);
+    if (b.n_chains <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_chain, dim3(b.n_chains), dim3(CHAIN_THREADS), 0, s, b, do_post, do_fk);
     return hipGetLastError();
 }
 
-hipError_t launch_force(ChainDev *const *table, const int32_t *atom_off, int n_chains, int total_atoms, int precision,
-                        hipStream_t s)
+hipError_t launch_place(const Batch &b, hipStream_t s)
 {
-    if (n_chains <= 0 || total_atoms <= 0) return hipSuccess;
+    if (b.total_blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_place, dim3(b.total_blocks), dim3(ATOM_BLOCK), 0, s, b);
+    return hipGetLastError();
+}
+
+hipError_t launch_cellscan(const Batch &b, hipStream_t s)
+{
+    if (b.n_chains <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_cellscan, dim3(b.n_chains), dim3(CHAIN_THREADS), 0, s, b);
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter(const Batch &b, hipStream_t s)
+{
+    if (b.total_blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_scatter, dim3(b.total_blocks), dim3(ATOM_BLOCK), 0, s, b);
+    return hipGetLastError();
+}
+
+hipError_t launch_cellsort(const Batch &b, hipStream_t s)
+{
+    if (b.total_blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_cellsort, dim3(b.total_blocks), dim3(ATOM_BLOCK), 0, s, b);
+    return hipGetLastError();
+}
+
+hipError_t launch_force(const Batch &b, int precision, hipStream_t s)
+{
+    if (b.total_atoms <= 0) return hipSuccess;
     if (precision == 1)
-        hipLaunchKernelGGL(k_force<float>, dim3(total_atoms), dim3(FORCE_THREADS), 0, s, table, atom_off, n_chains);
+        hipLaunchKernelGGL(k_force<float>, dim3(b.total_atoms), dim3(FORCE_THREADS), 0, s, b);
     else
-        hipLaunchKernelGGL(k_force<double>, dim3(total_atoms), dim3(FORCE_THREADS), 0, s, table, atom_off, n_chains);
-    return hipGetLastError();
-}
-
-hipError_t launch_chain_post(ChainDev *const *table, int n_chains, hipStream_t s)
-{
-    if (n_chains <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_chain_post, dim3(n_chains), dim3(CHAIN_THREADS), 0, s, table);
+        hipLaunchKernelGGL(k_force<double>, dim3(b.total_atoms), dim3(FORCE_THREADS), 0, s, b);
     return hipGetLastError();
 }
 

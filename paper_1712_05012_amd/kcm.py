@@ -23,7 +23,7 @@ KCM_TERM_ELEC, KCM_TERM_VDW, KCM_TERM_CAV, KCM_TERM_ALL = 1, 2, 4, 7
 
 EXPORTED = ("kcm_default_params", "kcm_chain_bytes", "kcm_build_chain", "kcm_step", "kcm_fold",
             "kcm_get_state", "kcm_get_forces", "kcm_set_theta", "kcm_get_cells", "kcm_chain_info",
-            "kcm_set_timing", "kcm_get_timing", "kcm_chain_free", "kcm_last_error")
+            "kcm_set_timing", "kcm_get_timing", "kcm_chain_free", "kcm_last_error", "kcm_get_atom_terms")
 
 
 class KcmError(RuntimeError):
@@ -82,6 +82,7 @@ def load_library(path: str = LIB_PATH):
     lib.kcm_get_state.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     lib.kcm_get_forces.argtypes = [vp, vp, vp, vp]
     lib.kcm_set_theta.argtypes = [vp, vp, vp]
+    lib.kcm_get_atom_terms.argtypes = [vp, vp, vp, vp, vp, vp]
     lib.kcm_get_cells.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, C.c_int32]
     lib.kcm_chain_info.argtypes = [vp, vp, vp, vp, vp]
     lib.kcm_set_timing.argtypes = [C.c_int]
@@ -227,6 +228,14 @@ def kcm_get_forces(handle, stream=None):
     return fp, fc
 
 
+def kcm_get_atom_terms(handle, stream=None):
+    n, _, _, _ = kcm_chain_info(handle)
+    ee, ev, ec = np.zeros(n), np.zeros(n), np.zeros(n)
+    nx = np.zeros(n, np.int32)
+    _check(load_library().kcm_get_atom_terms(handle, _stream_handle(stream), _p(ee), _p(ev), _p(ec), _p(nx)))
+    return {"e_elec": ee, "e_vdw": ev, "e_cav": ec, "n_exposed": nx}
+
+
 def kcm_set_theta(handle, theta, stream=None):
     th = np.ascontiguousarray(theta, dtype=np.float64)
     _check(load_library().kcm_set_theta(handle, _p(th), _stream_handle(stream)))
@@ -289,6 +298,9 @@ class Chain:
 
     def forces(self, stream=None):
         return kcm_get_forces(self.handle, stream)
+
+    def atom_terms(self, stream=None):
+        return kcm_get_atom_terms(self.handle, stream)
 
     def set_theta(self, theta, stream=None):
         kcm_set_theta(self.handle, theta, stream)
