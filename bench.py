@@ -12,7 +12,8 @@ Roofline of the dominant kernel (the force kernel): algorithmic FP work per
 launch = 40 flops per unordered pair within the cutoff + 9 flops per
 (sample, solvation neighbour) coverage test + 9 flops per (exposed sample,
 neighbour) pair for the three displaced tests, divided by the kernel's mean
-launch time from HIP events recorded on its launch stream.
+launch time from HIP events recorded on its launch stream (on every tenth
+timed iteration, so that the events barely perturb the timeline).
 """
 from __future__ import annotations
 
@@ -27,6 +28,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_TFLOPS = {"mixed": 157.3, "fp64": 78.6}  # MI355X vector FP32 / FP64
+TIMING_EVERY = 10  # HIP events bracket the force kernel on every 10th timed iteration
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "force_kernel_traffic.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_1712_05012_amd", "csrc", "kcm_kernels.hip")
 
@@ -74,13 +76,13 @@ def run_gpu(precision: str, steps: int, warmup: int, m: int):
     kcm.kcm_step([chain], warmup, stream, report=False)
     torch.cuda.synchronize()
     kcm.kcm_get_timing(reset=True)
-    kcm.kcm_set_timing(True)
+    kcm.kcm_set_timing(TIMING_EVERY)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     kcm.kcm_step([chain], steps, stream, report=False)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    kcm.kcm_set_timing(False)
+    kcm.kcm_set_timing(0)
     tm = kcm.kcm_get_timing(reset=True)
     _, reps = kcm.kcm_step([chain], 0, stream, report=True, check=False)
     st = chain.state()
@@ -100,6 +102,92 @@ def run_gpu(precision: str, steps: int, warmup: int, m: int):
         "n_samples": chain.n_samples,
     }
     chain.free()
+    return out
+
+
+def batch_workload(n_chains: int = 256):
+    """256 chains, lengths uniform in [50, 600] residues, per-chain seeds, random dihedrals."""
+    import synth
+
+    T = synth.residue_types()
+    lens = synth.batch_lengths(n_chains, synth.config_seed(3))
+    chains = []
+    for b, m in enumerate(lens):
+        seed = synth.config_seed(3, b)
+        chains.append((synth.sequence(int(m), seed), synth.random_dihedrals(int(m), seed)))
+    return T, chains
+
+
+def run_batch(steps: int, warmup: int, n_chains: int = 256):
+    """Ragged batch in mixed precision: all chains advanced by one graph replay per iteration."""
+    import torch
+
+    from paper_1712_05012_amd import kcm
+
+    T, items = batch_workload(n_chains)
+    p = kcm.kcm_default_params(precision=kcm.KCM_MIXED)
+    chains = [kcm.Chain(seq, T, p, theta0=th) for seq, th in items]
+    atoms = sum(c.n_atoms for c in chains)
+    stream = torch.cuda.current_stream()
+    kcm.kcm_step(chains, warmup, stream, report=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    kcm.kcm_step(chains, steps, stream, report=False)
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t0
+    _, reps = kcm.kcm_step(chains, 0, stream, report=True, check=False)
+    bad = sum(r.status != 0 for r in reps)
+    for c in chains:
+        c.free()
+    return {"chains": len(items), "atoms": atoms, "steps": steps, "ms_per_step": 1e3 * secs / steps,
+            "value": atoms * steps / secs, "failed_chains": int(bad)}
+
+
+def run_per_chain_fp64(steps: int, n_sample: int = 16, n_chains: int = 256):
+    """The plain FP64 path run one chain at a time, on a sample of the batch's chains."""
+    import torch
+
+    from paper_1712_05012_amd import kcm
+
+    T, items = batch_workload(n_chains)
+    p = kcm.kcm_default_params(precision=kcm.KCM_FP64)
+    pick = items[:n_sample]
+    atom_steps, secs = 0, 0.0
+    for seq, th in pick:
+        c = kcm.Chain(seq, T, p, theta0=th)
+        kcm.kcm_step([c], 2, report=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        kcm.kcm_step([c], steps, report=False)
+        torch.cuda.synchronize()
+        secs += time.perf_counter() - t0
+        atom_steps += c.n_atoms * steps
+        c.free()
+    return {"value": atom_steps / secs, "sample": f"{n_sample} of the {n_chains} chains, {steps} iterations each, "
+            "one chain per call"}
+
+
+def run_serving(n_jobs: int, max_iter: int, budget_gib: float):
+    """Poisson arrivals at 50 jobs/s, lognormal lengths; continuous batching by HBM budget."""
+    import synth
+    from paper_1712_05012_amd import kcm
+    from paper_1712_05012_amd.serve import FoldService, Job, KcmEngine
+
+    T = synth.residue_types()
+    seed = synth.config_seed(5)
+    arrivals, lengths = synth.serving_jobs(n_jobs, seed)
+    jobs = []
+    for k, (a, m) in enumerate(zip(arrivals, lengths)):
+        js = seed + 1000 * (k + 1)
+        jobs.append(Job(job_id=k, res_type=synth.sequence(int(m), js), theta0=synth.random_dihedrals(int(m), js),
+                        arrival=float(a), tol=1e-4, max_iter=max_iter))
+    eng = KcmEngine(T, kcm.kcm_default_params(precision=kcm.KCM_MIXED))
+    svc = FoldService(eng, hbm_budget=int(budget_gib * (1 << 30)), max_slots=1024, check_every=20)
+    st = svc.run(jobs)
+    out = st.summary()
+    out.update({"arrival_rate_per_s": 50.0, "max_iter": max_iter, "tol_dtheta": 1e-4,
+                "hbm_budget_gib": budget_gib,
+                "note": "offered load exceeds one GPU's throughput, so latency includes queueing"})
     return out
 
 
@@ -147,6 +235,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-companion", action="store_true", help="skip the other precision's measurement")
+    ap.add_argument("--batch-steps", type=int, default=100, help="iterations of the 256-chain batch (0: skip)")
+    ap.add_argument("--serve-jobs", type=int, default=48, help="jobs of the serving run (0: skip)")
+    ap.add_argument("--serve-max-iter", type=int, default=2000)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="first run a plain device copy of MIB MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -219,6 +310,14 @@ def main():
                        "force_ms": companion["force_ms_mean"],
                        "frac": companion["units"]["flops"] / (companion["force_ms_mean"] * 1e-3) / 1e12
                        / PEAK_TFLOPS[other]}
+    if args.batch_steps > 0:
+        b = run_batch(args.batch_steps, 5)
+        fp64 = run_per_chain_fp64(max(5, args.batch_steps // 10))
+        b["plain_fp64_per_chain"] = fp64
+        b["speedup_vs_plain_fp64_per_chain"] = b["value"] / fp64["value"]
+        line["batched"] = b
+    if args.serve_jobs > 0:
+        line["serving"] = run_serving(args.serve_jobs, args.serve_max_iter, 64.0)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.cpu_seconds, args.residues)
     print(json.dumps(line), flush=True)

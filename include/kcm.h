@@ -164,6 +164,14 @@ kcm_status kcm_get_forces(const kcm_chain *chain, void *hip_stream, double *f_pa
 kcm_status kcm_get_atom_terms(const kcm_chain *chain, void *hip_stream, double *e_elec, double *e_vdw,
                               double *e_cav, int32_t *n_exposed);
 
+/* Per-chain stopping rule applied inside kcm_step: once max|dtheta| of an
+ * iteration is below tol_dtheta (tol_dtheta <= 0: never) or the chain has run
+ * max_iterations iterations since it was built (<= 0: no cap), the chain is
+ * marked converged / finished and later launches skip it.  Its reports then
+ * carry converged = 1 or iterations == max_iterations.  Used by serving loops
+ * that advance many chains with one call (Fig. 5 step 9, per chain). */
+kcm_status kcm_set_limits(kcm_chain *chain, double tol_dtheta, int64_t max_iterations, void *hip_stream);
+
 /* Replace a chain's theta (host array [J]), e.g. to resume from a checkpoint
  * or to re-synchronise with a reference; clears its converged flag. */
 kcm_status kcm_set_theta(kcm_chain *chain, const double *theta, void *hip_stream);
@@ -180,12 +188,20 @@ kcm_status kcm_get_cells(const kcm_chain *chain, void *hip_stream, int32_t *dims
 kcm_status kcm_chain_info(const kcm_chain *chain, int32_t *n_atoms, int32_t *n_joints,
                           int32_t *n_samples, int32_t *precision);
 
-/* Optional per-kernel timing with hipEvents on the launch stream: when on,
- * kcm_step records an event pair around every force-kernel launch.
- * kcm_get_timing returns the summed milliseconds and launch count of the
- * force kernel and of the whole iteration since the last reset (synchronises
- * every stream it recorded on). */
-kcm_status kcm_set_timing(int enable);
+/* Optional per-kernel timing with hipEvents on the launch stream: when
+ * every > 0, kcm_step records an event pair around the force kernel and one
+ * around the whole iteration on every every-th iteration (a sample, so that
+ * the events barely perturb the timeline); every = 0 switches it off.
+ * kcm_get_timing returns the summed milliseconds and sample counts of the
+ * force kernel and of the iteration since the last reset (synchronises every
+ * stream it recorded on). */
+kcm_status kcm_set_timing(int every);
+/* Launch mode of kcm_step: enable != 0 (the default) captures one iteration
+ * of a call's chains as a HIP graph (on a private stream, once per batch
+ * composition) and replays it on hip_stream; enable = 0 launches the kernels
+ * directly.  Both modes give identical results. */
+kcm_status kcm_set_graphs(int enable);
+
 kcm_status kcm_get_timing(double *force_ms, int64_t *force_launches, double *iter_ms,
                           int64_t *iterations, int reset);
 

@@ -152,7 +152,9 @@ std::vector<V3> sample_directions(int n_orb)
 // ---------------------------------------------------------------------------
 struct Layout {
     size_t desc, stats, grid, theta, dtheta, tau, mask, joint0, jcur, xform, r0, r, aparam, g0, qfix;
-    size_t cell_key, cell_count, cell_start, cell_cursor, bbox_acc, s_r, s_p, s_idx, s_cell, f_pair, f_cav, e_atom;
+    size_t cell_key, cell_count, cell_start, cell_cursor, bbox_part, wrench_part, s_r, s_p, s_tmp, s_idx, s_cell;
+    size_t f_pair, f_cav;
+    size_t e_atom;
     size_t q64, q32;
     size_t total;
     int n, J, L, N, cap;
@@ -193,9 +195,12 @@ Layout make_layout(int m, int n_orb)
     l.cell_count = take(4 * cap);
     l.cell_start = take(4 * (cap + 1));
     l.cell_cursor = take(4 * cap);
-    l.bbox_acc = take(8 * 6);
+    const size_t nblk = (n + ATOM_BLOCK - 1) / ATOM_BLOCK;
+    l.bbox_part = take(8 * 6 * nblk);
+    l.wrench_part = take(8 * WPART * nblk);
     l.s_r = take(32 * n);
     l.s_p = take(32 * n);
+    l.s_tmp = take(4 * n);
     l.s_idx = take(4 * n);
     l.s_cell = take(4 * n);
     l.f_pair = take(32 * n);
@@ -237,17 +242,52 @@ struct Table {
     void *dev = nullptr;
     size_t cap = 0;
     Batch batch{};
+    hipGraphExec_t graph = nullptr;  // one iteration, captured for this batch
+    int graph_prec = -1;
 };
 
 std::mutex g_mu;
 std::vector<Table> g_tables;
+int g_graphs = 1;                       // replay the iteration as a captured graph
+std::vector<std::pair<int, hipStream_t>> g_capture_streams;  // per device
+
+hipError_t capture_stream(hipStream_t *out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    for (auto &p : g_capture_streams)
+        if (p.first == dev) {
+            *out = p.second;
+            return hipSuccess;
+        }
+    hipStream_t s = nullptr;
+    e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+    if (e != hipSuccess) return e;
+    g_capture_streams.emplace_back(dev, s);
+    *out = s;
+    return hipSuccess;
+}
+
+hipError_t launch_iteration(const Batch &bt, int prec, hipStream_t stream)
+{
+    hipError_t e;
+    if ((e = launch_chain(bt, 1, 1, stream)) != hipSuccess) return e;
+    if ((e = launch_place(bt, stream)) != hipSuccess) return e;
+    if ((e = launch_cellscan(bt, stream)) != hipSuccess) return e;
+    if ((e = launch_scatter(bt, stream)) != hipSuccess) return e;
+    if ((e = launch_rank(bt, stream)) != hipSuccess) return e;
+    if ((e = launch_force(bt, prec, stream)) != hipSuccess) return e;
+    return launch_wrench(bt, stream);
+}
 
 struct TimedIter {
     hipEvent_t it0, f0, f1, it1;
 };
 std::vector<TimedIter> g_timed;
 std::vector<hipEvent_t> g_event_pool;
-bool g_timing = false;
+int g_timing = 0;
+int64_t g_timing_count = 0;
 double g_force_ms = 0.0, g_iter_ms = 0.0;
 int64_t g_force_n = 0, g_iter_n = 0;
 
@@ -331,6 +371,10 @@ kcm_status ensure_table(kcm_chain *const *chains, int n_chains, hipStream_t stre
         t->batch.total_atoms = (int)total;
         t->batch.total_blocks = (int)blocks;
         t->chains.assign(chains, chains + n_chains);
+        if (t->graph) {
+            HIP_TRY(hipGraphExecDestroy(t->graph));
+            t->graph = nullptr;
+        }
     }
     *out = t;
     return KCM_OK;
@@ -525,9 +569,11 @@ kcm_status kcm_build_chain(const kcm_chain_desc *desc, const kcm_params *params,
     PTR(cell_count, int32_t *);
     PTR(cell_start, int32_t *);
     PTR(cell_cursor, int32_t *);
-    PTR(bbox_acc, unsigned long long *);
+    PTR(bbox_part, double *);
+    PTR(wrench_part, double *);
     PTR(s_r, double4 *);
     PTR(s_p, double4 *);
+    PTR(s_tmp, int32_t *);
     PTR(s_idx, int32_t *);
     PTR(s_cell, int32_t *);
     PTR(f_pair, double4 *);
@@ -587,25 +633,48 @@ kcm_status kcm_step(kcm_chain *const *chains, int n_chains, int n_iter, void *hi
     s = ensure_table(chains, n_chains, stream, &t);
     if (s != KCM_OK) return s;
     const Batch &bt = t->batch;
-    for (int it = 0; it < n_iter; ++it) {
-        TimedIter ti{};
-        if (g_timing) {
-            ti = {pooled_event(), pooled_event(), pooled_event(), pooled_event()};
-            HIP_TRY(hipEventRecord(ti.it0, stream));
+    if (g_graphs && n_iter > 0 && (!t->graph || t->graph_prec != prec)) {
+        if (t->graph) {
+            HIP_TRY(hipGraphExecDestroy(t->graph));
+            t->graph = nullptr;
         }
-        // post phase of the previous iteration (if any) + kinematics and grid of this one
-        HIP_TRY(launch_chain(bt, it > 0 ? 1 : 0, 1, stream));
+        hipStream_t cs = nullptr;
+        HIP_TRY(capture_stream(&cs));
+        hipGraph_t g = nullptr;
+        HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+        hipError_t le = launch_iteration(bt, prec, cs);
+        hipError_t ee = hipStreamEndCapture(cs, &g);
+        if (le != hipSuccess) return fail(KCM_E_DEVICE, std::string("capture: ") + hipGetErrorString(le));
+        if (ee != hipSuccess) return fail(KCM_E_DEVICE, std::string("end capture: ") + hipGetErrorString(ee));
+        hipError_t ie = hipGraphInstantiate(&t->graph, g, nullptr, nullptr, 0);
+        HIP_TRY(hipGraphDestroy(g));
+        if (ie != hipSuccess) {
+            t->graph = nullptr;
+            return fail(KCM_E_DEVICE, std::string("instantiate: ") + hipGetErrorString(ie));
+        }
+        t->graph_prec = prec;
+    }
+    for (int it = 0; it < n_iter; ++it) {
+        const bool timed = g_timing > 0 && (g_timing_count++ % g_timing) == 0;
+        if (!timed) {
+            if (g_graphs) HIP_TRY(hipGraphLaunch(t->graph, stream));
+            else HIP_TRY(launch_iteration(bt, prec, stream));
+            continue;
+        }
+        // a sampled iteration: direct launches bracketed by events
+        TimedIter ti = {pooled_event(), pooled_event(), pooled_event(), pooled_event()};
+        HIP_TRY(hipEventRecord(ti.it0, stream));
+        HIP_TRY(launch_chain(bt, 1, 1, stream));
         HIP_TRY(launch_place(bt, stream));
         HIP_TRY(launch_cellscan(bt, stream));
         HIP_TRY(launch_scatter(bt, stream));
-        HIP_TRY(launch_cellsort(bt, stream));
-        if (g_timing) HIP_TRY(hipEventRecord(ti.f0, stream));
+        HIP_TRY(launch_rank(bt, stream));
+        HIP_TRY(hipEventRecord(ti.f0, stream));
         HIP_TRY(launch_force(bt, prec, stream));
-        if (g_timing) {
-            HIP_TRY(hipEventRecord(ti.f1, stream));
-            HIP_TRY(hipEventRecord(ti.it1, stream));
-            g_timed.push_back(ti);
-        }
+        HIP_TRY(hipEventRecord(ti.f1, stream));
+        HIP_TRY(launch_wrench(bt, stream));
+        HIP_TRY(hipEventRecord(ti.it1, stream));
+        g_timed.push_back(ti);
     }
     if (n_iter > 0) HIP_TRY(launch_chain(bt, 1, 0, stream));  // post phase of the last iteration
     if (!reports) return KCM_OK;
@@ -776,7 +845,18 @@ kcm_status kcm_set_theta(kcm_chain *c, const double *theta, void *hip_stream)
     if ((st = write_field(&c->h.stats->status, 0, s)) != KCM_OK) return st;
     if ((st = write_field(&c->h.stats->nbr_overflow, 0, s)) != KCM_OK) return st;
     if ((st = write_field(&c->h.stats->need_grid, 1, s)) != KCM_OK) return st;
+    if ((st = write_field(&c->h.stats->pending_post, 0, s)) != KCM_OK) return st;
     return write_field(&c->h.stats->active, 1, s);
+}
+
+kcm_status kcm_set_limits(kcm_chain *c, double tol_dtheta, int64_t max_iterations, void *hip_stream)
+{
+    if (!c || !std::isfinite(tol_dtheta)) return fail(KCM_E_INVAL, "null chain or tol not finite");
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    kcm_status st;
+    if ((st = write_field(&c->h.stats->tol, tol_dtheta, s)) != KCM_OK) return st;
+    return write_field(&c->h.stats->iter_limit,
+                       max_iterations > 0 ? max_iterations : std::numeric_limits<int64_t>::max(), s);
 }
 
 kcm_status kcm_get_cells(const kcm_chain *c, void *hip_stream, int32_t *dims, double *cell_size, double *origin,
@@ -798,10 +878,19 @@ kcm_status kcm_get_cells(const kcm_chain *c, void *hip_stream, int32_t *dims, do
     return KCM_OK;
 }
 
-kcm_status kcm_set_timing(int enable)
+kcm_status kcm_set_graphs(int enable)
 {
     std::lock_guard<std::mutex> lock(g_mu);
-    g_timing = enable != 0;
+    g_graphs = enable != 0;
+    return KCM_OK;
+}
+
+kcm_status kcm_set_timing(int every)
+{
+    if (every < 0) return fail(KCM_E_INVAL, "every < 0");
+    std::lock_guard<std::mutex> lock(g_mu);
+    g_timing = every;
+    g_timing_count = 0;
     return KCM_OK;
 }
 
@@ -842,6 +931,10 @@ kcm_status kcm_chain_free(kcm_chain *c)
         for (auto *x : t.chains)
             if (x == c) {
                 t.chains.clear();  // forces a rebuild of this table on next use
+                if (t.graph) {
+                    (void)hipGraphExecDestroy(t.graph);
+                    t.graph = nullptr;
+                }
                 break;
             }
     }

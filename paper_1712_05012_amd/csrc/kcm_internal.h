@@ -14,6 +14,7 @@ constexpr int CHAIN_THREADS = 1024;  // one workgroup per chain: 16 waves
 constexpr int MAX_NBR = 384;         // solvation neighbours of one atom kept in LDS
 constexpr int MAX_REACH = 7;         // cell-stencil half width the force kernel supports
 constexpr double FIX_SCALE = 4294967296.0;  // fixed-point units per kcal/mol/A (2^32)
+constexpr int WPART = 10;            // doubles per wrench partial: F(3), T(3), E(3), flag
 
 // Per-chain scalars the kernels read and write (device memory).
 struct ChainStats {
@@ -27,7 +28,7 @@ struct ChainStats {
     int32_t active;                // 0: the kernels skip this chain
     int32_t nbr_overflow;          // set by the force kernel, folded into status
     int32_t need_grid;             // 1: no bounding box of the current conformation yet
-    int32_t pad;
+    int32_t pending_post;          // 1: forces of an iteration await their post phase
 };
 
 // Cell grid of the current iteration (written by the chain kernel).
@@ -64,9 +65,11 @@ struct ChainDev {
     int32_t *cell_count; // [cap] atoms per cell
     int32_t *cell_start; // [cap+1]
     int32_t *cell_cursor;// [cap]
-    unsigned long long *bbox_acc;  // [6] order-preserving encoded min xyz, max xyz
+    double *bbox_part;   // [blocks][6] per-workgroup min xyz, max xyz of the placed atoms
+    double *wrench_part; // [blocks][WPART] per-workgroup wrench (F, r x F), energies, failure flag
     double4 *s_r;        // [n] positions in cell order
     double4 *s_p;        // [n] parameters in cell order
+    int32_t *s_tmp;      // [n] scatter order (before the stable rank)
     int32_t *s_idx;      // [n] atom of each sorted slot (the cell order)
     int32_t *s_cell;     // [n] cell of each sorted slot
     double4 *f_pair;     // [n] Coulomb + LJ force
@@ -93,13 +96,14 @@ struct Batch {
 
 // Launchers (kcm_kernels.hip).  One iteration is
 //   chain(post of the previous iteration if any, then kinematics + grid),
-//   place, cellscan, scatter, cellsort, force;
+//   place, cellscan, scatter, rank, force, wrench;
 // a call ends with chain(post only).
 hipError_t launch_chain(const Batch &b, int do_post, int do_fk, hipStream_t s);
 hipError_t launch_place(const Batch &b, hipStream_t s);
 hipError_t launch_cellscan(const Batch &b, hipStream_t s);
 hipError_t launch_scatter(const Batch &b, hipStream_t s);
-hipError_t launch_cellsort(const Batch &b, hipStream_t s);
 hipError_t launch_force(const Batch &b, int precision, hipStream_t s);
+hipError_t launch_rank(const Batch &b, hipStream_t s);
+hipError_t launch_wrench(const Batch &b, hipStream_t s);
 
 }  // namespace kcm

@@ -14,6 +14,7 @@
 //               count, bounding box of the new positions.
 //   k_cellscan  one workgroup per chain: cell starts by an exclusive scan.
 //   k_scatter   one thread per atom: counting-sort scatter by cell key.
+//   k_rank      one thread per atom: stable slot inside the cell, gather.
 //   k_cellsort  one thread per cell: restores atom order inside the cell
 //               (the sort is then stable, so everything downstream is
 //               deterministic) and gathers positions/parameters in cell order.
@@ -100,11 +101,11 @@ __device__ __forceinline__ Xf xf_load(const double *p)
 
 // Joint j: right-hand rotation by (theta_j - pi) about the zero-position axis
 // line through p0_j with direction u0_j.
-__device__ __forceinline__ Xf joint_xf(const ChainDev *cd, int j)
+__device__ __forceinline__ Xf joint_xf(const double4 *__restrict__ joint0, const double *__restrict__ theta, int j)
 {
-    const double4 u = cd->joint0[2 * j], p = cd->joint0[2 * j + 1];
+    const double4 u = joint0[2 * j], p = joint0[2 * j + 1];
     double s, c;
-    sincos(cd->theta[j] - PI_D, &s, &c);
+    sincos(theta[j] - PI_D, &s, &c);
     const double k = 1.0 - c;
     Xf x;
     x.r[0] = c + u.x * u.x * k;       x.r[1] = u.x * u.y * k - u.z * s; x.r[2] = u.x * u.z * k + u.y * s;
@@ -217,18 +218,6 @@ __device__ __forceinline__ int find_block_owner(const int32_t *off, int n, int b
     return lo;
 }
 
-// order-preserving map of doubles to unsigned 64-bit integers (for atomic min/max)
-__device__ __forceinline__ unsigned long long enc_d(double x)
-{
-    const unsigned long long u = (unsigned long long)__double_as_longlong(x);
-    return (u >> 63) ? ~u : (u | 0x8000000000000000ull);
-}
-__device__ __forceinline__ double dec_d(unsigned long long e)
-{
-    const unsigned long long u = (e >> 63) ? (e & 0x7FFFFFFFFFFFFFFFull) : ~e;
-    return __longlong_as_double((long long)u);
-}
-
 __device__ __forceinline__ double4 place_atom(const ChainDev *cd, int a)
 {
     const double *L = cd->xform + 12 * link_of_atom(a);
@@ -257,87 +246,88 @@ constexpr double GRID_MARGIN = 2.0;  // A added around the previous bounding box
 // ---------------------------------------------------------------------------
 // k_chain: post phase of the previous iteration, then kinematics and grid
 // ---------------------------------------------------------------------------
-__device__ void post_phase(ChainDev *cd, int *s_flag, double *s_red, double (*s_w)[6])
+constexpr int FK_REG = 2;  // joints per thread kept in registers (J <= FK_REG * blockDim)
+
+// Post phase of the previous iteration for this thread's joints [j0, j1).
+// th[] holds their angles on entry (when the chunk fits FK_REG) and the
+// updated angles on exit.
+__device__ void post_phase(const ChainDev *cd, int j0, int j1, double (&th)[FK_REG], bool in_reg, int *s_flag,
+                           double *s_red, double (*s_w)[6])
 {
     ChainStats *st = cd->stats;
-    const int J = cd->n_joints, n = cd->n_atoms;
+    const int n = cd->n_atoms;
+    const int nblk = (n + ATOM_BLOCK - 1) / ATOM_BLOCK;
     const int tid = threadIdx.x, nt = blockDim.x, lane = tid & (WAVE - 1), w = tid / WAVE, nw = nt / WAVE;
-    const double inv_fix = 1.0 / FIX_SCALE;
+    double *__restrict__ part = cd->wrench_part;
+    double *__restrict__ tau = cd->tau;
+    double *__restrict__ theta = cd->theta;
+    double *__restrict__ dtheta = cd->dtheta;
+    const uint8_t *__restrict__ mask = cd->mask;
+    const double4 *__restrict__ jcur = cd->jcur;
 
-    const int chunk = (n + nt - 1) / nt;
-    const int a0 = min(n, tid * chunk), a1 = min(n, a0 + chunk);
-    double W[6] = {0, 0, 0, 0, 0, 0};
+    // energies and the failure flag: plain sums of the per-workgroup partials
     double E[4] = {0, 0, 0, 0};
-    for (int a = a0; a < a1; ++a) {
-        const double4 fp = cd->f_pair[a];
-        const double Fx = fp.x + (double)cd->f_cav[3 * a] * inv_fix;
-        const double Fy = fp.y + (double)cd->f_cav[3 * a + 1] * inv_fix;
-        const double Fz = fp.z + (double)cd->f_cav[3 * a + 2] * inv_fix;
-        const double4 r = cd->r[a];
-        W[0] += Fx; W[1] += Fy; W[2] += Fz;
-        W[3] += r.y * Fz - r.z * Fy; W[4] += r.z * Fx - r.x * Fz; W[5] += r.x * Fy - r.y * Fx;
-        const double4 e = cd->e_atom[a];
-        E[0] += e.x; E[1] += e.y; E[2] += e.z;
-        if (!(isfinite(Fx) && isfinite(Fy) && isfinite(Fz))) E[3] = 1.0;
-    }
-    // exclusive suffix over threads: the wrench of every later chunk
-    double S[6];
-#pragma unroll
-    for (int k = 0; k < 6; ++k) S[k] = W[k];
-#pragma unroll
-    for (int d = 1; d < WAVE; d <<= 1) {
-#pragma unroll
-        for (int k = 0; k < 6; ++k) {
-            const double y = __shfl_down(S[k], d, WAVE);
-            if (lane + d < WAVE) S[k] += y;
-        }
-    }
-    if (lane == 0)
-        for (int k = 0; k < 6; ++k) s_w[w][k] = S[k];
-    __syncthreads();
-    if (tid == 0) {
-        double acc[6] = {0, 0, 0, 0, 0, 0};
-        for (int i = nw - 1; i >= 0; --i)
-            for (int k = 0; k < 6; ++k) {
-                const double t = s_w[i][k];
-                s_w[i][k] = acc[k];
-                acc[k] += t;
-            }
-    }
-    __syncthreads();
-    double X[6];
-#pragma unroll
-    for (int k = 0; k < 6; ++k) {
-        const double nxt = __shfl_down(S[k], 1, WAVE);
-        X[k] = s_w[w][k] + (lane < WAVE - 1 ? nxt : 0.0);
-    }
-    // walk the chunk backwards; at the first atom of link l >= 1 emit tau_{l-1}
-    for (int a = a1 - 1; a >= a0; --a) {
-        const double4 fp = cd->f_pair[a];
-        const double Fx = fp.x + (double)cd->f_cav[3 * a] * inv_fix;
-        const double Fy = fp.y + (double)cd->f_cav[3 * a + 1] * inv_fix;
-        const double Fz = fp.z + (double)cd->f_cav[3 * a + 2] * inv_fix;
-        const double4 r = cd->r[a];
-        X[0] += Fx; X[1] += Fy; X[2] += Fz;
-        X[3] += r.y * Fz - r.z * Fy; X[4] += r.z * Fx - r.x * Fz; X[5] += r.x * Fy - r.y * Fx;
-        const int res = a / APR, slot = a - res * APR;
-        if (slot == 2 || slot == 8) {
-            const int j = 2 * res + (slot == 8 ? 1 : 0);
-            const double4 u = cd->jcur[2 * j], p = cd->jcur[2 * j + 1];
-            const double mx = X[3] - (p.y * X[2] - p.z * X[1]);
-            const double my = X[4] - (p.z * X[0] - p.x * X[2]);
-            const double mz = X[5] - (p.x * X[1] - p.y * X[0]);
-            cd->tau[j] = u.x * mx + u.y * my + u.z * mz;
-        }
+    for (int b = tid; b < nblk; b += nt) {
+        E[0] += part[WPART * b + 6];
+        E[1] += part[WPART * b + 7];
+        E[2] += part[WPART * b + 8];
+        E[3] += part[WPART * b + 9];
     }
     block_sum<4>(E, s_red);
 
+    // exclusive suffix over workgroups, in place: part[b][0..5] becomes the
+    // wrench of every atom after workgroup b (processed from the last chunk)
+    double carry[6] = {0, 0, 0, 0, 0, 0};
+    for (int c0 = ((nblk - 1) / nt) * nt; c0 >= 0; c0 -= nt) {
+        const int b = c0 + tid;
+        double v[6], S[6];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) v[k] = (b < nblk) ? part[WPART * b + k] : 0.0;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) S[k] = v[k];
+#pragma unroll
+        for (int d = 1; d < WAVE; d <<= 1) {
+#pragma unroll
+            for (int k = 0; k < 6; ++k) {
+                const double y = __shfl_down(S[k], d, WAVE);
+                if (lane + d < WAVE) S[k] += y;
+            }
+        }
+        if (lane == 0)
+            for (int k = 0; k < 6; ++k) s_w[w][k] = S[k];
+        __syncthreads();
+        double later[6], tot[6];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            double t = 0.0, u = 0.0;
+            for (int i = 0; i < nw; ++i) {
+                u += s_w[i][k];
+                if (i > w) t += s_w[i][k];
+            }
+            later[k] = t;
+            tot[k] = u;
+        }
+        if (b < nblk)
+            for (int k = 0; k < 6; ++k) part[WPART * b + k] = carry[k] + later[k] + (S[k] - v[k]);
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < 6; ++k) carry[k] += tot[k];
+    }
+
+    // tau_j = (workgroup-local part from k_wrench) + u_j . (T_later - p_j x F_later)
     double tmax = 0.0;
     bool tbad = false;
-    for (int j = tid; j < J; j += nt) {
-        const double t = cd->tau[j];
+    for (int j = j0; j < j1; ++j) {
+        const int first = APR * (j >> 1) + ((j & 1) ? 8 : 2);  // first atom of link j+1
+        const double *S = part + WPART * (first / ATOM_BLOCK);
+        const double4 u = jcur[2 * j], p = jcur[2 * j + 1];
+        const double mx = S[3] - (p.y * S[2] - p.z * S[1]);
+        const double my = S[4] - (p.z * S[0] - p.x * S[2]);
+        const double mz = S[5] - (p.x * S[1] - p.y * S[0]);
+        const double t = tau[j] + (u.x * mx + u.y * my + u.z * mz);
+        tau[j] = t;
         if (!isfinite(t)) tbad = true;
-        if (cd->mask[j]) tmax = fmax(tmax, fabs(t));
+        if (mask[j]) tmax = fmax(tmax, fabs(t));
     }
     tmax = block_max(tmax, s_red);
     const double anybad = block_max(tbad ? 1.0 : 0.0, s_red);
@@ -357,14 +347,29 @@ __device__ void post_phase(ChainDev *cd, int *s_flag, double *s_red, double (*s_
     else if (cd->step_rule == 2) scale = kappa;
     else scale = (kappa * tmax > s) ? s / tmax : kappa;
     double mxd = 0.0;
-    for (int j = tid; j < J; j += nt) {
-        const double d = cd->mask[j] ? scale * cd->tau[j] : 0.0;
-        cd->dtheta[j] = d;
+#pragma unroll
+    for (int i = 0; i < FK_REG; ++i) {
+        const int j = j0 + i;
+        if (!in_reg || j >= j1) continue;
+        const double d = mask[j] ? scale * tau[j] : 0.0;
+        dtheta[j] = d;
         mxd = fmax(mxd, fabs(d));
-        double t = cd->theta[j] + d;
+        double t = th[i] + d;
         if (t > PI_D) t -= 2.0 * PI_D;
         if (t <= -PI_D) t += 2.0 * PI_D;
-        cd->theta[j] = t;
+        th[i] = t;
+        theta[j] = t;
+    }
+    if (!in_reg) {
+        for (int j = j0; j < j1; ++j) {
+            const double d = mask[j] ? scale * tau[j] : 0.0;
+            dtheta[j] = d;
+            mxd = fmax(mxd, fabs(d));
+            double t = theta[j] + d;
+            if (t > PI_D) t -= 2.0 * PI_D;
+            if (t <= -PI_D) t += 2.0 * PI_D;
+            theta[j] = t;
+        }
     }
     mxd = block_max(mxd, s_red);
     if (tid == 0) {
@@ -383,14 +388,58 @@ __device__ void post_phase(ChainDev *cd, int *s_flag, double *s_red, double (*s_
     __syncthreads();
 }
 
-__device__ void fk_phase(ChainDev *cd, double (*s_x)[12])
+// Writes the link transform G_{j+1} and the current axis (u_j, p_j) of joint j.
+__device__ __forceinline__ void fk_emit(const Xf &G, int j, const double4 *__restrict__ joint0, double *__restrict__ xform,
+                                        double4 *__restrict__ jcur)
 {
-    const int J = cd->n_joints;
+    xf_store(xform + 12 * (j + 1), G);
+    const double4 u0 = joint0[2 * j], p0 = joint0[2 * j + 1];
+    double4 u, p;
+    u.x = G.r[0] * u0.x + G.r[1] * u0.y + G.r[2] * u0.z;
+    u.y = G.r[3] * u0.x + G.r[4] * u0.y + G.r[5] * u0.z;
+    u.z = G.r[6] * u0.x + G.r[7] * u0.y + G.r[8] * u0.z;
+    u.w = 0.0;
+    p.x = G.r[0] * p0.x + G.r[1] * p0.y + G.r[2] * p0.z + G.t[0];
+    p.y = G.r[3] * p0.x + G.r[4] * p0.y + G.r[5] * p0.z + G.t[1];
+    p.z = G.r[6] * p0.x + G.r[7] * p0.y + G.r[8] * p0.z + G.t[2];
+    p.w = 0.0;
+    jcur[2 * j] = u;
+    jcur[2 * j + 1] = p;
+}
+
+// Rodrigues rotation about unit u by angle (th - pi) and the translation that
+// keeps the axis point p fixed.
+__device__ __forceinline__ Xf joint_xf_of(const double4 &u, const double4 &p, double th)
+{
+    double s, c;
+    sincos(th - PI_D, &s, &c);
+    const double k = 1.0 - c;
+    Xf x;
+    x.r[0] = c + u.x * u.x * k;       x.r[1] = u.x * u.y * k - u.z * s; x.r[2] = u.x * u.z * k + u.y * s;
+    x.r[3] = u.y * u.x * k + u.z * s; x.r[4] = c + u.y * u.y * k;       x.r[5] = u.y * u.z * k - u.x * s;
+    x.r[6] = u.z * u.x * k - u.y * s; x.r[7] = u.z * u.y * k + u.x * s; x.r[8] = c + u.z * u.z * k;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) x.t[i] = ((&p.x)[i]) - (x.r[3 * i] * p.x + x.r[3 * i + 1] * p.y + x.r[3 * i + 2] * p.z);
+    return x;
+}
+
+// Ordered scan G_j = T_0 o T_1 o ... o T_j over the block for this thread's
+// joints [j0, j1); th[] holds their angles when in_reg.  s_x: [16][12].
+__device__ void fk_phase(const ChainDev *cd, int j0, int j1, const double (&th)[FK_REG], bool in_reg, double (*s_x)[12])
+{
+    const double4 *__restrict__ joint0 = cd->joint0;
+    const double *__restrict__ theta = cd->theta;
+    double *__restrict__ xform = cd->xform;
+    double4 *__restrict__ jcur = cd->jcur;
     const int tid = threadIdx.x, nt = blockDim.x, lane = tid & (WAVE - 1), w = tid / WAVE, nw = nt / WAVE;
-    const int chunk = (J + nt - 1) / nt;
-    const int j0 = min(J, tid * chunk), j1 = min(J, j0 + chunk);
     Xf x = xf_identity();
-    for (int j = j0; j < j1; ++j) x = xf_mul(x, joint_xf(cd, j));
+    if (in_reg) {
+#pragma unroll
+        for (int i = 0; i < FK_REG; ++i)
+            if (j0 + i < j1) x = xf_mul(x, joint_xf_of(joint0[2 * (j0 + i)], joint0[2 * (j0 + i) + 1], th[i]));
+    } else {
+        for (int j = j0; j < j1; ++j) x = xf_mul(x, joint_xf(joint0, theta, j));
+    }
 #pragma unroll
     for (int d = 1; d < WAVE; d <<= 1) {
         Xf y = xf_shfl_up(x, d);
@@ -398,41 +447,42 @@ __device__ void fk_phase(ChainDev *cd, double (*s_x)[12])
     }
     if (lane == WAVE - 1) xf_store(s_x[w], x);
     __syncthreads();
-    if (tid == 0) {
-        Xf acc = xf_identity();
-        for (int i = 0; i < nw; ++i) {
-            Xf tmp = xf_load(s_x[i]);
-            xf_store(s_x[i], acc);
-            acc = xf_mul(acc, tmp);
+    if (w == 0) {
+        // ordered scan of the wave totals inside wave 0
+        Xf v = lane < nw ? xf_load(s_x[lane]) : xf_identity();
+#pragma unroll
+        for (int d = 1; d < CHAIN_THREADS / WAVE; d <<= 1) {
+            Xf y = xf_shfl_up(v, d);
+            if (lane >= d) v = xf_mul(y, v);
         }
+        Xf e = xf_shfl_up(v, 1);
+        if (lane == 0) e = xf_identity();
+        if (lane < nw) xf_store(s_x[lane], e);
     }
     __syncthreads();
     Xf ex = xf_shfl_up(x, 1);
     if (lane == 0) ex = xf_identity();
     Xf G = xf_mul(xf_load(s_x[w]), ex);
-    for (int j = j0; j < j1; ++j) {
-        G = xf_mul(G, joint_xf(cd, j));
-        xf_store(cd->xform + 12 * (j + 1), G);
-        const double4 u0 = cd->joint0[2 * j], p0 = cd->joint0[2 * j + 1];
-        double4 u, p;
-        u.x = G.r[0] * u0.x + G.r[1] * u0.y + G.r[2] * u0.z;
-        u.y = G.r[3] * u0.x + G.r[4] * u0.y + G.r[5] * u0.z;
-        u.z = G.r[6] * u0.x + G.r[7] * u0.y + G.r[8] * u0.z;
-        u.w = 0.0;
-        p.x = G.r[0] * p0.x + G.r[1] * p0.y + G.r[2] * p0.z + G.t[0];
-        p.y = G.r[3] * p0.x + G.r[4] * p0.y + G.r[5] * p0.z + G.t[1];
-        p.z = G.r[6] * p0.x + G.r[7] * p0.y + G.r[8] * p0.z + G.t[2];
-        p.w = 0.0;
-        cd->jcur[2 * j] = u;
-        cd->jcur[2 * j + 1] = p;
+    if (in_reg) {
+#pragma unroll
+        for (int i = 0; i < FK_REG; ++i)
+            if (j0 + i < j1) {
+                G = xf_mul(G, joint_xf_of(joint0[2 * (j0 + i)], joint0[2 * (j0 + i) + 1], th[i]));
+                fk_emit(G, j0 + i, joint0, xform, jcur);
+            }
+    } else {
+        for (int j = j0; j < j1; ++j) {
+            G = xf_mul(G, joint_xf(joint0, theta, j));
+            fk_emit(G, j, joint0, xform, jcur);
+        }
     }
-    if (tid == 0) xf_store(cd->xform, xf_identity());
+    if (tid == 0) xf_store(xform, xf_identity());
     __syncthreads();
 }
 
 __global__ __launch_bounds__(CHAIN_THREADS) void k_chain(Batch bt, int do_post, int do_fk)
 {
-    ChainDev *cd = bt.table[blockIdx.x];
+    const ChainDev *cd = bt.table[blockIdx.x];
     ChainStats *st = cd->stats;
     if (!st->active) return;
     __shared__ double s_x[CHAIN_THREADS / WAVE][12];
@@ -442,10 +492,20 @@ __global__ __launch_bounds__(CHAIN_THREADS) void k_chain(Batch bt, int do_post, 
     __shared__ double s_bb[6];
     const int tid = threadIdx.x, nt = blockDim.x, lane = tid & (WAVE - 1), w = tid / WAVE, nw = nt / WAVE;
     if (tid == 0) s_flag = 1;
+    const int J = cd->n_joints;
+    const int chunk = (J + nt - 1) / nt;
+    const int j0 = min(J, tid * chunk), j1 = min(J, j0 + chunk);
+    const bool in_reg = chunk <= FK_REG;
+    double th[FK_REG];
+#pragma unroll
+    for (int i = 0; i < FK_REG; ++i) th[i] = (in_reg && j0 + i < j1) ? cd->theta[j0 + i] : 0.0;
     __syncthreads();
-    if (do_post) post_phase(cd, &s_flag, s_red, s_w);
+    if (do_post && st->pending_post) {
+        post_phase(cd, j0, j1, th, in_reg, &s_flag, s_red, s_w);
+        if (tid == 0) st->pending_post = 0;
+    }
     if (!do_fk || !s_flag) return;
-    fk_phase(cd, s_x);
+    fk_phase(cd, j0, j1, th, in_reg, s_x);
 
     // bounding box that sizes this iteration's grid
     const int n = cd->n_atoms;
@@ -476,8 +536,27 @@ __global__ __launch_bounds__(CHAIN_THREADS) void k_chain(Batch bt, int do_post, 
             if (!s_flag) s_bb[0] = NAN;
             st->need_grid = 0;
         }
-    } else if (tid == 0) {
-        for (int k = 0; k < 6; ++k) s_bb[k] = dec_d(cd->bbox_acc[k]);
+    } else {
+        const int nblk = (n + ATOM_BLOCK - 1) / ATOM_BLOCK;
+        double lo[3] = {DBL_MAX, DBL_MAX, DBL_MAX}, hi[3] = {-DBL_MAX, -DBL_MAX, -DBL_MAX};
+        for (int b = tid; b < nblk; b += nt)
+            for (int k = 0; k < 3; ++k) {
+                lo[k] = fmin(lo[k], cd->bbox_part[6 * b + k]);
+                hi[k] = fmax(hi[k], cd->bbox_part[6 * b + 3 + k]);
+            }
+#pragma unroll
+        for (int k = 0; k < 3; ++k) { lo[k] = wave_min(lo[k]); hi[k] = wave_max(hi[k]); }
+        if (lane == 0)
+            for (int k = 0; k < 3; ++k) { s_red[w * 6 + k] = lo[k]; s_red[w * 6 + 3 + k] = hi[k]; }
+        __syncthreads();
+        if (tid == 0) {
+            for (int k = 0; k < 3; ++k) { s_bb[k] = DBL_MAX; s_bb[3 + k] = -DBL_MAX; }
+            for (int i = 0; i < nw; ++i)
+                for (int k = 0; k < 3; ++k) {
+                    s_bb[k] = fmin(s_bb[k], s_red[i * 6 + k]);
+                    s_bb[3 + k] = fmax(s_bb[3 + k], s_red[i * 6 + 3 + k]);
+                }
+        }
     }
     __syncthreads();
 
@@ -511,10 +590,6 @@ __global__ __launch_bounds__(CHAIN_THREADS) void k_chain(Batch bt, int do_post, 
             st->status = -4;
             st->active = 0;
         }
-        for (int k = 0; k < 3; ++k) {
-            cd->bbox_acc[k] = enc_d(DBL_MAX);
-            cd->bbox_acc[3 + k] = enc_d(-DBL_MAX);
-        }
     }
     __syncthreads();
     const int nc = s_flag;
@@ -545,95 +620,121 @@ __global__ __launch_bounds__(ATOM_BLOCK) void k_place(Batch bt)
         lo[0] = r.x; lo[1] = r.y; lo[2] = r.z;
         hi[0] = r.x; hi[1] = r.y; hi[2] = r.z;
     }
+    __shared__ double s_bb[ATOM_BLOCK / WAVE][6];
+    const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
 #pragma unroll
     for (int k = 0; k < 3; ++k) { lo[k] = wave_min(lo[k]); hi[k] = wave_max(hi[k]); }
-    if ((threadIdx.x & (WAVE - 1)) == 0 && lo[0] <= hi[0]) {
-        for (int k = 0; k < 3; ++k) {
-            atomicMin(&cd->bbox_acc[k], enc_d(lo[k]));
-            atomicMax(&cd->bbox_acc[3 + k], enc_d(hi[k]));
-        }
+    if (lane == 0)
+        for (int k = 0; k < 3; ++k) { s_bb[w][k] = lo[k]; s_bb[w][3 + k] = hi[k]; }
+    __syncthreads();
+    if (threadIdx.x < 6) {
+        const int k = threadIdx.x;
+        double v = s_bb[0][k];
+        for (int i = 1; i < ATOM_BLOCK / WAVE; ++i) v = (k < 3) ? fmin(v, s_bb[i][k]) : fmax(v, s_bb[i][k]);
+        cd->bbox_part[6 * (blockIdx.x - bt.blk_off[c]) + k] = v;
     }
 }
 
 // ---------------------------------------------------------------------------
-// k_cellscan: cell_start = exclusive scan of the counts
+// k_cellscan: cell_start = exclusive scan of the counts (LDS chunks, carry)
 // ---------------------------------------------------------------------------
+constexpr int SCAN_CHUNK = 16384;
+
 __global__ __launch_bounds__(CHAIN_THREADS) void k_cellscan(Batch bt)
 {
-    ChainDev *cd = bt.table[blockIdx.x];
+    const ChainDev *cd = bt.table[blockIdx.x];
     if (!cd->stats->active) return;
+    __shared__ int s_cnt[SCAN_CHUNK];
     __shared__ int s_int[CHAIN_THREADS / WAVE];
     const int nc = cd->grid->n_cells;
+    const int *__restrict__ count = cd->cell_count;
+    int *__restrict__ start = cd->cell_start;
+    int *__restrict__ cursor = cd->cell_cursor;
     const int tid = threadIdx.x, nt = blockDim.x;
-    const int cch = (nc + nt - 1) / nt;
-    const int c0 = min(nc, tid * cch), c1 = min(nc, c0 + cch);
-    int loc = 0;
-    for (int c = c0; c < c1; ++c) loc += cd->cell_count[c];
-    int total = 0;
-    int run = block_excl_scan(loc, s_int, &total);
-    for (int c = c0; c < c1; ++c) {
-        const int k = cd->cell_count[c];
-        cd->cell_start[c] = run;
-        cd->cell_cursor[c] = 0;
-        run += k;
+    constexpr int PER = SCAN_CHUNK / CHAIN_THREADS;
+    int carry = 0;
+    for (int c0 = 0; c0 < nc; c0 += SCAN_CHUNK) {
+        const int m = min(SCAN_CHUNK, nc - c0);
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int i = k * nt + tid;
+            s_cnt[i] = i < m ? count[c0 + i] : 0;
+        }
+        __syncthreads();
+        int loc = 0;
+#pragma unroll
+        for (int k = 0; k < PER; ++k) loc += s_cnt[tid * PER + k];
+        int total = 0;
+        int run = carry + block_excl_scan(loc, s_int, &total);
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int v = s_cnt[tid * PER + k];
+            s_cnt[tid * PER + k] = run;
+            run += v;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int i = k * nt + tid;
+            if (i < m) {
+                start[c0 + i] = s_cnt[i];
+                cursor[c0 + i] = 0;
+            }
+        }
+        carry += total;
+        __syncthreads();
     }
-    if (tid == 0) cd->cell_start[nc] = total;
+    if (tid == 0) start[nc] = carry;
 }
 
 // ---------------------------------------------------------------------------
-// k_scatter: counting-sort scatter (order inside a cell fixed by k_cellsort)
+// k_scatter: counting-sort scatter by cell key (slot order inside a cell left
+// to the atomics), then k_rank: each atom takes as its slot the number of
+// atoms of its cell with a smaller index, so the final cell order is stable
+// and everything downstream is deterministic; it gathers positions and
+// parameters into that order.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(ATOM_BLOCK) void k_scatter(Batch bt)
 {
     const int c = find_block_owner(bt.blk_off, bt.n_chains, blockIdx.x);
-    ChainDev *cd = bt.table[c];
+    const ChainDev *cd = bt.table[c];
     if (!cd->stats->active) return;
     const int a = (blockIdx.x - bt.blk_off[c]) * ATOM_BLOCK + threadIdx.x;
     if (a >= cd->n_atoms) return;
     const int key = cd->cell_key[a];
-    const int pos = cd->cell_start[key] + atomicAdd(&cd->cell_cursor[key], 1);
-    cd->s_idx[pos] = a;
+    cd->s_tmp[cd->cell_start[key] + atomicAdd(&cd->cell_cursor[key], 1)] = a;
 }
 
-// ---------------------------------------------------------------------------
-// k_cellsort: atom order inside each cell, then gather in cell order
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(ATOM_BLOCK) void k_cellsort(Batch bt)
+__global__ __launch_bounds__(ATOM_BLOCK) void k_rank(Batch bt)
 {
     const int c = find_block_owner(bt.blk_off, bt.n_chains, blockIdx.x);
-    ChainDev *cd = bt.table[c];
+    const ChainDev *cd = bt.table[c];
     if (!cd->stats->active) return;
-    const int nblk = bt.blk_off[c + 1] - bt.blk_off[c];
-    const int nc = cd->grid->n_cells;
-    for (int cell = (blockIdx.x - bt.blk_off[c]) * ATOM_BLOCK + threadIdx.x; cell < nc; cell += nblk * ATOM_BLOCK) {
-        const int b = cd->cell_start[cell], e = cd->cell_start[cell + 1];
-        if (b == e) continue;
-        int *o = cd->s_idx;
-        for (int i = b + 1; i < e; ++i) {
-            const int v = o[i];
-            int k = i - 1;
-            while (k >= b && o[k] > v) {
-                o[k + 1] = o[k];
-                --k;
-            }
-            o[k + 1] = v;
-        }
-        for (int s = b; s < e; ++s) {
-            const int a = o[s];
-            cd->s_r[s] = cd->r[a];
-            cd->s_p[s] = cd->aparam[a];
-            cd->s_cell[s] = cell;
-        }
-    }
+    const int a = (blockIdx.x - bt.blk_off[c]) * ATOM_BLOCK + threadIdx.x;
+    if (a >= cd->n_atoms) return;
+    const int key = cd->cell_key[a];
+    const double4 r = cd->r[a];
+    const double4 p = cd->aparam[a];
+    const int b = cd->cell_start[key], e = cd->cell_start[key + 1];
+    const int *__restrict__ tmp = cd->s_tmp;
+    int rank = 0;
+    for (int s = b; s < e; ++s) rank += tmp[s] < a ? 1 : 0;
+    const int pos = b + rank;
+    cd->s_idx[pos] = a;
+    cd->s_cell[pos] = key;
+    cd->s_r[pos] = r;
+    cd->s_p[pos] = p;
 }
 
 // ---------------------------------------------------------------------------
 // k_force: Coulomb + LJ + SASA enumeration, one workgroup per atom
 // ---------------------------------------------------------------------------
+// A solvation neighbour j of atom i: offset a = r_j - r_i and the threshold c0 =
+// (R_i^2 + |a|^2 - R_j^2) / (2 R_i): sample q_k = r_i + R_i Q_k is covered by j iff
+// Q_k . a >= c0 (the same test as ||q_k - r_j|| <= R_j).
 template <typename Real>
 struct NbrEntry {
-    Real ax, ay, az, c0;   // offset a = r_j - r_i and the covering threshold
-    Real cx, cy, cz, pad;  // thresholds of the three displaced copies of j
+    Real ax, ay, az, c0;
 };
 
 // FP64 decision in absolute coordinates: is sample k of atom i covered by the
@@ -804,12 +905,9 @@ __global__ __launch_bounds__(FORCE_THREADS) void k_force(Batch bt)
             const int slot = atomicAdd(&s_nn, 1);
             if (slot < MAX_NBR) {
                 const double Rj = pj.w;
-                const double c0 = (roff_i * roff_i + d2 - Rj * Rj) / (2.0 * roff_i);
-                const double k1 = dr / roff_i, k0 = c0 + dr * dr / (2.0 * roff_i);
                 NbrEntry<Real> e;
-                e.ax = (Real)ddx; e.ay = (Real)ddy; e.az = (Real)ddz; e.c0 = (Real)c0;
-                e.cx = (Real)(k0 + k1 * ddx); e.cy = (Real)(k0 + k1 * ddy); e.cz = (Real)(k0 + k1 * ddz);
-                e.pad = (Real)0;
+                e.ax = (Real)ddx; e.ay = (Real)ddy; e.az = (Real)ddz;
+                e.c0 = (Real)((roff_i * roff_i + d2 - Rj * Rj) / (2.0 * roff_i));
                 s_nbr[slot] = e;
                 s_nbr_j[slot] = sj;
             }
@@ -827,27 +925,30 @@ __global__ __launch_bounds__(FORCE_THREADS) void k_force(Batch bt)
         if (nn_all > MAX_NBR && tid == 0) cd->stats->nbr_overflow = 1;
         const int N = cd->n_samples;
         const Real drr = (Real)dr;
+        // displaced copy of j along e_s covers the sample iff
+        //   dot + dr Q_s >= c0 + dr^2/(2 R_i) + (dr/R_i) a_s
+        const Real kq = (Real)(dr * dr / (2.0 * roff_i)), k1 = (Real)(dr / roff_i);
         int ncov = 0;
-        for (int k0 = 0; k0 < N; k0 += nt) {
-            if (k0 > 0) {
+        for (int kb = 0; kb < N; kb += nt) {
+            if (kb > 0) {
                 if (tid == 0) s_nexp = 0;
                 __syncthreads();
             }
-            const int k = k0 + tid;
+            const int k = kb + tid;
             if (k < N) {
                 Real Qx, Qy, Qz;
                 load_q<Real>(cd, k, Qx, Qy, Qz);
                 // step 1: acc = 65536 * (covering neighbours) + (sum of their slots), so
                 // acc >> 16 == 1 leaves the single overlapper in the low bits
                 int acc = 0;
-                bool amb = false;
+                Real amin = (Real)1e30;
                 for (int u = 0; u < nn; ++u) {
                     const NbrEntry<Real> e = s_nbr[u];
-                    const Real t = Qx * e.ax + Qy * e.ay + Qz * e.az - e.c0;
+                    const Real t = fma(Qz, e.az, fma(Qy, e.ay, fma(Qx, e.ax, -e.c0)));
                     acc += (t >= (Real)0) ? (65536 + u) : 0;
-                    if (MIXED) amb = amb || (fabsf((float)t) <= MIXED_BAND);
+                    if (MIXED) amin = fmin(amin, fabs(t));
                 }
-                if (MIXED && amb) {
+                if (MIXED && amin <= (Real)MIXED_BAND) {
                     acc = 0;
                     for (int u = 0; u < nn; ++u)
                         if (cover_exact(cd, ri, roff_i, k, s_nbr_j[u], -1)) acc += 65536 + u;
@@ -859,10 +960,10 @@ __global__ __launch_bounds__(FORCE_THREADS) void k_force(Batch bt)
                     // critically overlapped: only the overlapper's shifted copies can expose it
                     const int u = acc & 0xFFFF;
                     const NbrEntry<Real> e = s_nbr[u];
-                    const Real dot = Qx * e.ax + Qy * e.ay + Qz * e.az;
-                    if (!test_cover<Real, MIXED>(dot + drr * Qx, e.cx, cd, ri, roff_i, k, s_nbr_j[u], 0)) atomicAdd(&s_ev[3 * u + 0], 1);
-                    if (!test_cover<Real, MIXED>(dot + drr * Qy, e.cy, cd, ri, roff_i, k, s_nbr_j[u], 1)) atomicAdd(&s_ev[3 * u + 1], 1);
-                    if (!test_cover<Real, MIXED>(dot + drr * Qz, e.cz, cd, ri, roff_i, k, s_nbr_j[u], 2)) atomicAdd(&s_ev[3 * u + 2], 1);
+                    const Real base = Qx * e.ax + Qy * e.ay + Qz * e.az - e.c0 - kq;
+                    if (!test_cover<Real, MIXED>(base + drr * Qx - k1 * e.ax, (Real)0, cd, ri, roff_i, k, s_nbr_j[u], 0)) atomicAdd(&s_ev[3 * u + 0], 1);
+                    if (!test_cover<Real, MIXED>(base + drr * Qy - k1 * e.ay, (Real)0, cd, ri, roff_i, k, s_nbr_j[u], 1)) atomicAdd(&s_ev[3 * u + 1], 1);
+                    if (!test_cover<Real, MIXED>(base + drr * Qz - k1 * e.az, (Real)0, cd, ri, roff_i, k, s_nbr_j[u], 2)) atomicAdd(&s_ev[3 * u + 2], 1);
                 }
                 if (C >= 1) ++ncov;
             }
@@ -876,10 +977,10 @@ __global__ __launch_bounds__(FORCE_THREADS) void k_force(Batch bt)
                 Real Qx, Qy, Qz;
                 load_q<Real>(cd, k, Qx, Qy, Qz);
                 const NbrEntry<Real> e = s_nbr[u];
-                const Real dot = Qx * e.ax + Qy * e.ay + Qz * e.az;
-                if (test_cover<Real, MIXED>(dot + drr * Qx, e.cx, cd, ri, roff_i, k, s_nbr_j[u], 0)) atomicAdd(&s_ev[3 * u + 0], -1);
-                if (test_cover<Real, MIXED>(dot + drr * Qy, e.cy, cd, ri, roff_i, k, s_nbr_j[u], 1)) atomicAdd(&s_ev[3 * u + 1], -1);
-                if (test_cover<Real, MIXED>(dot + drr * Qz, e.cz, cd, ri, roff_i, k, s_nbr_j[u], 2)) atomicAdd(&s_ev[3 * u + 2], -1);
+                const Real base = Qx * e.ax + Qy * e.ay + Qz * e.az - e.c0 - kq;
+                if (test_cover<Real, MIXED>(base + drr * Qx - k1 * e.ax, (Real)0, cd, ri, roff_i, k, s_nbr_j[u], 0)) atomicAdd(&s_ev[3 * u + 0], -1);
+                if (test_cover<Real, MIXED>(base + drr * Qy - k1 * e.ay, (Real)0, cd, ri, roff_i, k, s_nbr_j[u], 1)) atomicAdd(&s_ev[3 * u + 1], -1);
+                if (test_cover<Real, MIXED>(base + drr * Qz - k1 * e.az, (Real)0, cd, ri, roff_i, k, s_nbr_j[u], 2)) atomicAdd(&s_ev[3 * u + 2], -1);
             }
             __syncthreads();
         }
@@ -916,6 +1017,75 @@ __global__ __launch_bounds__(FORCE_THREADS) void k_force(Batch bt)
 }
 
 // ---------------------------------------------------------------------------
+// k_wrench: per-atom wrench (F, r x F) (eqs KCM_01, KCM_02), the suffix sum
+// inside each workgroup and the workgroup-local joint torques; the chain
+// kernel adds the contribution of later workgroups
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(ATOM_BLOCK) void k_wrench(Batch bt)
+{
+    const int c = find_block_owner(bt.blk_off, bt.n_chains, blockIdx.x);
+    ChainDev *cd = bt.table[c];
+    if (!cd->stats->active) return;
+    __shared__ double s_w[ATOM_BLOCK / WAVE][WPART];
+    const int lb = blockIdx.x - bt.blk_off[c];
+    const int a = lb * ATOM_BLOCK + threadIdx.x;
+    const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE, nw = ATOM_BLOCK / WAVE;
+    double v[WPART] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    double4 r = make_double4(0, 0, 0, 0);
+    if (a < cd->n_atoms) {
+        const double inv_fix = 1.0 / FIX_SCALE;
+        const double4 fp = cd->f_pair[a];
+        const double Fx = fp.x + (double)cd->f_cav[3 * a] * inv_fix;
+        const double Fy = fp.y + (double)cd->f_cav[3 * a + 1] * inv_fix;
+        const double Fz = fp.z + (double)cd->f_cav[3 * a + 2] * inv_fix;
+        r = cd->r[a];
+        v[0] = Fx; v[1] = Fy; v[2] = Fz;
+        v[3] = r.y * Fz - r.z * Fy; v[4] = r.z * Fx - r.x * Fz; v[5] = r.x * Fy - r.y * Fx;
+        const double4 e = cd->e_atom[a];
+        v[6] = e.x; v[7] = e.y; v[8] = e.z;
+        v[9] = (isfinite(Fx) && isfinite(Fy) && isfinite(Fz)) ? 0.0 : 1.0;
+    }
+    // inclusive suffix over the workgroup: this atom and every later one
+    double S[WPART];
+#pragma unroll
+    for (int k = 0; k < WPART; ++k) S[k] = v[k];
+#pragma unroll
+    for (int d = 1; d < WAVE; d <<= 1) {
+#pragma unroll
+        for (int k = 0; k < WPART; ++k) {
+            const double y = __shfl_down(S[k], d, WAVE);
+            if (lane + d < WAVE) S[k] += y;
+        }
+    }
+    if (lane == 0)
+        for (int k = 0; k < WPART; ++k) s_w[w][k] = S[k];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        double t = 0.0;
+        for (int i = w + 1; i < nw; ++i) t += s_w[i][k];
+        S[k] += t;
+    }
+    if (a < cd->n_atoms) {
+        const int res = a / APR, slot = a - res * APR;
+        if (slot == 2 || slot == 8) {
+            const int j = 2 * res + (slot == 8 ? 1 : 0);
+            const double4 u = cd->jcur[2 * j], p = cd->jcur[2 * j + 1];
+            const double mx = S[3] - (p.y * S[2] - p.z * S[1]);
+            const double my = S[4] - (p.z * S[0] - p.x * S[2]);
+            const double mz = S[5] - (p.x * S[1] - p.y * S[0]);
+            cd->tau[j] = u.x * mx + u.y * my + u.z * mz;
+        }
+    }
+    if (threadIdx.x < WPART) {
+        double t = 0.0;
+        for (int i = 0; i < nw; ++i) t += s_w[i][threadIdx.x];
+        cd->wrench_part[WPART * lb + threadIdx.x] = t;
+    }
+    if (lb == 0 && threadIdx.x == 0) cd->stats->pending_post = 1;
+}
+
+// ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
 hipError_t launch_chain(const Batch &b, int do_post, int do_fk, hipStream_t s)
@@ -946,10 +1116,17 @@ hipError_t launch_scatter(const Batch &b, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_cellsort(const Batch &b, hipStream_t s)
+hipError_t launch_rank(const Batch &b, hipStream_t s)
 {
     if (b.total_blocks <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_cellsort, dim3(b.total_blocks), dim3(ATOM_BLOCK), 0, s, b);
+    hipLaunchKernelGGL(k_rank, dim3(b.total_blocks), dim3(ATOM_BLOCK), 0, s, b);
+    return hipGetLastError();
+}
+
+hipError_t launch_wrench(const Batch &b, hipStream_t s)
+{
+    if (b.total_blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_wrench, dim3(b.total_blocks), dim3(ATOM_BLOCK), 0, s, b);
     return hipGetLastError();
 }
 

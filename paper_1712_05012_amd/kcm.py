@@ -23,7 +23,8 @@ KCM_TERM_ELEC, KCM_TERM_VDW, KCM_TERM_CAV, KCM_TERM_ALL = 1, 2, 4, 7
 
 EXPORTED = ("kcm_default_params", "kcm_chain_bytes", "kcm_build_chain", "kcm_step", "kcm_fold",
             "kcm_get_state", "kcm_get_forces", "kcm_set_theta", "kcm_get_cells", "kcm_chain_info",
-            "kcm_set_timing", "kcm_get_timing", "kcm_chain_free", "kcm_last_error", "kcm_get_atom_terms")
+            "kcm_set_timing", "kcm_get_timing", "kcm_chain_free", "kcm_last_error", "kcm_get_atom_terms",
+            "kcm_set_limits", "kcm_set_graphs")
 
 
 class KcmError(RuntimeError):
@@ -83,6 +84,8 @@ def load_library(path: str = LIB_PATH):
     lib.kcm_get_forces.argtypes = [vp, vp, vp, vp]
     lib.kcm_set_theta.argtypes = [vp, vp, vp]
     lib.kcm_get_atom_terms.argtypes = [vp, vp, vp, vp, vp, vp]
+    lib.kcm_set_limits.argtypes = [vp, C.c_double, C.c_int64, vp]
+    lib.kcm_set_graphs.argtypes = [C.c_int]
     lib.kcm_get_cells.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, C.c_int32]
     lib.kcm_chain_info.argtypes = [vp, vp, vp, vp, vp]
     lib.kcm_set_timing.argtypes = [C.c_int]
@@ -236,6 +239,10 @@ def kcm_get_atom_terms(handle, stream=None):
     return {"e_elec": ee, "e_vdw": ev, "e_cav": ec, "n_exposed": nx}
 
 
+def kcm_set_limits(handle, tol: float, max_iterations: int, stream=None):
+    _check(load_library().kcm_set_limits(handle, float(tol), int(max_iterations), _stream_handle(stream)))
+
+
 def kcm_set_theta(handle, theta, stream=None):
     th = np.ascontiguousarray(theta, dtype=np.float64)
     _check(load_library().kcm_set_theta(handle, _p(th), _stream_handle(stream)))
@@ -257,8 +264,13 @@ def kcm_get_cells(handle, stream=None):
     return {"dims": dims, "cell": cell.value, "origin": origin, "order": order, "cell_start": cs}
 
 
-def kcm_set_timing(enable: bool):
-    _check(load_library().kcm_set_timing(1 if enable else 0))
+def kcm_set_graphs(enable: bool):
+    _check(load_library().kcm_set_graphs(1 if enable else 0))
+
+
+def kcm_set_timing(every: int):
+    """Sample HIP events on every `every`-th iteration (0 = off)."""
+    _check(load_library().kcm_set_timing(int(every)))
 
 
 def kcm_get_timing(reset: bool = False):

@@ -216,3 +216,63 @@ def test_fold_converges_and_reports():
     if res[0].converged:
         assert gpu.step(1).max_dtheta < 1e-4 * 1.5 or True
     gpu.free()
+
+
+def test_graph_replay_equals_direct_launches():
+    # replays of the captured iteration, with eager work and synchronisations
+    # between calls, must match direct launches bit for bit after every call
+    p = params(kcm.KCM_MIXED)
+    seqs = [(synth.sequence(m, 140 + m), synth.random_dihedrals(m, 140 + m)) for m in (9, 27, 14)]
+    a = [kcm.Chain(s, TYPES, p, theta0=t) for s, t in seqs]
+    b = [kcm.Chain(s, TYPES, p, theta0=t) for s, t in seqs]
+    try:
+        for rep in range(4):
+            kcm.kcm_set_graphs(True)
+            kcm.kcm_step(a, 3)
+            x = torch.ones(1000, device="cuda").sum().item()  # eager work in between
+            assert x == 1000.0
+            kcm.kcm_set_graphs(False)
+            kcm.kcm_step(b, 3)
+            torch.cuda.synchronize()
+            for ca, cb in zip(a, b):
+                sa, sb = ca.state(), cb.state()
+                for key in ("theta", "xyz", "force", "tau"):
+                    assert np.array_equal(sa[key], sb[key]), (rep, key)
+    finally:
+        kcm.kcm_set_graphs(True)
+        for c in a + b:
+            c.free()
+
+
+def test_device_side_limits_stop_chains():
+    p = params(kcm.KCM_MIXED)
+    c1 = kcm.Chain(synth.sequence(6, 151), TYPES, p, theta0=synth.random_dihedrals(6, 151))
+    c2 = kcm.Chain(synth.sequence(6, 152), TYPES, p, theta0=synth.random_dihedrals(6, 152))
+    kcm.kcm_set_limits(c1.handle, 0.0, 7)      # iteration cap only
+    kcm.kcm_set_limits(c2.handle, 10.0, 0)     # converges on the first step (max|dtheta| < 10 rad)
+    _, reps = kcm.kcm_step([c1, c2], 20)
+    assert reps[0].iterations == 7 and not reps[0].converged
+    assert reps[1].iterations == 1 and reps[1].converged
+    c1.free()
+    c2.free()
+
+
+def test_served_job_result_same_alone_and_in_mix():
+    from paper_1712_05012_amd.serve import FoldService, Job, KcmEngine
+
+    def jobs():
+        out = []
+        for k, (m, a) in enumerate([(12, 0.0), (30, 0.0), (8, 0.01), (20, 0.02), (15, 0.02)]):
+            out.append(Job(job_id=k, res_type=synth.sequence(m, 160 + k), theta0=synth.random_dihedrals(m, 160 + k),
+                           arrival=a, tol=1e-4, max_iter=60 + 10 * k))
+        return out
+
+    p = params(kcm.KCM_MIXED)
+    mix = FoldService(KcmEngine(TYPES, p), hbm_budget=3 * 1024 * 1024, max_slots=3, check_every=7).run(jobs())
+    assert mix.max_live >= 2
+    for target in (1, 3):
+        alone = FoldService(KcmEngine(TYPES, p), hbm_budget=1 << 30, max_slots=1, check_every=7)
+        st = alone.run([j for j in jobs() if j.job_id == target])
+        a, b = st.jobs[0], [j for j in mix.jobs if j.job_id == target][0]
+        assert a.iterations == b.iterations
+        assert np.array_equal(a.theta, b.theta)
