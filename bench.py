@@ -238,6 +238,8 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=100, help="iterations of the 256-chain batch (0: skip)")
     ap.add_argument("--serve-jobs", type=int, default=48, help="jobs of the serving run (0: skip)")
     ap.add_argument("--serve-max-iter", type=int, default=2000)
+    ap.add_argument("--no-graphs", action="store_true",
+                    help="launch each iteration's kernels directly instead of replaying a HIP graph")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="first run a plain device copy of MIB MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -256,6 +258,10 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     torch.cuda.set_device(0)
+    if args.no_graphs:
+        from paper_1712_05012_amd import kcm
+
+        kcm.kcm_set_graphs(0)
     if args.copy_probe > 0:
         src = torch.empty(args.copy_probe << 18, dtype=torch.float32, device="cuda").fill_(1.0)
         dst = torch.empty_like(src)

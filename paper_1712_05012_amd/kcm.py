@@ -13,7 +13,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libkcm.so")
+LIB_PATH = os.environ.get("KCM_LIB", os.path.join(_HERE, "libkcm.so"))
 _lib = None
 
 KCM_OK, KCM_E_INVAL, KCM_E_NOMEM, KCM_E_DEVICE, KCM_E_NUMERIC, KCM_E_STATE, KCM_E_CAPACITY = 0, -1, -2, -3, -4, -5, -6
