@@ -151,7 +151,8 @@ std::vector<V3> sample_directions(int n_orb)
 // device block layout
 // ---------------------------------------------------------------------------
 struct Layout {
-    size_t desc, stats, grid, theta, dtheta, tau, mask, joint0, jcur, xform, r0, r, aparam, g0, qfix;
+    size_t desc, stats, grid, theta, dtheta, tau, mask, joint0, jcur, xform, xform_loc, blk_xf, tmax_part, bad_part;
+    size_t r0, r, aparam, g0, qfix;
     size_t cell_key, cell_count, cell_start, cell_cursor, bbox_part, wrench_part, s_r, s_p, s_tmp, s_idx, s_cell;
     size_t f_pair, f_cav;
     size_t e_atom;
@@ -178,7 +179,7 @@ Layout make_layout(int m, int n_orb)
     const size_t n = l.n, J = l.J, L = l.L, N = l.N, cap = l.cap;
     l.desc = take(sizeof(ChainDev));
     l.stats = take(sizeof(ChainStats));
-    l.grid = take(sizeof(Grid));
+    l.grid = take(3 * sizeof(Grid));
     l.theta = take(8 * J);
     l.dtheta = take(8 * J);
     l.tau = take(8 * J);
@@ -186,6 +187,11 @@ Layout make_layout(int m, int n_orb)
     l.joint0 = take(64 * J);
     l.jcur = take(64 * J);
     l.xform = take(96 * L);
+    const size_t njb = (J + JOINT_BLOCK - 1) / JOINT_BLOCK;
+    l.xform_loc = take(96 * J);
+    l.blk_xf = take(96 * njb);
+    l.tmax_part = take(8 * njb);
+    l.bad_part = take(4 * njb);
     l.r0 = take(32 * n);
     l.r = take(32 * n);
     l.aparam = take(32 * n);
@@ -269,21 +275,47 @@ hipError_t capture_stream(hipStream_t *out)
     return hipSuccess;
 }
 
-hipError_t launch_iteration(const Batch &bt, int prec, hipStream_t stream)
-{
-    hipError_t e;
-    if ((e = launch_chain(bt, 1, 1, stream)) != hipSuccess) return e;
-    if ((e = launch_place(bt, stream)) != hipSuccess) return e;
-    if ((e = launch_cellscan(bt, stream)) != hipSuccess) return e;
-    if ((e = launch_scatter(bt, stream)) != hipSuccess) return e;
-    if ((e = launch_rank(bt, stream)) != hipSuccess) return e;
-    if ((e = launch_force(bt, prec, stream)) != hipSuccess) return e;
-    return launch_wrench(bt, stream);
-}
-
 struct TimedIter {
     hipEvent_t it0, f0, f1, it1;
 };
+
+// One iteration; with ti, events bracket the iteration and the force kernel.
+hipError_t launch_iteration(const Batch &bt, int prec, hipStream_t stream, const TimedIter *ti = nullptr)
+{
+    hipError_t e;
+    if (ti && (e = hipEventRecord(ti->it0, stream)) != hipSuccess) return e;
+    if ((e = launch_tau(bt, stream)) != hipSuccess) return e;
+    if ((e = launch_stepfk(bt, MODE_ITER, stream)) != hipSuccess) return e;
+    if ((e = launch_place(bt, MODE_ITER, stream)) != hipSuccess) return e;
+    if ((e = launch_cellscan(bt, stream)) != hipSuccess) return e;
+    if ((e = launch_scatter(bt, stream)) != hipSuccess) return e;
+    if ((e = launch_rank(bt, stream)) != hipSuccess) return e;
+    if (ti && (e = hipEventRecord(ti->f0, stream)) != hipSuccess) return e;
+    if ((e = launch_force(bt, prec, stream)) != hipSuccess) return e;
+    if (ti && (e = hipEventRecord(ti->f1, stream)) != hipSuccess) return e;
+    if ((e = launch_wrench(bt, stream)) != hipSuccess) return e;
+    if (ti && (e = hipEventRecord(ti->it1, stream)) != hipSuccess) return e;
+    return hipSuccess;
+}
+
+// Positions and the first grid of every chain of the batch that has none
+// (the kernels skip the others).
+hipError_t launch_boot(const Batch &bt, hipStream_t stream)
+{
+    hipError_t e;
+    if ((e = launch_stepfk(bt, MODE_BOOT, stream)) != hipSuccess) return e;
+    if ((e = launch_place(bt, MODE_BOOT, stream)) != hipSuccess) return e;
+    return launch_gridboot(bt, stream);
+}
+
+// The post phase of the last forces of a call.
+hipError_t launch_final(const Batch &bt, hipStream_t stream)
+{
+    hipError_t e;
+    if ((e = launch_tau(bt, stream)) != hipSuccess) return e;
+    if ((e = launch_stepfk(bt, MODE_FINAL, stream)) != hipSuccess) return e;
+    return launch_finish(bt, stream);
+}
 std::vector<TimedIter> g_timed;
 std::vector<hipEvent_t> g_event_pool;
 int g_timing = 0;
@@ -313,6 +345,7 @@ struct kcm_chain {
     int device;
     int m, n, J, N;
     std::vector<unsigned char> staging;  // host source of the build copies
+    bool boot = true;    // the conformation has no grid yet (built, or new angles)
 };
 
 namespace {
@@ -333,9 +366,11 @@ kcm_status ensure_table(kcm_chain *const *chains, int n_chains, hipStream_t stre
     bool same = (int)t->chains.size() == n_chains;
     for (int i = 0; same && i < n_chains; ++i) same = t->chains[i] == chains[i];
     if (!same) {
+        const size_t ints = ((sizeof(int32_t) * (n_chains + 1) + 255) & ~size_t(255));
         const size_t off_pos = (sizeof(ChainDev *) * n_chains + 255) & ~size_t(255);
-        const size_t blk_pos = off_pos + ((sizeof(int32_t) * (n_chains + 1) + 255) & ~size_t(255));
-        const size_t need = blk_pos + sizeof(int32_t) * (n_chains + 1);
+        const size_t blk_pos = off_pos + ints;
+        const size_t jblk_pos = blk_pos + ints;
+        const size_t need = jblk_pos + sizeof(int32_t) * (n_chains + 1);
         if (need > t->cap) {
             if (t->dev) {
                 HIP_TRY(hipStreamSynchronize(stream));
@@ -350,26 +385,32 @@ kcm_status ensure_table(kcm_chain *const *chains, int n_chains, hipStream_t stre
         ChainDev **tab = reinterpret_cast<ChainDev **>(host.data());
         int32_t *off = reinterpret_cast<int32_t *>(host.data() + off_pos);
         int32_t *blk = reinterpret_cast<int32_t *>(host.data() + blk_pos);
-        long long total = 0, blocks = 0;
+        int32_t *jblk = reinterpret_cast<int32_t *>(host.data() + jblk_pos);
+        long long total = 0, blocks = 0, jblocks = 0;
         for (int i = 0; i < n_chains; ++i) {
             tab[i] = chains[i]->d_desc;
             off[i] = (int32_t)total;
             blk[i] = (int32_t)blocks;
+            jblk[i] = (int32_t)jblocks;
             total += chains[i]->n;
             blocks += (chains[i]->n + ATOM_BLOCK - 1) / ATOM_BLOCK;
+            jblocks += (chains[i]->J + JOINT_BLOCK - 1) / JOINT_BLOCK;
         }
         if (total > std::numeric_limits<int32_t>::max()) return fail(KCM_E_INVAL, "too many atoms in one call");
         off[n_chains] = (int32_t)total;
         blk[n_chains] = (int32_t)blocks;
+        jblk[n_chains] = (int32_t)jblocks;
         HIP_TRY(hipMemcpyAsync(t->dev, host.data(), need, hipMemcpyHostToDevice, stream));
         HIP_TRY(hipStreamSynchronize(stream));
         unsigned char *d = static_cast<unsigned char *>(t->dev);
         t->batch.table = reinterpret_cast<ChainDev *const *>(d);
         t->batch.atom_off = reinterpret_cast<const int32_t *>(d + off_pos);
         t->batch.blk_off = reinterpret_cast<const int32_t *>(d + blk_pos);
+        t->batch.jblk_off = reinterpret_cast<const int32_t *>(d + jblk_pos);
         t->batch.n_chains = n_chains;
         t->batch.total_atoms = (int)total;
         t->batch.total_blocks = (int)blocks;
+        t->batch.total_jblocks = (int)jblocks;
         t->chains.assign(chains, chains + n_chains);
         if (t->graph) {
             HIP_TRY(hipGraphExecDestroy(t->graph));
@@ -550,6 +591,7 @@ kcm_status kcm_build_chain(const kcm_chain_desc *desc, const kcm_params *params,
     st.tol = 0.0;
     st.iter_limit = std::numeric_limits<int64_t>::max();
     st.active = 1;
+    st.run = 1;
     st.need_grid = 1;
 
 #define PTR(field, type) h.field = reinterpret_cast<type>(base + l.field)
@@ -560,6 +602,10 @@ kcm_status kcm_build_chain(const kcm_chain_desc *desc, const kcm_params *params,
     PTR(joint0, double4 *);
     PTR(jcur, double4 *);
     PTR(xform, double *);
+    PTR(xform_loc, double *);
+    PTR(blk_xf, double *);
+    PTR(tmax_part, double *);
+    PTR(bad_part, int32_t *);
     PTR(r0, double4 *);
     PTR(r, double4 *);
     PTR(aparam, double4 *);
@@ -582,6 +628,8 @@ kcm_status kcm_build_chain(const kcm_chain_desc *desc, const kcm_params *params,
     PTR(q64, double4 *);
     PTR(q32, float4 *);
     PTR(grid, Grid *);
+    h.grid_next = h.grid + 1;
+    h.grid_last = h.grid + 2;
     PTR(stats, ChainStats *);
 #undef PTR
     c->d_desc = reinterpret_cast<ChainDev *>(base + l.desc);
@@ -654,6 +702,14 @@ kcm_status kcm_step(kcm_chain *const *chains, int n_chains, int n_iter, void *hi
         }
         t->graph_prec = prec;
     }
+    if (n_iter > 0) {
+        bool boot = false;
+        for (int i = 0; i < n_chains; ++i) boot = boot || chains[i]->boot;
+        if (boot) {
+            HIP_TRY(launch_boot(bt, stream));
+            for (int i = 0; i < n_chains; ++i) chains[i]->boot = false;
+        }
+    }
     for (int it = 0; it < n_iter; ++it) {
         const bool timed = g_timing > 0 && (g_timing_count++ % g_timing) == 0;
         if (!timed) {
@@ -663,20 +719,11 @@ kcm_status kcm_step(kcm_chain *const *chains, int n_chains, int n_iter, void *hi
         }
         // a sampled iteration: direct launches bracketed by events
         TimedIter ti = {pooled_event(), pooled_event(), pooled_event(), pooled_event()};
-        HIP_TRY(hipEventRecord(ti.it0, stream));
-        HIP_TRY(launch_chain(bt, 1, 1, stream));
-        HIP_TRY(launch_place(bt, stream));
-        HIP_TRY(launch_cellscan(bt, stream));
-        HIP_TRY(launch_scatter(bt, stream));
-        HIP_TRY(launch_rank(bt, stream));
-        HIP_TRY(hipEventRecord(ti.f0, stream));
-        HIP_TRY(launch_force(bt, prec, stream));
-        HIP_TRY(hipEventRecord(ti.f1, stream));
-        HIP_TRY(launch_wrench(bt, stream));
-        HIP_TRY(hipEventRecord(ti.it1, stream));
+        if (!ti.it0 || !ti.f0 || !ti.f1 || !ti.it1) return fail(KCM_E_DEVICE, "event creation failed");
+        HIP_TRY(launch_iteration(bt, prec, stream, &ti));
         g_timed.push_back(ti);
     }
-    if (n_iter > 0) HIP_TRY(launch_chain(bt, 1, 0, stream));  // post phase of the last iteration
+    if (n_iter > 0) HIP_TRY(launch_final(bt, stream));
     if (!reports) return KCM_OK;
     std::vector<ChainStats> st(n_chains);
     for (int i = 0; i < n_chains; ++i) {
@@ -725,6 +772,7 @@ kcm_status kcm_fold(kcm_chain *const *chains, int n_chains, double tol_dtheta, i
         if ((s = write_field(&d->iter_limit, st[i].iterations + (int64_t)max_iter, stream)) != KCM_OK) return s;
         if ((s = write_field(&d->converged, 0, stream)) != KCM_OK) return s;
         if ((s = write_field(&d->active, max_iter > 0 ? act : 0, stream)) != KCM_OK) return s;
+        if ((s = write_field(&d->run, max_iter > 0 ? act : 0, stream)) != KCM_OK) return s;
     }
     int done = 0;
     while (done < max_iter) {
@@ -746,7 +794,9 @@ kcm_status kcm_fold(kcm_chain *const *chains, int n_chains, double tol_dtheta, i
         ChainStats *d = chains[i]->h.stats;
         if ((s = write_field(&d->tol, 0.0, stream)) != KCM_OK) return s;
         if ((s = write_field(&d->iter_limit, std::numeric_limits<int64_t>::max(), stream)) != KCM_OK) return s;
-        if ((s = write_field(&d->active, st[i].status == 0 && !st[i].converged ? 1 : 0, stream)) != KCM_OK) return s;
+        const int again = st[i].status == 0 && !st[i].converged ? 1 : 0;
+        if ((s = write_field(&d->active, again, stream)) != KCM_OK) return s;
+        if ((s = write_field(&d->run, again, stream)) != KCM_OK) return s;
         if (results) {
             results[i].iterations = st[i].iterations - start[i];
             results[i].converged = st[i].converged;
@@ -846,6 +896,8 @@ kcm_status kcm_set_theta(kcm_chain *c, const double *theta, void *hip_stream)
     if ((st = write_field(&c->h.stats->nbr_overflow, 0, s)) != KCM_OK) return st;
     if ((st = write_field(&c->h.stats->need_grid, 1, s)) != KCM_OK) return st;
     if ((st = write_field(&c->h.stats->pending_post, 0, s)) != KCM_OK) return st;
+    if ((st = write_field(&c->h.stats->run, 1, s)) != KCM_OK) return st;
+    c->boot = true;
     return write_field(&c->h.stats->active, 1, s);
 }
 
@@ -865,7 +917,7 @@ kcm_status kcm_get_cells(const kcm_chain *c, void *hip_stream, int32_t *dims, do
     if (!c) return fail(KCM_E_INVAL, "null chain");
     HIP_TRY(hipStreamSynchronize(static_cast<hipStream_t>(hip_stream)));
     Grid g;
-    HIP_TRY(hipMemcpy(&g, c->h.grid, sizeof g, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(&g, c->h.grid_last, sizeof g, hipMemcpyDeviceToHost));
     if (dims) for (int k = 0; k < 3; ++k) dims[k] = g.dims[k];
     if (cell_size) *cell_size = g.cell;
     if (origin) for (int k = 0; k < 3; ++k) origin[k] = g.origin[k];

@@ -9,10 +9,10 @@
 namespace kcm {
 
 constexpr int APR = 10;              // atoms per residue
-constexpr int FORCE_THREADS = 256;   // one workgroup per atom: 4 waves
 constexpr int CHAIN_THREADS = 1024;  // one workgroup per chain: 16 waves
+constexpr int JOINT_BLOCK = 256;     // joints per workgroup of the torque / step / kinematics kernels
 constexpr int MAX_NBR = 384;         // solvation neighbours of one atom kept in LDS
-constexpr int MAX_REACH = 7;         // cell-stencil half width the force kernel supports
+constexpr int MAX_REACH = 3;         // cell-stencil half width the force kernel supports (cells >= reach/3)
 constexpr double FIX_SCALE = 4294967296.0;  // fixed-point units per kcal/mol/A (2^32)
 constexpr int WPART = 10;            // doubles per wrench partial: F(3), T(3), E(3), flag
 
@@ -25,13 +25,21 @@ struct ChainStats {
     int64_t iter_limit;            // stop when iterations reaches this (kcm_fold)
     int32_t status;                // 0 ok, -4 numeric, -6 neighbour capacity
     int32_t converged;
-    int32_t active;                // 0: the kernels skip this chain
+    int32_t active;                // 0: the chain is stopped (converged, limit or failure)
     int32_t nbr_overflow;          // set by the force kernel, folded into status
     int32_t need_grid;             // 1: no bounding box of the current conformation yet
     int32_t pending_post;          // 1: forces of an iteration await their post phase
+    int32_t post_bad;              // set by the torque kernel: a non-finite force in the pending post phase
+    int32_t run;                   // 0: the kernels after the step skip this chain in this iteration
 };
+// active is read by the torque and step kernels and written only at the end of
+// an iteration (or call) from run; run is written by the step kernel and the
+// cell scan and read by every later kernel.  So no kernel reads a flag that
+// another workgroup of the same kernel may change.
 
-// Cell grid of the current iteration (written by the chain kernel).
+// A cell grid.  A chain holds three: the one the current iteration's cell list
+// uses, the one sized for the next iteration, and the one of the last
+// completed cell list.
 struct Grid {
     double origin[3];
     double cell, inv_cell;
@@ -56,6 +64,10 @@ struct ChainDev {
     double4 *joint0;     // [J][2]: (u0, 0), (p0, 0) zero-position axis and point
     double4 *jcur;       // [J][2]: current (u, 0), (p, 0)
     double *xform;       // [L][12] link transforms: R row-major, then t
+    double *xform_loc;   // [J][12] product of the joint transforms from the start of j's joint block to j
+    double *blk_xf;      // [nJB][12] product of all joint transforms of each joint block
+    double *tmax_part;   // [nJB] max |tau| over the masked joints of each joint block
+    int32_t *bad_part;   // [nJB] 1 if a torque of the block is not finite
     double4 *r0;         // [n] zero-position coordinates
     double4 *r;          // [n] current coordinates
     double4 *aparam;     // [n] (q, R_vdw, sqrt(eps), R_off)
@@ -77,29 +89,42 @@ struct ChainDev {
     double4 *e_atom;     // [n] (elec, vdw, cav, exposed samples) per atom
     double4 *q64;        // [N] unit sample directions
     float4 *q32;         // [N]
-    Grid *grid;
+    Grid *grid;          // grid of the current iteration
+    Grid *grid_next;     // sized from this iteration's positions, used by the next one
+    Grid *grid_last;     // grid of the last completed cell list
     ChainStats *stats;
 };
 
 // The chains of one call.  table: device array of device descriptors;
-// atom_off / blk_off: device arrays [n_chains+1] of cumulative atom counts and
-// of cumulative per-atom workgroup counts (ATOM_BLOCK atoms per workgroup).
+// atom_off / blk_off / jblk_off: device arrays [n_chains+1] of cumulative atom
+// counts, of cumulative per-atom workgroup counts (ATOM_BLOCK atoms per
+// workgroup) and of cumulative joint-block counts (JOINT_BLOCK joints each).
 constexpr int ATOM_BLOCK = 256;
 struct Batch {
     ChainDev *const *table;
     const int32_t *atom_off;
     const int32_t *blk_off;
+    const int32_t *jblk_off;
     int n_chains;
     int total_atoms;
     int total_blocks;
+    int total_jblocks;
 };
 
+// Modes of the step/kinematics and placement kernels.
+enum : int { MODE_ITER = 0, MODE_FINAL = 1, MODE_BOOT = 2 };
+
 // Launchers (kcm_kernels.hip).  One iteration is
-//   chain(post of the previous iteration if any, then kinematics + grid),
-//   place, cellscan, scatter, rank, force, wrench;
-// a call ends with chain(post only).
-hipError_t launch_chain(const Batch &b, int do_post, int do_fk, hipStream_t s);
-hipError_t launch_place(const Batch &b, hipStream_t s);
+//   tau, stepfk (post phase of the previous forces if pending, then the
+//   kinematics of each joint block), place, cellscan, scatter, rank, force,
+//   wrench;
+// a call ends with tau, stepfk(MODE_FINAL), finish.  A chain without a grid
+// (new, or new angles) first runs stepfk(MODE_BOOT), place(MODE_BOOT), gridboot.
+hipError_t launch_tau(const Batch &b, hipStream_t s);
+hipError_t launch_stepfk(const Batch &b, int mode, hipStream_t s);
+hipError_t launch_gridboot(const Batch &b, hipStream_t s);
+hipError_t launch_finish(const Batch &b, hipStream_t s);
+hipError_t launch_place(const Batch &b, int mode, hipStream_t s);
 hipError_t launch_cellscan(const Batch &b, hipStream_t s);
 hipError_t launch_scatter(const Batch &b, hipStream_t s);
 hipError_t launch_force(const Batch &b, int precision, hipStream_t s);

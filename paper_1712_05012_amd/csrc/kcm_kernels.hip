@@ -1,31 +1,32 @@
 // kcm_kernels.hip -- gfx950 kernels of one KCM iteration.
 //
-//   k_chain     one workgroup per chain.  Post phase of the previous
-//               iteration: link wrenches and the suffix (row) scan of eq 04_9
-//               giving tau_k = u_k . (T_k - p_k x F_k) (eqs KCM_01-KCM_06),
-//               then the compliance step (eq KCM_07).  Then forward
-//               kinematics of the new angles as an ordered prefix scan of
-//               rigid transforms (eqs kin_02-kin_04, r1; prefix computation
-//               item 1 of Sec. 3.5) and the cell grid of Sec. 3.2, sized from
-//               the previous bounding box plus a margin (atoms outside it are
-//               clamped to the border cells, which keeps every neighbour
-//               within the stencil).
-//   k_place     one thread per atom: r_a = G_link(a) r0_a, cell key, cell
-//               count, bounding box of the new positions.
-//   k_cellscan  one workgroup per chain: cell starts by an exclusive scan.
+//   k_tau       one thread per joint: joint torques of the pending forces,
+//               tau_k = u_k . (T_k - p_k x F_k) (eqs KCM_01-KCM_06), with the
+//               wrench of later atom workgroups from a suffix (row) scan
+//               (eq 04_9).
+//   k_stepfk    one thread per joint: the compliance step (eq KCM_07), then
+//               forward kinematics of the new angles as an ordered prefix
+//               scan of rigid transforms inside each joint block (eqs
+//               kin_02-kin_04, r1; prefix computation item 1 of Sec. 3.5).
+//   k_place     one thread per atom: link transforms (products of the
+//               earlier joint blocks composed in front of the block-local
+//               ones), r_a = G_link(a) r0_a, cell key on the grid of Sec. 3.2,
+//               cell count, bounding box of the new positions.
+//   k_cellscan  one workgroup per chain: cell starts by an exclusive scan,
+//               and the next iteration's grid, sized from this bounding box
+//               plus a margin (atoms outside it are clamped to the border
+//               cells, which keeps every neighbour within the stencil).
 //   k_scatter   one thread per atom: counting-sort scatter by cell key.
 //   k_rank      one thread per atom: stable slot inside the cell, gather.
-//   k_cellsort  one thread per cell: restores atom order inside the cell
-//               (the sort is then stable, so everything downstream is
-//               deterministic) and gathers positions/parameters in cell order.
-//   k_force     one workgroup per atom, atoms in cell order: stencil
-//               candidates in FP64, Coulomb + LJ (eqs 02-03_9) over the full
-//               pair list, solvation neighbours in LDS, and the SASA
-//               enumeration of Algorithm 1 with the C-state rules (Sec. 3.4):
-//               coverage counts with one sample per lane, then the displaced
-//               tests for the compacted exposed samples only.  Solvation
-//               events are scattered as fixed-point integers, so every sum is
-//               order independent.
+//   k_force     one wave per atom, atoms in cell order: stencil candidates
+//               in FP64, Coulomb + LJ (eqs 02-03_9), solvation neighbours in
+//               LDS, and the SASA enumeration of Algorithm 1 with the C-state
+//               rules (Sec. 3.4): coverage counts with four samples per lane,
+//               the displaced tests of critical samples inline and those of
+//               exposed samples with one lane per neighbour.  Solvation
+//               events are scattered as fixed-point integers.
+//   k_wrench    one thread per atom: wrench (F, r x F), the suffix sum inside
+//               the workgroup and the workgroup-local part of each torque.
 #include "kcm_internal.h"
 
 #include <float.h>
@@ -96,23 +97,6 @@ __device__ __forceinline__ Xf xf_load(const double *p)
     for (int k = 0; k < 9; ++k) x.r[k] = p[k];
 #pragma unroll
     for (int k = 0; k < 3; ++k) x.t[k] = p[9 + k];
-    return x;
-}
-
-// Joint j: right-hand rotation by (theta_j - pi) about the zero-position axis
-// line through p0_j with direction u0_j.
-__device__ __forceinline__ Xf joint_xf(const double4 *__restrict__ joint0, const double *__restrict__ theta, int j)
-{
-    const double4 u = joint0[2 * j], p = joint0[2 * j + 1];
-    double s, c;
-    sincos(theta[j] - PI_D, &s, &c);
-    const double k = 1.0 - c;
-    Xf x;
-    x.r[0] = c + u.x * u.x * k;       x.r[1] = u.x * u.y * k - u.z * s; x.r[2] = u.x * u.z * k + u.y * s;
-    x.r[3] = u.y * u.x * k + u.z * s; x.r[4] = c + u.y * u.y * k;       x.r[5] = u.y * u.z * k - u.x * s;
-    x.r[6] = u.z * u.x * k - u.y * s; x.r[7] = u.z * u.y * k + u.x * s; x.r[8] = c + u.z * u.z * k;
-#pragma unroll
-    for (int i = 0; i < 3; ++i) x.t[i] = ((&p.x)[i]) - (x.r[3 * i] * p.x + x.r[3 * i + 1] * p.y + x.r[3 * i + 2] * p.z);
     return x;
 }
 
@@ -218,18 +202,6 @@ __device__ __forceinline__ int find_block_owner(const int32_t *off, int n, int b
     return lo;
 }
 
-__device__ __forceinline__ double4 place_atom(const ChainDev *cd, int a)
-{
-    const double *L = cd->xform + 12 * link_of_atom(a);
-    const double4 q = cd->r0[a];
-    double4 r;
-    r.x = L[0] * q.x + L[1] * q.y + L[2] * q.z + L[9];
-    r.y = L[3] * q.x + L[4] * q.y + L[5] * q.z + L[10];
-    r.z = L[6] * q.x + L[7] * q.y + L[8] * q.z + L[11];
-    r.w = 0.0;
-    return r;
-}
-
 __device__ __forceinline__ int cell_of(const Grid &g, const double4 &r)
 {
     int cx = (int)floor((r.x - g.origin[0]) * g.inv_cell);
@@ -242,150 +214,21 @@ __device__ __forceinline__ int cell_of(const Grid &g, const double4 &r)
 }
 
 constexpr double GRID_MARGIN = 2.0;  // A added around the previous bounding box
+constexpr int LINKS_PER_BLOCK = 56;  // links touched by ATOM_BLOCK consecutive atoms (at most 53)
 
-// ---------------------------------------------------------------------------
-// k_chain: post phase of the previous iteration, then kinematics and grid
-// ---------------------------------------------------------------------------
-constexpr int FK_REG = 2;  // joints per thread kept in registers (J <= FK_REG * blockDim)
+// First atom moved by joint j: the first atom of link j+1 (C-alpha for phi,
+// C for psi).
+__device__ __forceinline__ int first_atom_of_joint(int j) { return APR * (j >> 1) + ((j & 1) ? 8 : 2); }
+__device__ __forceinline__ int first_atom_of_link(int l) { return l == 0 ? 0 : first_atom_of_joint(l - 1); }
 
-// Post phase of the previous iteration for this thread's joints [j0, j1).
-// th[] holds their angles on entry (when the chunk fits FK_REG) and the
-// updated angles on exit.
-__device__ void post_phase(const ChainDev *cd, int j0, int j1, double (&th)[FK_REG], bool in_reg, int *s_flag,
-                           double *s_red, double (*s_w)[6])
+__device__ __forceinline__ Xf xf_shfl_idx(const Xf &x, int src)
 {
-    ChainStats *st = cd->stats;
-    const int n = cd->n_atoms;
-    const int nblk = (n + ATOM_BLOCK - 1) / ATOM_BLOCK;
-    const int tid = threadIdx.x, nt = blockDim.x, lane = tid & (WAVE - 1), w = tid / WAVE, nw = nt / WAVE;
-    double *__restrict__ part = cd->wrench_part;
-    double *__restrict__ tau = cd->tau;
-    double *__restrict__ theta = cd->theta;
-    double *__restrict__ dtheta = cd->dtheta;
-    const uint8_t *__restrict__ mask = cd->mask;
-    const double4 *__restrict__ jcur = cd->jcur;
-
-    // energies and the failure flag: plain sums of the per-workgroup partials
-    double E[4] = {0, 0, 0, 0};
-    for (int b = tid; b < nblk; b += nt) {
-        E[0] += part[WPART * b + 6];
-        E[1] += part[WPART * b + 7];
-        E[2] += part[WPART * b + 8];
-        E[3] += part[WPART * b + 9];
-    }
-    block_sum<4>(E, s_red);
-
-    // exclusive suffix over workgroups, in place: part[b][0..5] becomes the
-    // wrench of every atom after workgroup b (processed from the last chunk)
-    double carry[6] = {0, 0, 0, 0, 0, 0};
-    for (int c0 = ((nblk - 1) / nt) * nt; c0 >= 0; c0 -= nt) {
-        const int b = c0 + tid;
-        double v[6], S[6];
+    Xf y;
 #pragma unroll
-        for (int k = 0; k < 6; ++k) v[k] = (b < nblk) ? part[WPART * b + k] : 0.0;
+    for (int k = 0; k < 9; ++k) y.r[k] = __shfl(x.r[k], src, WAVE);
 #pragma unroll
-        for (int k = 0; k < 6; ++k) S[k] = v[k];
-#pragma unroll
-        for (int d = 1; d < WAVE; d <<= 1) {
-#pragma unroll
-            for (int k = 0; k < 6; ++k) {
-                const double y = __shfl_down(S[k], d, WAVE);
-                if (lane + d < WAVE) S[k] += y;
-            }
-        }
-        if (lane == 0)
-            for (int k = 0; k < 6; ++k) s_w[w][k] = S[k];
-        __syncthreads();
-        double later[6], tot[6];
-#pragma unroll
-        for (int k = 0; k < 6; ++k) {
-            double t = 0.0, u = 0.0;
-            for (int i = 0; i < nw; ++i) {
-                u += s_w[i][k];
-                if (i > w) t += s_w[i][k];
-            }
-            later[k] = t;
-            tot[k] = u;
-        }
-        if (b < nblk)
-            for (int k = 0; k < 6; ++k) part[WPART * b + k] = carry[k] + later[k] + (S[k] - v[k]);
-        __syncthreads();
-#pragma unroll
-        for (int k = 0; k < 6; ++k) carry[k] += tot[k];
-    }
-
-    // tau_j = (workgroup-local part from k_wrench) + u_j . (T_later - p_j x F_later)
-    double tmax = 0.0;
-    bool tbad = false;
-    for (int j = j0; j < j1; ++j) {
-        const int first = APR * (j >> 1) + ((j & 1) ? 8 : 2);  // first atom of link j+1
-        const double *S = part + WPART * (first / ATOM_BLOCK);
-        const double4 u = jcur[2 * j], p = jcur[2 * j + 1];
-        const double mx = S[3] - (p.y * S[2] - p.z * S[1]);
-        const double my = S[4] - (p.z * S[0] - p.x * S[2]);
-        const double mz = S[5] - (p.x * S[1] - p.y * S[0]);
-        const double t = tau[j] + (u.x * mx + u.y * my + u.z * mz);
-        tau[j] = t;
-        if (!isfinite(t)) tbad = true;
-        if (mask[j]) tmax = fmax(tmax, fabs(t));
-    }
-    tmax = block_max(tmax, s_red);
-    const double anybad = block_max(tbad ? 1.0 : 0.0, s_red);
-    if (E[3] > 0.0 || anybad > 0.0) {
-        if (tid == 0) {
-            st->e_elec = E[0]; st->e_vdw = E[1]; st->e_cav = E[2];
-            st->status = -4;
-            st->active = 0;
-            *s_flag = 0;
-        }
-        __syncthreads();
-        return;
-    }
-    const double kappa = cd->kappa, s = cd->max_step;
-    double scale;
-    if (cd->step_rule == 1) scale = tmax > 0.0 ? s / tmax : 0.0;
-    else if (cd->step_rule == 2) scale = kappa;
-    else scale = (kappa * tmax > s) ? s / tmax : kappa;
-    double mxd = 0.0;
-#pragma unroll
-    for (int i = 0; i < FK_REG; ++i) {
-        const int j = j0 + i;
-        if (!in_reg || j >= j1) continue;
-        const double d = mask[j] ? scale * tau[j] : 0.0;
-        dtheta[j] = d;
-        mxd = fmax(mxd, fabs(d));
-        double t = th[i] + d;
-        if (t > PI_D) t -= 2.0 * PI_D;
-        if (t <= -PI_D) t += 2.0 * PI_D;
-        th[i] = t;
-        theta[j] = t;
-    }
-    if (!in_reg) {
-        for (int j = j0; j < j1; ++j) {
-            const double d = mask[j] ? scale * tau[j] : 0.0;
-            dtheta[j] = d;
-            mxd = fmax(mxd, fabs(d));
-            double t = theta[j] + d;
-            if (t > PI_D) t -= 2.0 * PI_D;
-            if (t <= -PI_D) t += 2.0 * PI_D;
-            theta[j] = t;
-        }
-    }
-    mxd = block_max(mxd, s_red);
-    if (tid == 0) {
-        st->e_elec = E[0]; st->e_vdw = E[1]; st->e_cav = E[2];
-        st->max_tau = tmax;
-        st->max_dtheta = mxd;
-        st->iterations += 1;
-        if (st->nbr_overflow) st->status = -6;
-        if (st->tol > 0.0 && mxd < st->tol) {
-            st->converged = 1;
-            st->active = 0;
-        }
-        if (st->iterations >= st->iter_limit) st->active = 0;
-        *s_flag = st->active;
-    }
-    __syncthreads();
+    for (int k = 0; k < 3; ++k) y.t[k] = __shfl(x.t[k], src, WAVE);
+    return y;
 }
 
 // Writes the link transform G_{j+1} and the current axis (u_j, p_j) of joint j.
@@ -423,152 +266,47 @@ __device__ __forceinline__ Xf joint_xf_of(const double4 &u, const double4 &p, do
     return x;
 }
 
-// Ordered scan G_j = T_0 o T_1 o ... o T_j over the block for this thread's
-// joints [j0, j1); th[] holds their angles when in_reg.  s_x: [16][12].
-__device__ void fk_phase(const ChainDev *cd, int j0, int j1, const double (&th)[FK_REG], bool in_reg, double (*s_x)[12])
+// Grid of Sec. 3.2 from the per-workgroup bounding boxes of the placed atoms,
+// plus a margin; the cell edge starts at max(cell_min, reach / MAX_REACH) and
+// grows until the grid fits the chain's cell capacity.  Block-wide (any block
+// size); returns false (and a one-cell grid) when the box is not finite or
+// cannot be covered.  s_red: [nw * 6].
+__device__ bool grid_from_parts(const ChainDev *cd, Grid *out, double *s_red, int *s_ok)
 {
-    const double4 *__restrict__ joint0 = cd->joint0;
-    const double *__restrict__ theta = cd->theta;
-    double *__restrict__ xform = cd->xform;
-    double4 *__restrict__ jcur = cd->jcur;
-    const int tid = threadIdx.x, nt = blockDim.x, lane = tid & (WAVE - 1), w = tid / WAVE, nw = nt / WAVE;
-    Xf x = xf_identity();
-    if (in_reg) {
-#pragma unroll
-        for (int i = 0; i < FK_REG; ++i)
-            if (j0 + i < j1) x = xf_mul(x, joint_xf_of(joint0[2 * (j0 + i)], joint0[2 * (j0 + i) + 1], th[i]));
-    } else {
-        for (int j = j0; j < j1; ++j) x = xf_mul(x, joint_xf(joint0, theta, j));
-    }
-#pragma unroll
-    for (int d = 1; d < WAVE; d <<= 1) {
-        Xf y = xf_shfl_up(x, d);
-        if (lane >= d) x = xf_mul(y, x);
-    }
-    if (lane == WAVE - 1) xf_store(s_x[w], x);
-    __syncthreads();
-    if (w == 0) {
-        // ordered scan of the wave totals inside wave 0
-        Xf v = lane < nw ? xf_load(s_x[lane]) : xf_identity();
-#pragma unroll
-        for (int d = 1; d < CHAIN_THREADS / WAVE; d <<= 1) {
-            Xf y = xf_shfl_up(v, d);
-            if (lane >= d) v = xf_mul(y, v);
-        }
-        Xf e = xf_shfl_up(v, 1);
-        if (lane == 0) e = xf_identity();
-        if (lane < nw) xf_store(s_x[lane], e);
-    }
-    __syncthreads();
-    Xf ex = xf_shfl_up(x, 1);
-    if (lane == 0) ex = xf_identity();
-    Xf G = xf_mul(xf_load(s_x[w]), ex);
-    if (in_reg) {
-#pragma unroll
-        for (int i = 0; i < FK_REG; ++i)
-            if (j0 + i < j1) {
-                G = xf_mul(G, joint_xf_of(joint0[2 * (j0 + i)], joint0[2 * (j0 + i) + 1], th[i]));
-                fk_emit(G, j0 + i, joint0, xform, jcur);
-            }
-    } else {
-        for (int j = j0; j < j1; ++j) {
-            G = xf_mul(G, joint_xf(joint0, theta, j));
-            fk_emit(G, j, joint0, xform, jcur);
-        }
-    }
-    if (tid == 0) xf_store(xform, xf_identity());
-    __syncthreads();
-}
-
-__global__ __launch_bounds__(CHAIN_THREADS) void k_chain(Batch bt, int do_post, int do_fk)
-{
-    const ChainDev *cd = bt.table[blockIdx.x];
-    ChainStats *st = cd->stats;
-    if (!st->active) return;
-    __shared__ double s_x[CHAIN_THREADS / WAVE][12];
-    __shared__ double s_w[CHAIN_THREADS / WAVE][6];
-    __shared__ double s_red[CHAIN_THREADS / WAVE * 6];
-    __shared__ int s_flag;
-    __shared__ double s_bb[6];
-    const int tid = threadIdx.x, nt = blockDim.x, lane = tid & (WAVE - 1), w = tid / WAVE, nw = nt / WAVE;
-    if (tid == 0) s_flag = 1;
-    const int J = cd->n_joints;
-    const int chunk = (J + nt - 1) / nt;
-    const int j0 = min(J, tid * chunk), j1 = min(J, j0 + chunk);
-    const bool in_reg = chunk <= FK_REG;
-    double th[FK_REG];
-#pragma unroll
-    for (int i = 0; i < FK_REG; ++i) th[i] = (in_reg && j0 + i < j1) ? cd->theta[j0 + i] : 0.0;
-    __syncthreads();
-    if (do_post && st->pending_post) {
-        post_phase(cd, j0, j1, th, in_reg, &s_flag, s_red, s_w);
-        if (tid == 0) st->pending_post = 0;
-    }
-    if (!do_fk || !s_flag) return;
-    fk_phase(cd, j0, j1, th, in_reg, s_x);
-
-    // bounding box that sizes this iteration's grid
     const int n = cd->n_atoms;
-    if (st->need_grid) {
-        double lo[3] = {DBL_MAX, DBL_MAX, DBL_MAX}, hi[3] = {-DBL_MAX, -DBL_MAX, -DBL_MAX};
-        bool finite = true;
-        for (int a = tid; a < n; a += nt) {
-            const double4 r = place_atom(cd, a);
-            finite = finite && isfinite(r.x) && isfinite(r.y) && isfinite(r.z);
-            lo[0] = fmin(lo[0], r.x); lo[1] = fmin(lo[1], r.y); lo[2] = fmin(lo[2], r.z);
-            hi[0] = fmax(hi[0], r.x); hi[1] = fmax(hi[1], r.y); hi[2] = fmax(hi[2], r.z);
+    const int nblk = (n + ATOM_BLOCK - 1) / ATOM_BLOCK;
+    const int tid = threadIdx.x, nt = blockDim.x, lane = tid & (WAVE - 1), w = tid / WAVE, nw = nt / WAVE;
+    double lo[3] = {DBL_MAX, DBL_MAX, DBL_MAX}, hi[3] = {-DBL_MAX, -DBL_MAX, -DBL_MAX};
+    bool fin = true;
+    for (int b = tid; b < nblk; b += nt)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const double l = cd->bbox_part[6 * b + k], h = cd->bbox_part[6 * b + 3 + k];
+            fin = fin && isfinite(l) && isfinite(h);
+            lo[k] = fmin(lo[k], l);
+            hi[k] = fmax(hi[k], h);
         }
 #pragma unroll
-        for (int k = 0; k < 3; ++k) { lo[k] = wave_min(lo[k]); hi[k] = wave_max(hi[k]); }
-        const int bad_w = __any(!finite);
-        if (lane == 0) {
-            for (int k = 0; k < 3; ++k) { s_red[w * 6 + k] = lo[k]; s_red[w * 6 + 3 + k] = hi[k]; }
-            if (bad_w) s_flag = 0;
-        }
-        __syncthreads();
-        if (tid == 0) {
-            for (int k = 0; k < 3; ++k) { s_bb[k] = DBL_MAX; s_bb[3 + k] = -DBL_MAX; }
-            for (int i = 0; i < nw; ++i)
-                for (int k = 0; k < 3; ++k) {
-                    s_bb[k] = fmin(s_bb[k], s_red[i * 6 + k]);
-                    s_bb[3 + k] = fmax(s_bb[3 + k], s_red[i * 6 + 3 + k]);
-                }
-            if (!s_flag) s_bb[0] = NAN;
-            st->need_grid = 0;
-        }
-    } else {
-        const int nblk = (n + ATOM_BLOCK - 1) / ATOM_BLOCK;
-        double lo[3] = {DBL_MAX, DBL_MAX, DBL_MAX}, hi[3] = {-DBL_MAX, -DBL_MAX, -DBL_MAX};
-        for (int b = tid; b < nblk; b += nt)
-            for (int k = 0; k < 3; ++k) {
-                lo[k] = fmin(lo[k], cd->bbox_part[6 * b + k]);
-                hi[k] = fmax(hi[k], cd->bbox_part[6 * b + 3 + k]);
-            }
-#pragma unroll
-        for (int k = 0; k < 3; ++k) { lo[k] = wave_min(lo[k]); hi[k] = wave_max(hi[k]); }
-        if (lane == 0)
-            for (int k = 0; k < 3; ++k) { s_red[w * 6 + k] = lo[k]; s_red[w * 6 + 3 + k] = hi[k]; }
-        __syncthreads();
-        if (tid == 0) {
-            for (int k = 0; k < 3; ++k) { s_bb[k] = DBL_MAX; s_bb[3 + k] = -DBL_MAX; }
-            for (int i = 0; i < nw; ++i)
-                for (int k = 0; k < 3; ++k) {
-                    s_bb[k] = fmin(s_bb[k], s_red[i * 6 + k]);
-                    s_bb[3 + k] = fmax(s_bb[3 + k], s_red[i * 6 + 3 + k]);
-                }
-        }
+    for (int k = 0; k < 3; ++k) { lo[k] = wave_min(lo[k]); hi[k] = wave_max(hi[k]); }
+    const bool bad_w = __any(!fin);
+    if (tid == 0) *s_ok = 1;
+    __syncthreads();
+    if (lane == 0) {
+        for (int k = 0; k < 3; ++k) { s_red[w * 6 + k] = lo[k]; s_red[w * 6 + 3 + k] = hi[k]; }
+        if (bad_w) *s_ok = 0;
     }
     __syncthreads();
-
     if (tid == 0) {
-        const double reach_len = fmax(cd->cutoff, 2.0 * cd->roff_max + cd->delta_r) + 1e-7;
         double L3[3], H3[3];
-        bool ok = true;
+        bool ok = *s_ok != 0;
         for (int k = 0; k < 3; ++k) {
-            L3[k] = s_bb[k] - GRID_MARGIN;
-            H3[k] = s_bb[3 + k] + GRID_MARGIN;
+            double l = DBL_MAX, h = -DBL_MAX;
+            for (int i = 0; i < nw; ++i) { l = fmin(l, s_red[i * 6 + k]); h = fmax(h, s_red[i * 6 + 3 + k]); }
+            L3[k] = l - GRID_MARGIN;
+            H3[k] = h + GRID_MARGIN;
             ok = ok && isfinite(L3[k]) && isfinite(H3[k]) && H3[k] >= L3[k] && (H3[k] - L3[k]) < 1e7;
         }
+        const double reach_len = fmax(cd->cutoff, 2.0 * cd->roff_max + cd->delta_r) + 1e-7;
         double cell = fmax(cd->cell_min, reach_len / MAX_REACH);
         long long dims[3] = {1, 1, 1};
         for (int it = 0; ok && it < 200; ++it) {
@@ -582,57 +320,315 @@ __global__ __launch_bounds__(CHAIN_THREADS) void k_chain(Batch bt, int do_post, 
         g.cell = cell;
         g.inv_cell = 1.0 / cell;
         g.reach = max(1, (int)ceil(reach_len / cell - 1e-9));
-        g.n_cells = ok ? (int)(dims[0] * dims[1] * dims[2]) : 0;
+        g.n_cells = ok ? (int)(dims[0] * dims[1] * dims[2]) : 1;
         g.pad = 0;
-        *cd->grid = g;
-        s_flag = ok ? g.n_cells : 0;
-        if (!ok) {
-            st->status = -4;
-            st->active = 0;
-        }
+        *out = g;
+        *s_ok = ok ? 1 : 0;
     }
     __syncthreads();
-    const int nc = s_flag;
-    for (int c = tid; c < nc; c += nt) cd->cell_count[c] = 0;
+    return *s_ok != 0;
 }
 
 // ---------------------------------------------------------------------------
-// k_place: positions, cell keys, cell counts, bounding box
+// k_tau: joint torques of the pending forces, one thread per joint
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(ATOM_BLOCK) void k_place(Batch bt)
+// k_wrench left in tau[j] the part of tau_j from the atoms of the workgroup
+// that holds j's first downstream atom, and in wrench_part[b] the wrench sum
+// (F, r x F) of atom workgroup b.  The rest comes from every later workgroup
+// (the row scan of eq 04_9): tau_j += u_j . (T_later - p_j x F_later), eqs
+// KCM_01-KCM_06.
+__global__ __launch_bounds__(JOINT_BLOCK) void k_tau(Batch bt)
+{
+    const int c = find_block_owner(bt.jblk_off, bt.n_chains, blockIdx.x);
+    const ChainDev *cd = bt.table[c];
+    ChainStats *st = cd->stats;
+    if (!st->active || !st->pending_post) return;
+    __shared__ double s_red[(JOINT_BLOCK / WAVE) * 6];
+    __shared__ double s_S[8][6];
+    const int jb = blockIdx.x - bt.jblk_off[c];
+    const int tid = threadIdx.x;
+    const int J = cd->n_joints, n = cd->n_atoms;
+    const int nblk = (n + ATOM_BLOCK - 1) / ATOM_BLOCK;
+    const double *__restrict__ part = cd->wrench_part;
+    // the joints of this workgroup take their later-workgroup wrench after
+    // atom workgroups blo..bhi (at most 6 of them)
+    const int jlo = jb * JOINT_BLOCK, jhi = min(J, jlo + JOINT_BLOCK) - 1;
+    const int blo = first_atom_of_joint(jlo) / ATOM_BLOCK, bhi = first_atom_of_joint(jhi) / ATOM_BLOCK;
+    double v[6] = {0, 0, 0, 0, 0, 0};
+    for (int b = bhi + 1 + tid; b < nblk; b += JOINT_BLOCK)
+#pragma unroll
+        for (int k = 0; k < 6; ++k) v[k] += part[WPART * b + k];
+    block_sum<6>(v, s_red);
+    if (tid == 0) {
+        for (int b = bhi; b >= blo; --b) {
+            for (int k = 0; k < 6; ++k) s_S[b - blo][k] = v[k];
+            for (int k = 0; k < 6; ++k) v[k] += part[WPART * b + k];
+        }
+    }
+    __syncthreads();
+
+    const int j = jlo + tid;
+    double tabs = 0.0, bad = 0.0;
+    if (j < J) {
+        const double *S = s_S[first_atom_of_joint(j) / ATOM_BLOCK - blo];
+        const double4 u = cd->jcur[2 * j], p = cd->jcur[2 * j + 1];
+        const double mx = S[3] - (p.y * S[2] - p.z * S[1]);
+        const double my = S[4] - (p.z * S[0] - p.x * S[2]);
+        const double mz = S[5] - (p.x * S[1] - p.y * S[0]);
+        const double t = cd->tau[j] + (u.x * mx + u.y * my + u.z * mz);
+        cd->tau[j] = t;
+        if (!isfinite(t)) bad = 1.0;
+        if (cd->mask[j]) tabs = fabs(t);
+    }
+    const double tmax = block_max(tabs, s_red);
+    const double anybad = block_max(bad, s_red);
+    if (tid == 0) {
+        cd->tmax_part[jb] = tmax;
+        cd->bad_part[jb] = anybad > 0.0 ? 1 : 0;
+    }
+    if (jb == 0) {
+        // energies and the non-finite force flag of the pending forces
+        double E[4] = {0, 0, 0, 0};
+        for (int b = tid; b < nblk; b += JOINT_BLOCK)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) E[k] += part[WPART * b + 6 + k];
+        block_sum<4>(E, s_red);
+        if (tid == 0) {
+            st->e_elec = E[0];
+            st->e_vdw = E[1];
+            st->e_cav = E[2];
+            st->post_bad = E[3] > 0.0 ? 1 : 0;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_stepfk: compliance step of the pending forces (eq KCM_07), then the
+// kinematics of the new angles inside each joint block (eqs kin_02-kin_04,
+// r1): xform_loc[j] = T_{jlo} o ... o T_j by an ordered scan, and the block
+// product in blk_xf.  k_place composes the products of earlier blocks in
+// front (prefix computation, item 1 of Sec. 3.5).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(JOINT_BLOCK) void k_stepfk(Batch bt, int mode)
+{
+    const int c = find_block_owner(bt.jblk_off, bt.n_chains, blockIdx.x);
+    const ChainDev *cd = bt.table[c];
+    ChainStats *st = cd->stats;
+    if (!st->active) return;
+    if (mode == MODE_BOOT && !st->need_grid) return;
+    __shared__ double s_red[JOINT_BLOCK / WAVE];
+    __shared__ double s_x[JOINT_BLOCK / WAVE][12];
+    const int jb = blockIdx.x - bt.jblk_off[c];
+    const int tid = threadIdx.x, lane = tid & (WAVE - 1), w = tid / WAVE;
+    const int J = cd->n_joints;
+    const int j = jb * JOINT_BLOCK + tid;
+    const bool valid = j < J;
+    double th = valid ? cd->theta[j] : 0.0;
+    const bool lead = jb == 0 && tid == 0;
+
+    if (mode != MODE_BOOT && st->pending_post) {
+        const int nb = (J + JOINT_BLOCK - 1) / JOINT_BLOCK;
+        double tm = 0.0, bad = 0.0;
+        for (int b = tid; b < nb; b += JOINT_BLOCK) {
+            tm = fmax(tm, cd->tmax_part[b]);
+            if (cd->bad_part[b]) bad = 1.0;
+        }
+        tm = block_max(tm, s_red);
+        bad = block_max(bad, s_red);
+        if (bad > 0.0 || st->post_bad) {
+            if (lead) {
+                st->status = -4;
+                st->run = 0;
+            }
+            return;
+        }
+        const double kappa = cd->kappa, smax = cd->max_step;
+        double scale;
+        if (cd->step_rule == 1) scale = tm > 0.0 ? smax / tm : 0.0;
+        else if (cd->step_rule == 2) scale = kappa;
+        else scale = (kappa * tm > smax) ? smax / tm : kappa;
+        if (valid) {
+            const double d = cd->mask[j] ? scale * cd->tau[j] : 0.0;
+            cd->dtheta[j] = d;
+            double t = th + d;
+            if (t > PI_D) t -= 2.0 * PI_D;
+            if (t <= -PI_D) t += 2.0 * PI_D;
+            th = t;
+            cd->theta[j] = t;
+        }
+        if (lead) {
+            // max |dtheta| over the moving joints is scale * max |tau| exactly
+            const double mxd = scale * tm;
+            st->max_tau = tm;
+            st->max_dtheta = mxd;
+            st->iterations += 1;
+            if (st->nbr_overflow) st->status = -6;
+            int go = 1;
+            if (st->tol > 0.0 && mxd < st->tol) {
+                st->converged = 1;
+                go = 0;
+            }
+            if (st->iterations >= st->iter_limit) go = 0;
+            st->run = go;
+        }
+    } else if (lead && mode != MODE_BOOT) {
+        st->run = 1;
+    }
+    if (mode == MODE_FINAL) return;
+
+    Xf x = xf_identity();
+    if (valid) x = joint_xf_of(cd->joint0[2 * j], cd->joint0[2 * j + 1], th);
+#pragma unroll
+    for (int d = 1; d < WAVE; d <<= 1) {
+        Xf y = xf_shfl_up(x, d);
+        if (lane >= d) x = xf_mul(y, x);
+    }
+    if (lane == WAVE - 1) xf_store(s_x[w], x);
+    __syncthreads();
+    if (w > 0) {
+        Xf pre = xf_load(s_x[0]);
+        for (int i = 1; i < w; ++i) pre = xf_mul(pre, xf_load(s_x[i]));
+        x = xf_mul(pre, x);
+    }
+    if (valid) xf_store(cd->xform_loc + 12 * j, x);
+    if (tid == min(J - jb * JOINT_BLOCK, JOINT_BLOCK) - 1) xf_store(cd->blk_xf + 12 * jb, x);
+}
+
+// ---------------------------------------------------------------------------
+// k_place: link transforms of this workgroup's links, positions
+// r_a = G_link(a) r0_a, cell keys and counts, bounding box
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(ATOM_BLOCK) void k_place(Batch bt, int mode)
 {
     const int c = find_block_owner(bt.blk_off, bt.n_chains, blockIdx.x);
     ChainDev *cd = bt.table[c];
-    if (!cd->stats->active) return;
-    const int a = (blockIdx.x - bt.blk_off[c]) * ATOM_BLOCK + threadIdx.x;
+    ChainStats *st = cd->stats;
+    const int lb = blockIdx.x - bt.blk_off[c];
+    // the step and torque kernels of this iteration have consumed the pending forces
+    if (mode == MODE_ITER && lb == 0 && threadIdx.x == 0) st->pending_post = 0;
+    if (mode == MODE_BOOT ? !(st->active && st->need_grid) : !st->run) return;
+    __shared__ double s_G[LINKS_PER_BLOCK][12];
+    __shared__ double s_c[2][12];
+    __shared__ double s_bb[ATOM_BLOCK / WAVE][6];
+    __shared__ int s_bad[ATOM_BLOCK / WAVE];
+    const int tid = threadIdx.x, lane = tid & (WAVE - 1), w = tid / WAVE;
     const int n = cd->n_atoms;
+    const int a0 = lb * ATOM_BLOCK, a1 = min(n, a0 + ATOM_BLOCK) - 1;
+    const int l_lo = link_of_atom(a0), l_hi = link_of_atom(a1);
+    // link l (>= 1) needs the product of the joint blocks before joint l-1
+    const int jb_lo = (max(l_lo, 1) - 1) / JOINT_BLOCK, jb_hi = (max(l_hi, 1) - 1) / JOINT_BLOCK;
+    if (w == 0) {
+        Xf acc = xf_identity();
+        for (int base = 0; base < jb_hi; base += WAVE) {
+            Xf x = (base + lane < jb_hi) ? xf_load(cd->blk_xf + 12 * (base + lane)) : xf_identity();
+#pragma unroll
+            for (int d = 1; d < WAVE; d <<= 1) {
+                Xf y = xf_shfl_up(x, d);
+                if (lane >= d) x = xf_mul(y, x);
+            }
+            if (base > 0) x = xf_mul(acc, x);
+            if (base + lane == jb_lo - 1) xf_store(s_c[0], x);
+            if (base + lane == jb_hi - 1) xf_store(s_c[1], x);
+            acc = xf_shfl_idx(x, WAVE - 1);
+        }
+        if (lane == 0) {
+            if (jb_lo == 0) xf_store(s_c[0], xf_identity());
+            if (jb_hi == 0) xf_store(s_c[1], xf_identity());
+        }
+    }
+    __syncthreads();
+    const int nL = l_hi - l_lo + 1;
+    for (int t = tid; t < nL; t += ATOM_BLOCK) {
+        const int l = l_lo + t;
+        Xf G = xf_identity();
+        if (l > 0) {
+            const int j = l - 1;
+            G = xf_mul(xf_load(s_c[j / JOINT_BLOCK == jb_lo ? 0 : 1]), xf_load(cd->xform_loc + 12 * j));
+        }
+        xf_store(s_G[t], G);
+        const int fa = first_atom_of_link(l);
+        if (fa >= a0 && fa <= a1) {
+            if (l == 0) xf_store(cd->xform, G);
+            else fk_emit(G, l - 1, cd->joint0, cd->xform, cd->jcur);
+        }
+    }
+    __syncthreads();
+
+    const int a = a0 + tid;
     double lo[3] = {DBL_MAX, DBL_MAX, DBL_MAX}, hi[3] = {-DBL_MAX, -DBL_MAX, -DBL_MAX};
-    if (a < n) {
-        const Grid g = *cd->grid;
-        const double4 r = place_atom(cd, a);
+    bool fin = true;
+    if (a <= a1) {
+        const double *L = s_G[link_of_atom(a) - l_lo];
+        const double4 q = cd->r0[a];
+        double4 r;
+        r.x = L[0] * q.x + L[1] * q.y + L[2] * q.z + L[9];
+        r.y = L[3] * q.x + L[4] * q.y + L[5] * q.z + L[10];
+        r.z = L[6] * q.x + L[7] * q.y + L[8] * q.z + L[11];
+        r.w = 0.0;
         cd->r[a] = r;
-        const int key = cell_of(g, r);
-        cd->cell_key[a] = key;
-        atomicAdd(&cd->cell_count[key], 1);
-        cd->f_cav[3 * a] = 0;
-        cd->f_cav[3 * a + 1] = 0;
-        cd->f_cav[3 * a + 2] = 0;
+        fin = isfinite(r.x) && isfinite(r.y) && isfinite(r.z);
+        if (mode == MODE_ITER) {
+            const Grid g = *cd->grid;
+            const int key = cell_of(g, r);
+            cd->cell_key[a] = key;
+            atomicAdd(&cd->cell_count[key], 1);
+            cd->f_cav[3 * a] = 0;
+            cd->f_cav[3 * a + 1] = 0;
+            cd->f_cav[3 * a + 2] = 0;
+        }
         lo[0] = r.x; lo[1] = r.y; lo[2] = r.z;
         hi[0] = r.x; hi[1] = r.y; hi[2] = r.z;
     }
-    __shared__ double s_bb[ATOM_BLOCK / WAVE][6];
-    const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
 #pragma unroll
     for (int k = 0; k < 3; ++k) { lo[k] = wave_min(lo[k]); hi[k] = wave_max(hi[k]); }
-    if (lane == 0)
+    const bool bad_w = __any(!fin);
+    if (lane == 0) {
         for (int k = 0; k < 3; ++k) { s_bb[w][k] = lo[k]; s_bb[w][3 + k] = hi[k]; }
-    __syncthreads();
-    if (threadIdx.x < 6) {
-        const int k = threadIdx.x;
-        double v = s_bb[0][k];
-        for (int i = 1; i < ATOM_BLOCK / WAVE; ++i) v = (k < 3) ? fmin(v, s_bb[i][k]) : fmax(v, s_bb[i][k]);
-        cd->bbox_part[6 * (blockIdx.x - bt.blk_off[c]) + k] = v;
+        s_bad[w] = bad_w ? 1 : 0;
     }
+    __syncthreads();
+    if (tid < 6) {
+        const int k = tid;
+        double v = s_bb[0][k];
+        int bad = s_bad[0];
+        for (int i = 1; i < ATOM_BLOCK / WAVE; ++i) {
+            v = (k < 3) ? fmin(v, s_bb[i][k]) : fmax(v, s_bb[i][k]);
+            bad |= s_bad[i];
+        }
+        cd->bbox_part[6 * lb + k] = bad ? NAN : v;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_gridboot: first grid of a chain whose conformation has no grid yet
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(CHAIN_THREADS) void k_gridboot(Batch bt)
+{
+    ChainDev *cd = bt.table[blockIdx.x];
+    ChainStats *st = cd->stats;
+    if (!st->active || !st->need_grid) return;
+    __shared__ double s_red[CHAIN_THREADS / WAVE * 6];
+    __shared__ int s_ok;
+    const bool ok = grid_from_parts(cd, cd->grid, s_red, &s_ok);
+    if (threadIdx.x == 0) {
+        st->need_grid = 0;
+        if (!ok) {
+            st->status = -4;
+            st->active = 0;
+            st->run = 0;
+        }
+    }
+}
+
+// k_finish: the call's last post phase is applied; the chain's state for the
+// next call is its run flag.
+__global__ void k_finish(Batch bt)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= bt.n_chains) return;
+    ChainStats *st = bt.table[c]->stats;
+    st->pending_post = 0;
+    st->active = st->run;
 }
 
 // ---------------------------------------------------------------------------
@@ -643,11 +639,14 @@ constexpr int SCAN_CHUNK = 16384;
 __global__ __launch_bounds__(CHAIN_THREADS) void k_cellscan(Batch bt)
 {
     const ChainDev *cd = bt.table[blockIdx.x];
-    if (!cd->stats->active) return;
+    ChainStats *st = cd->stats;
+    if (!st->run) return;
     __shared__ int s_cnt[SCAN_CHUNK];
     __shared__ int s_int[CHAIN_THREADS / WAVE];
+    __shared__ double s_red[CHAIN_THREADS / WAVE * 6];
+    __shared__ int s_ok;
     const int nc = cd->grid->n_cells;
-    const int *__restrict__ count = cd->cell_count;
+    int *__restrict__ count = cd->cell_count;
     int *__restrict__ start = cd->cell_start;
     int *__restrict__ cursor = cd->cell_cursor;
     const int tid = threadIdx.x, nt = blockDim.x;
@@ -679,12 +678,18 @@ __global__ __launch_bounds__(CHAIN_THREADS) void k_cellscan(Batch bt)
             if (i < m) {
                 start[c0 + i] = s_cnt[i];
                 cursor[c0 + i] = 0;
+                count[c0 + i] = 0;  // every count is zero again for the next placement
             }
         }
         carry += total;
         __syncthreads();
     }
     if (tid == 0) start[nc] = carry;
+    // the next iteration's grid, from this iteration's bounding box
+    if (!grid_from_parts(cd, cd->grid_next, s_red, &s_ok) && tid == 0) {
+        st->status = -4;
+        st->run = 0;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -698,7 +703,7 @@ __global__ __launch_bounds__(ATOM_BLOCK) void k_scatter(Batch bt)
 {
     const int c = find_block_owner(bt.blk_off, bt.n_chains, blockIdx.x);
     const ChainDev *cd = bt.table[c];
-    if (!cd->stats->active) return;
+    if (!cd->stats->run) return;
     const int a = (blockIdx.x - bt.blk_off[c]) * ATOM_BLOCK + threadIdx.x;
     if (a >= cd->n_atoms) return;
     const int key = cd->cell_key[a];
@@ -709,7 +714,7 @@ __global__ __launch_bounds__(ATOM_BLOCK) void k_rank(Batch bt)
 {
     const int c = find_block_owner(bt.blk_off, bt.n_chains, blockIdx.x);
     const ChainDev *cd = bt.table[c];
-    if (!cd->stats->active) return;
+    if (!cd->stats->run) return;
     const int a = (blockIdx.x - bt.blk_off[c]) * ATOM_BLOCK + threadIdx.x;
     if (a >= cd->n_atoms) return;
     const int key = cd->cell_key[a];
@@ -722,12 +727,14 @@ __global__ __launch_bounds__(ATOM_BLOCK) void k_rank(Batch bt)
     const int pos = b + rank;
     cd->s_idx[pos] = a;
     cd->s_cell[pos] = key;
-    cd->s_r[pos] = r;
+    // the sorted copy carries the atom index in w, so the force kernel reads
+    // position and index with one load
+    cd->s_r[pos] = make_double4(r.x, r.y, r.z, __longlong_as_double((long long)a));
     cd->s_p[pos] = p;
 }
 
 // ---------------------------------------------------------------------------
-// k_force: Coulomb + LJ + SASA enumeration, one workgroup per atom
+// k_force: Coulomb + LJ + SASA enumeration, one wave per atom
 // ---------------------------------------------------------------------------
 // A solvation neighbour j of atom i: offset a = r_j - r_i and the threshold c0 =
 // (R_i^2 + |a|^2 - R_j^2) / (2 R_i): sample q_k = r_i + R_i Q_k is covered by j iff
@@ -737,29 +744,58 @@ struct NbrEntry {
     Real ax, ay, az, c0;
 };
 
+constexpr int SPL = 4;                              // samples per lane in one pass: passes of 256 samples
+constexpr int NSLOT = (MAX_NBR + WAVE - 1) / WAVE;  // neighbours per lane in step 2
+// Step-1 count of a sample: acc = (covering neighbours << ACC_SHIFT) + (sum of
+// their slots), so acc >> ACC_SHIFT == 1 leaves the single overlapper in the
+// low bits; slots below MAX_NBR keep the slot sum below 2^ACC_SHIFT.
+constexpr int ACC_SHIFT = 17;
+static_assert(MAX_NBR * (MAX_NBR - 1) / 2 < (1 << ACC_SHIFT), "slot sum must stay below the count field");
+static_assert(MAX_NBR * 2 < (1 << (31 - ACC_SHIFT)), "count field must not overflow");
+static_assert((2 * MAX_REACH + 1) * (2 * MAX_REACH + 1) <= WAVE, "stencil rows must fit one wave");
+
+__device__ __forceinline__ float bcast(float x, int l)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l));
+}
+__device__ __forceinline__ double bcast(double x, int l)
+{
+    const long long b = __double_as_longlong(x);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(b & 0xffffffffll), l);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+__device__ __forceinline__ long long wave_sum_ll(long long v)
+{
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) v += __shfl_xor(v, d, WAVE);
+    return v;
+}
+
 // FP64 decision in absolute coordinates: is sample k of atom i covered by the
-// offset sphere of sorted atom sj, shifted by delta_r along axis s (s < 0: not
+// offset sphere of atom aj, shifted by delta_r along axis s (s < 0: not
 // shifted)?
-__device__ __forceinline__ bool cover_exact(const ChainDev *cd, const double4 &ri, double roff_i, int k, int sj, int s)
+__device__ __forceinline__ bool cover_exact(const ChainDev *cd, const double4 &ri, double roff_i, int k, int aj, int s)
 {
     const double4 q = cd->q64[k];
     const double qx = ri.x + roff_i * q.x, qy = ri.y + roff_i * q.y, qz = ri.z + roff_i * q.z;
-    double4 c = cd->s_r[sj];
+    double4 c = cd->r[aj];
     if (s == 0) c.x += cd->delta_r;
     if (s == 1) c.y += cd->delta_r;
     if (s == 2) c.z += cd->delta_r;
-    const double rj = cd->s_p[sj].w;
+    const double rj = cd->aparam[aj].w;
     const double dx = qx - c.x, dy = qy - c.y, dz = qz - c.z;
     return dx * dx + dy * dy + dz * dz - rj * rj <= 0.0;
 }
 
+// Coverage by a displaced neighbour, v = (tested quantity) with threshold 0;
+// the mixed form decides again in FP64 inside the band.
 template <typename Real, bool MIXED>
-__device__ __forceinline__ bool test_cover(Real v, Real thr, const ChainDev *cd, const double4 &ri, double roff_i, int k,
-                                           int sj, int s)
+__device__ __forceinline__ bool test_cover(Real v, const ChainDev *cd, const double4 &ri, double roff_i, int k, int aj, int s)
 {
-    bool hit = v >= thr;
+    bool hit = v >= (Real)0;
     if (MIXED) {
-        if (fabsf((float)(v - thr)) <= MIXED_BAND) hit = cover_exact(cd, ri, roff_i, k, sj, s);
+        if (fabsf((float)v) <= MIXED_BAND) hit = cover_exact(cd, ri, roff_i, k, aj, s);
     }
     return hit;
 }
@@ -777,67 +813,50 @@ __device__ __forceinline__ void load_q(const ChainDev *cd, int k, Real &x, Real 
 }
 
 template <typename Real>
-__global__ __launch_bounds__(FORCE_THREADS) void k_force(Batch bt)
+__global__ __launch_bounds__(WAVE) void k_force(Batch bt)
 {
     constexpr bool MIXED = sizeof(Real) == 4;
-    constexpr int MAX_ROWS = (2 * MAX_REACH + 1) * (2 * MAX_REACH + 1);
     __shared__ NbrEntry<Real> s_nbr[MAX_NBR];
-    __shared__ int s_nbr_j[MAX_NBR];
-    __shared__ int s_ev[MAX_NBR * 3];
-    __shared__ int s_row_beg[MAX_ROWS];
-    __shared__ int s_row_off[MAX_ROWS + 1];
-    __shared__ int s_exp[FORCE_THREADS];
-    __shared__ double s_red[(FORCE_THREADS / WAVE) * 5];
-    __shared__ int s_nn, s_ncov, s_nexp;
-    __shared__ unsigned long long s_own[3];
+    __shared__ int s_nbr_a[MAX_NBR];
+    __shared__ int s_ev[3][MAX_NBR];  // net events of each neighbour and axis
 
     const int c = find_block_owner(bt.atom_off, bt.n_chains, blockIdx.x);
     ChainDev *cd = bt.table[c];
-    if (!cd->stats->active) return;
+    if (!cd->stats->run) return;
     const int si = blockIdx.x - bt.atom_off[c];
-    const int tid = threadIdx.x, nt = blockDim.x;
+    const int lane = threadIdx.x;
+    const unsigned long long below = (1ull << lane) - 1ull;
 
     const Grid g = *cd->grid;
     const double4 ri = cd->s_r[si];
     const double4 pi = cd->s_p[si];
-    const int ai = cd->s_idx[si];
+    const int ai = (int)__double_as_longlong(ri.w);
     const int key = cd->s_cell[si];
     const int dxn = g.dims[0], dyn = g.dims[1], dzn = g.dims[2];
     const int cx = key % dxn, cy = (key / dxn) % dyn, cz = key / (dxn * dyn);
     const int R = g.reach, side = 2 * R + 1, nrows = side * side;
 
-    // stencil rows: for each (dy, dz) one contiguous run of cells along x
-    for (int t = tid; t < nrows; t += nt) {
-        const int y = cy + (t % side) - R, z = cz + (t / side) - R;
-        int beg = 0, cnt = 0;
+    // stencil rows, one per lane: for each (dy, dz) one contiguous run of
+    // cells along x, i.e. one contiguous run of the cell-ordered atoms
+    int beg = 0, cnt = 0;
+    if (lane < nrows) {
+        const int y = cy + (lane % side) - R, z = cz + (lane / side) - R;
         if (y >= 0 && y < dyn && z >= 0 && z < dzn) {
             const int xl = max(0, cx - R), xh = min(dxn - 1, cx + R);
             const int base = (z * dyn + y) * dxn;
             beg = cd->cell_start[base + xl];
             cnt = cd->cell_start[base + xh + 1] - beg;
         }
-        s_row_beg[t] = beg;
-        s_row_off[t] = cnt;
     }
-    for (int t = tid; t < 3 * MAX_NBR; t += nt) s_ev[t] = 0;
-    if (tid == 0) {
-        s_nn = 0;
-        s_ncov = 0;
-        s_nexp = 0;
-        s_own[0] = s_own[1] = s_own[2] = 0ull;
+    int off = cnt;
+#pragma unroll
+    for (int d = 1; d < WAVE; d <<= 1) {
+        const int y = __shfl_up(off, d, WAVE);
+        if (lane >= d) off += y;
     }
-    __syncthreads();
-    if (tid == 0) {
-        int run = 0;
-        for (int t = 0; t < nrows; ++t) {
-            const int cnt = s_row_off[t];
-            s_row_off[t] = run;
-            run += cnt;
-        }
-        s_row_off[nrows] = run;
-    }
-    __syncthreads();
-    const int T = s_row_off[nrows];
+    const int T = __shfl(off, WAVE - 1, WAVE);
+    off -= cnt;                   // first candidate number of this row
+    const int rbase = beg - off;  // candidate number k of row t is sorted atom rbase_t + k
 
     const int terms = cd->terms;
     const bool do_elec = terms & 1, do_vdw = terms & 2, do_cav = terms & 4;
@@ -851,29 +870,28 @@ __global__ __launch_bounds__(FORCE_THREADS) void k_force(Batch bt)
     const Real coul = (Real)cd->coulomb;
     const Real qi = (Real)pi.x, Ri = (Real)pi.y, sei = (Real)pi.z;
 
+    // sorted atom of candidate number k: the row is the last one starting at or before k
+    auto cand_atom = [&](int k) -> int {
+        int lo = 0;
+#pragma unroll
+        for (int step = 32; step >= 1; step >>= 1) {
+            const int t = lo + step;
+            const int o = __shfl(off, t & (WAVE - 1), WAVE);
+            if (t < nrows && o <= k) lo = t;
+        }
+        return __shfl(rbase, lo, WAVE) + k;
+    };
+
     Real fx = 0, fy = 0, fz = 0;
     double ee = 0.0, evw = 0.0;
-    for (int k = tid; k < T; k += nt) {
-        int rlo = 0, rhi = nrows;
-        while (rhi - rlo > 1) {
-            const int mid = (rlo + rhi) >> 1;
-            if (s_row_off[mid] <= k) rlo = mid; else rhi = mid;
-        }
-        const int sj = s_row_beg[rlo] + (k - s_row_off[rlo]);
-        if (sj == si) continue;
-        const double4 rj = cd->s_r[sj];
+    int nn = 0;
+    // one candidate: pair terms into (fx, fy, fz, ee, evw); a solvation
+    // neighbour is appended to the list in lane order
+    auto visit = [&](bool valid, const double4 &rj, const double4 &pj) {
         const double ddx = rj.x - ri.x, ddy = rj.y - ri.y, ddz = rj.z - ri.z;
         const double d2 = ddx * ddx + ddy * ddy + ddz * ddz;
-        const bool in_pair = do_pair && d2 <= cut2;
-        bool in_cav = false;
-        double4 pj;
-        if (in_pair || do_cav) pj = cd->s_p[sj];
-        if (do_cav) {
-            const double lim = roff_i + pj.w + dr;
-            in_cav = d2 <= lim * lim;
-        }
-        if (in_pair) {
-            const int aj = cd->s_idx[sj];
+        const int aj = (int)__double_as_longlong(rj.w);
+        if (valid && do_pair && d2 <= cut2) {
             const int res_j = aj / APR, dres = res_j - res_i;
             Real we = do_elec ? (Real)1 : (Real)0, wv = do_vdw ? (Real)1 : (Real)0;
             if (dres >= -1 && dres <= 1) {
@@ -901,116 +919,157 @@ __global__ __launch_bounds__(FORCE_THREADS) void k_force(Batch bt)
                 evw += (double)elj;
             }
         }
+        bool in_cav = false;
+        if (do_cav) {
+            const double lim = roff_i + pj.w + dr;
+            in_cav = valid && d2 <= lim * lim;
+        }
+        const unsigned long long m = __ballot(in_cav);
         if (in_cav) {
-            const int slot = atomicAdd(&s_nn, 1);
-            if (slot < MAX_NBR) {
+            const int pos = nn + __popcll(m & below);
+            if (pos < MAX_NBR) {
                 const double Rj = pj.w;
                 NbrEntry<Real> e;
                 e.ax = (Real)ddx; e.ay = (Real)ddy; e.az = (Real)ddz;
                 e.c0 = (Real)((roff_i * roff_i + d2 - Rj * Rj) / (2.0 * roff_i));
-                s_nbr[slot] = e;
-                s_nbr_j[slot] = sj;
+                s_nbr[pos] = e;
+                s_nbr_a[pos] = aj;
             }
         }
+        nn += __popcll(m);
+    };
+
+    // two candidates per lane per trip, both loads issued before either is used
+    for (int kb = 0; kb < T; kb += 2 * WAVE) {
+        const int k0 = kb + lane, k1 = kb + WAVE + lane;
+        const int sj0 = cand_atom(k0), sj1 = cand_atom(k1);
+        const bool v0 = k0 < T && sj0 != si, v1 = k1 < T && sj1 != si;
+        const int l0 = k0 < T ? sj0 : si, l1 = k1 < T ? sj1 : si;
+        const double4 rj0 = cd->s_r[l0], pj0 = cd->s_p[l0];
+        const double4 rj1 = cd->s_r[l1], pj1 = cd->s_p[l1];
+        visit(v0, rj0, pj0);
+        visit(v1, rj1, pj1);
     }
 
-    // pair force and energy of atom i (each unordered pair is seen from both ends)
+    // pair force and energies of atom i (each unordered pair is seen from both ends)
     double pv[5] = {(double)fx, (double)fy, (double)fz, ee, evw};
-    block_sum<5>(pv, s_red);
+#pragma unroll
+    for (int k = 0; k < 5; ++k) pv[k] = wave_sum(pv[k]);
 
     double e_cav = 0.0, n_exp = -1.0;
     if (do_cav) {
-        const int nn_all = s_nn;
-        const int nn = min(nn_all, MAX_NBR);
-        if (nn_all > MAX_NBR && tid == 0) cd->stats->nbr_overflow = 1;
+        if (nn > MAX_NBR && lane == 0) cd->stats->nbr_overflow = 1;
+        const int nnc = min(nn, MAX_NBR);
         const int N = cd->n_samples;
         const Real drr = (Real)dr;
         // displaced copy of j along e_s covers the sample iff
-        //   dot + dr Q_s >= c0 + dr^2/(2 R_i) + (dr/R_i) a_s
+        //   dot + dr Q_s - c0 - dr^2/(2 R_i) - (dr/R_i) a_s >= 0
         const Real kq = (Real)(dr * dr / (2.0 * roff_i)), k1 = (Real)(dr / roff_i);
-        int ncov = 0;
-        for (int kb = 0; kb < N; kb += nt) {
-            if (kb > 0) {
-                if (tid == 0) s_nexp = 0;
-                __syncthreads();
-            }
-            const int k = kb + tid;
-            if (k < N) {
-                Real Qx, Qy, Qz;
-                load_q<Real>(cd, k, Qx, Qy, Qz);
-                // step 1: acc = 65536 * (covering neighbours) + (sum of their slots), so
-                // acc >> 16 == 1 leaves the single overlapper in the low bits
-                int acc = 0;
-                Real amin = (Real)1e30;
-                for (int u = 0; u < nn; ++u) {
-                    const NbrEntry<Real> e = s_nbr[u];
-                    const Real t = fma(Qz, e.az, fma(Qy, e.ay, fma(Qx, e.ax, -e.c0)));
-                    acc += (t >= (Real)0) ? (65536 + u) : 0;
-                    if (MIXED) amin = fmin(amin, fabs(t));
-                }
-                if (MIXED && amin <= (Real)MIXED_BAND) {
-                    acc = 0;
-                    for (int u = 0; u < nn; ++u)
-                        if (cover_exact(cd, ri, roff_i, k, s_nbr_j[u], -1)) acc += 65536 + u;
-                }
-                const int C = acc >> 16;
-                if (C == 0) {
-                    s_exp[atomicAdd(&s_nexp, 1)] = k;
-                } else if (C == 1) {
-                    // critically overlapped: only the overlapper's shifted copies can expose it
-                    const int u = acc & 0xFFFF;
-                    const NbrEntry<Real> e = s_nbr[u];
-                    const Real base = Qx * e.ax + Qy * e.ay + Qz * e.az - e.c0 - kq;
-                    if (!test_cover<Real, MIXED>(base + drr * Qx - k1 * e.ax, (Real)0, cd, ri, roff_i, k, s_nbr_j[u], 0)) atomicAdd(&s_ev[3 * u + 0], 1);
-                    if (!test_cover<Real, MIXED>(base + drr * Qy - k1 * e.ay, (Real)0, cd, ri, roff_i, k, s_nbr_j[u], 1)) atomicAdd(&s_ev[3 * u + 1], 1);
-                    if (!test_cover<Real, MIXED>(base + drr * Qz - k1 * e.az, (Real)0, cd, ri, roff_i, k, s_nbr_j[u], 2)) atomicAdd(&s_ev[3 * u + 2], 1);
-                }
-                if (C >= 1) ++ncov;
-            }
-            __syncthreads();
-            // step 2 for the exposed samples of this batch: every (sample, neighbour) pair
-            const int nexp = s_nexp;
-            const int work = nexp * nn;
-            for (int wi = tid; wi < work; wi += nt) {
-                const int e_i = wi / nn, u = wi - e_i * nn;
-                const int k = s_exp[e_i];
-                Real Qx, Qy, Qz;
-                load_q<Real>(cd, k, Qx, Qy, Qz);
-                const NbrEntry<Real> e = s_nbr[u];
-                const Real base = Qx * e.ax + Qy * e.ay + Qz * e.az - e.c0 - kq;
-                if (test_cover<Real, MIXED>(base + drr * Qx - k1 * e.ax, (Real)0, cd, ri, roff_i, k, s_nbr_j[u], 0)) atomicAdd(&s_ev[3 * u + 0], -1);
-                if (test_cover<Real, MIXED>(base + drr * Qy - k1 * e.ay, (Real)0, cd, ri, roff_i, k, s_nbr_j[u], 1)) atomicAdd(&s_ev[3 * u + 1], -1);
-                if (test_cover<Real, MIXED>(base + drr * Qz - k1 * e.az, (Real)0, cd, ri, roff_i, k, s_nbr_j[u], 2)) atomicAdd(&s_ev[3 * u + 2], -1);
-            }
-            __syncthreads();
-        }
-        ncov = wave_sum_i(ncov);
-        if ((tid & (WAVE - 1)) == 0) atomicAdd(&s_ncov, ncov);
+        for (int u = lane; u < nnc; u += WAVE) s_ev[0][u] = s_ev[1][u] = s_ev[2][u] = 0;
         __syncthreads();
+        int ncov = 0;
+        for (int kb = 0; kb < N; kb += WAVE * SPL) {
+            // step 1: coverage counts of SPL samples per lane
+            Real Qx[SPL], Qy[SPL], Qz[SPL], amin[SPL];
+            int acc[SPL];
+#pragma unroll
+            for (int i = 0; i < SPL; ++i) {
+                const int k = kb + lane + WAVE * i;
+                Qx[i] = Qy[i] = Qz[i] = (Real)0;
+                if (k < N) load_q<Real>(cd, k, Qx[i], Qy[i], Qz[i]);
+                acc[i] = 0;
+                amin[i] = (Real)1e30;
+            }
+            for (int u = 0; u < nnc; ++u) {
+                const NbrEntry<Real> e = s_nbr[u];
+                const int inc = (1 << ACC_SHIFT) + u;
+#pragma unroll
+                for (int i = 0; i < SPL; ++i) {
+                    const Real t = fma(Qz[i], e.az, fma(Qy[i], e.ay, fma(Qx[i], e.ax, -e.c0)));
+                    acc[i] += (t >= (Real)0) ? inc : 0;
+                    if (MIXED) amin[i] = fmin(amin[i], fabs(t));
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < SPL; ++i) {
+                const int k = kb + lane + WAVE * i;
+                const bool valid = k < N;
+                if (MIXED && valid && amin[i] <= (Real)MIXED_BAND) {
+                    int a2 = 0;
+                    for (int u = 0; u < nnc; ++u)
+                        if (cover_exact(cd, ri, roff_i, k, s_nbr_a[u], -1)) a2 += (1 << ACC_SHIFT) + u;
+                    acc[i] = a2;
+                }
+                const int C = acc[i] >> ACC_SHIFT;
+                if (valid && C == 1) {
+                    // critically overlapped: only the overlapper's shifted copies can expose it
+                    const int u = acc[i] & ((1 << ACC_SHIFT) - 1);
+                    const NbrEntry<Real> e = s_nbr[u];
+                    const int aj = s_nbr_a[u];
+                    const Real base = Qx[i] * e.ax + Qy[i] * e.ay + Qz[i] * e.az - e.c0 - kq;
+                    if (!test_cover<Real, MIXED>(base + drr * Qx[i] - k1 * e.ax, cd, ri, roff_i, k, aj, 0)) atomicAdd(&s_ev[0][u], 1);
+                    if (!test_cover<Real, MIXED>(base + drr * Qy[i] - k1 * e.ay, cd, ri, roff_i, k, aj, 1)) atomicAdd(&s_ev[1][u], 1);
+                    if (!test_cover<Real, MIXED>(base + drr * Qz[i] - k1 * e.az, cd, ri, roff_i, k, aj, 2)) atomicAdd(&s_ev[2][u], 1);
+                }
+                if (valid && C >= 1) ++ncov;
+                // step 2 for the exposed samples of this slot: one lane per
+                // neighbour, the samples broadcast from their lanes
+                const unsigned long long em0 = __ballot(valid && C == 0);
+                if (em0) {
+#pragma unroll
+                    for (int v = 0; v < NSLOT; ++v) {
+                        if (WAVE * v >= nnc) break;
+                        const int u = lane + WAVE * v;
+                        const bool own = u < nnc;
+                        const NbrEntry<Real> e = s_nbr[own ? u : 0];
+                        const int aj = s_nbr_a[own ? u : 0];
+                        int d0 = 0, d1 = 0, d2 = 0;
+                        unsigned long long em = em0;
+                        while (em) {
+                            const int l = __ffsll((long long)em) - 1;
+                            em &= em - 1;
+                            const Real qx = bcast(Qx[i], l), qy = bcast(Qy[i], l), qz = bcast(Qz[i], l);
+                            if (own) {
+                                const int kx = kb + l + WAVE * i;
+                                const Real base = qx * e.ax + qy * e.ay + qz * e.az - e.c0 - kq;
+                                if (test_cover<Real, MIXED>(base + drr * qx - k1 * e.ax, cd, ri, roff_i, kx, aj, 0)) --d0;
+                                if (test_cover<Real, MIXED>(base + drr * qy - k1 * e.ay, cd, ri, roff_i, kx, aj, 1)) --d1;
+                                if (test_cover<Real, MIXED>(base + drr * qz - k1 * e.az, cd, ri, roff_i, kx, aj, 2)) --d2;
+                            }
+                        }
+                        if (d0) atomicAdd(&s_ev[0][u], d0);
+                        if (d1) atomicAdd(&s_ev[1][u], d1);
+                        if (d2) atomicAdd(&s_ev[2][u], d2);
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        ncov = wave_sum_i(ncov);
 
         // eq F_cav_patch: atom i gains G0_i ev / (N dr) per axis, neighbour j the opposite
         const long long qf = cd->qfix[ai];
         long long own0 = 0, own1 = 0, own2 = 0;
-        for (int u = tid; u < nn; u += nt) {
-            const int e0 = s_ev[3 * u], e1 = s_ev[3 * u + 1], e2 = s_ev[3 * u + 2];
+        for (int u = lane; u < nnc; u += WAVE) {
+            const int e0 = s_ev[0][u], e1 = s_ev[1][u], e2 = s_ev[2][u];
             if (!(e0 | e1 | e2)) continue;
-            const int aj = cd->s_idx[s_nbr_j[u]];
-            if (e0) { const long long v = (long long)e0 * qf; own0 += v; atomicAdd((unsigned long long *)&cd->f_cav[3 * aj + 0], (unsigned long long)(-v)); }
-            if (e1) { const long long v = (long long)e1 * qf; own1 += v; atomicAdd((unsigned long long *)&cd->f_cav[3 * aj + 1], (unsigned long long)(-v)); }
-            if (e2) { const long long v = (long long)e2 * qf; own2 += v; atomicAdd((unsigned long long *)&cd->f_cav[3 * aj + 2], (unsigned long long)(-v)); }
+            const int aj = s_nbr_a[u];
+            if (e0) { const long long x = (long long)e0 * qf; own0 += x; atomicAdd((unsigned long long *)&cd->f_cav[3 * aj + 0], (unsigned long long)(-x)); }
+            if (e1) { const long long x = (long long)e1 * qf; own1 += x; atomicAdd((unsigned long long *)&cd->f_cav[3 * aj + 1], (unsigned long long)(-x)); }
+            if (e2) { const long long x = (long long)e2 * qf; own2 += x; atomicAdd((unsigned long long *)&cd->f_cav[3 * aj + 2], (unsigned long long)(-x)); }
         }
-        if (own0) atomicAdd(&s_own[0], (unsigned long long)own0);
-        if (own1) atomicAdd(&s_own[1], (unsigned long long)own1);
-        if (own2) atomicAdd(&s_own[2], (unsigned long long)own2);
-        __syncthreads();
-        if (tid == 0) {
-            for (int s = 0; s < 3; ++s)
-                if (s_own[s]) atomicAdd((unsigned long long *)&cd->f_cav[3 * ai + s], s_own[s]);
-            e_cav = cd->g0[ai] * (double)(N - s_ncov) / (double)N;  // eq G_cav_patch
-            n_exp = (double)(N - s_ncov);
+        own0 = wave_sum_ll(own0);
+        own1 = wave_sum_ll(own1);
+        own2 = wave_sum_ll(own2);
+        if (lane == 0) {
+            if (own0) atomicAdd((unsigned long long *)&cd->f_cav[3 * ai + 0], (unsigned long long)own0);
+            if (own1) atomicAdd((unsigned long long *)&cd->f_cav[3 * ai + 1], (unsigned long long)own1);
+            if (own2) atomicAdd((unsigned long long *)&cd->f_cav[3 * ai + 2], (unsigned long long)own2);
         }
+        e_cav = cd->g0[ai] * (double)(N - ncov) / (double)N;  // eq G_cav_patch
+        n_exp = (double)(N - ncov);
     }
-    if (tid == 0) {
+    if (lane == 0) {
         cd->f_pair[ai] = make_double4(pv[0], pv[1], pv[2], 0.0);
         cd->e_atom[ai] = make_double4(0.5 * pv[3], 0.5 * pv[4], e_cav, n_exp);
     }
@@ -1025,9 +1084,21 @@ __global__ __launch_bounds__(ATOM_BLOCK) void k_wrench(Batch bt)
 {
     const int c = find_block_owner(bt.blk_off, bt.n_chains, blockIdx.x);
     ChainDev *cd = bt.table[c];
-    if (!cd->stats->active) return;
-    __shared__ double s_w[ATOM_BLOCK / WAVE][WPART];
+    ChainStats *st = cd->stats;
     const int lb = blockIdx.x - bt.blk_off[c];
+    if (lb == 0 && threadIdx.x == 0) {
+        // end of the iteration: the chain stays active iff it ran; its forces
+        // await the post phase, and the next grid becomes current
+        const int go = st->run;
+        st->active = go;
+        if (go) {
+            st->pending_post = 1;
+            *cd->grid_last = *cd->grid;
+            *cd->grid = *cd->grid_next;
+        }
+    }
+    if (!st->run) return;
+    __shared__ double s_w[ATOM_BLOCK / WAVE][WPART];
     const int a = lb * ATOM_BLOCK + threadIdx.x;
     const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE, nw = ATOM_BLOCK / WAVE;
     double v[WPART] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
@@ -1082,23 +1153,43 @@ __global__ __launch_bounds__(ATOM_BLOCK) void k_wrench(Batch bt)
         for (int i = 0; i < nw; ++i) t += s_w[i][threadIdx.x];
         cd->wrench_part[WPART * lb + threadIdx.x] = t;
     }
-    if (lb == 0 && threadIdx.x == 0) cd->stats->pending_post = 1;
 }
 
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-hipError_t launch_chain(const Batch &b, int do_post, int do_fk, hipStream_t s)
+hipError_t launch_tau(const Batch &b, hipStream_t s)
 {
-    if (b.n_chains <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_chain, dim3(b.n_chains), dim3(CHAIN_THREADS), 0, s, b, do_post, do_fk);
+    if (b.total_jblocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_tau, dim3(b.total_jblocks), dim3(JOINT_BLOCK), 0, s, b);
     return hipGetLastError();
 }
 
-hipError_t launch_place(const Batch &b, hipStream_t s)
+hipError_t launch_stepfk(const Batch &b, int mode, hipStream_t s)
+{
+    if (b.total_jblocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_stepfk, dim3(b.total_jblocks), dim3(JOINT_BLOCK), 0, s, b, mode);
+    return hipGetLastError();
+}
+
+hipError_t launch_gridboot(const Batch &b, hipStream_t s)
+{
+    if (b.n_chains <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gridboot, dim3(b.n_chains), dim3(CHAIN_THREADS), 0, s, b);
+    return hipGetLastError();
+}
+
+hipError_t launch_finish(const Batch &b, hipStream_t s)
+{
+    if (b.n_chains <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_finish, dim3((b.n_chains + 255) / 256), dim3(256), 0, s, b);
+    return hipGetLastError();
+}
+
+hipError_t launch_place(const Batch &b, int mode, hipStream_t s)
 {
     if (b.total_blocks <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_place, dim3(b.total_blocks), dim3(ATOM_BLOCK), 0, s, b);
+    hipLaunchKernelGGL(k_place, dim3(b.total_blocks), dim3(ATOM_BLOCK), 0, s, b, mode);
     return hipGetLastError();
 }
 
@@ -1134,9 +1225,9 @@ hipError_t launch_force(const Batch &b, int precision, hipStream_t s)
 {
     if (b.total_atoms <= 0) return hipSuccess;
     if (precision == 1)
-        hipLaunchKernelGGL(k_force<float>, dim3(b.total_atoms), dim3(FORCE_THREADS), 0, s, b);
+        hipLaunchKernelGGL(k_force<float>, dim3(b.total_atoms), dim3(WAVE), 0, s, b);
     else
-        hipLaunchKernelGGL(k_force<double>, dim3(b.total_atoms), dim3(FORCE_THREADS), 0, s, b);
+        hipLaunchKernelGGL(k_force<double>, dim3(b.total_atoms), dim3(WAVE), 0, s, b);
     return hipGetLastError();
 }
 

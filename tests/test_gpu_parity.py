@@ -107,6 +107,26 @@ def test_extended_chain_coarsens_grid():
     gpu.free()
 
 
+@pytest.mark.parametrize("m", [129, 9000])
+def test_long_chain_kinematics(m):
+    # 258 joints: two joint blocks; 18000 joints: 71 joint blocks, more than
+    # one wave of block products.  Forces off, so the step is zero and the
+    # positions are the kinematics of theta alone.
+    p = params(kcm.KCM_FP64, terms=0)
+    seed = 90 + m
+    gpu, ref, th = build_pair(m, seed, p)
+    rep = gpu.step(2)
+    st = gpu.state()
+    r, u, _ = oracle.fk(ref, th)
+    scale = max(np.abs(r).max(), 1.0)
+    err = float(np.abs(st["xyz"] - r).max())
+    _log(case="long_fk", m=m, xyz=err, scale=scale, status=rep.status)
+    assert rep.status == 0
+    assert err <= 1e-12 * scale * np.sqrt(2 * m)
+    assert np.array_equal(st["theta"], th)  # zero torque: the angles do not move
+    gpu.free()
+
+
 def test_cell_list_is_a_valid_stable_partition():
     p = params(kcm.KCM_FP64)
     gpu, ref, th = build_pair(80, 71, p)
