@@ -228,7 +228,7 @@ kcm_status check_inputs(const kcm_chain_desc *d, const kcm_params *p)
     if (!(p->cutoff > 0.0) || !(p->delta_r > 0.0) || !(p->r_probe >= 0.0) || !(p->kappa >= 0.0) || !(p->max_step > 0.0))
         return fail(KCM_E_INVAL, "cutoff, delta_r, r_probe, kappa or max_step out of range");
     if (p->n_orbits < 1 || p->n_orbits > 64) return fail(KCM_E_INVAL, "n_orbits must be in 1..64");
-    if ((int)sample_directions(p->n_orbits).size() > 65535) return fail(KCM_E_INVAL, "too many samples");
+    if ((int)sample_directions(p->n_orbits).size() > 32767) return fail(KCM_E_INVAL, "too many samples");
     if (p->step_rule < 0 || p->step_rule > 2) return fail(KCM_E_INVAL, "bad step_rule");
     if (p->precision != KCM_FP64 && p->precision != KCM_MIXED) return fail(KCM_E_INVAL, "bad precision");
     if (p->terms < 0 || p->terms > KCM_TERM_ALL) return fail(KCM_E_INVAL, "bad terms");

@@ -753,6 +753,11 @@ constexpr int ACC_SHIFT = 17;
 static_assert(MAX_NBR * (MAX_NBR - 1) / 2 < (1 << ACC_SHIFT), "slot sum must stay below the count field");
 static_assert(MAX_NBR * 2 < (1 << (31 - ACC_SHIFT)), "count field must not overflow");
 static_assert((2 * MAX_REACH + 1) * (2 * MAX_REACH + 1) <= WAVE, "stencil rows must fit one wave");
+// Net events of one neighbour and axis lie in [-N, N] with N < 2^15 samples:
+// axes 0 and 1 share a word as two halves biased by 2^15 (no carry or borrow
+// crosses the halves), axis 2 has a word of its own.
+constexpr int EV_BIAS = 0x8000;
+constexpr int EV_INIT = EV_BIAS | (EV_BIAS << 16);
 
 __device__ __forceinline__ float bcast(float x, int l)
 {
@@ -818,7 +823,8 @@ __global__ __launch_bounds__(WAVE) void k_force(Batch bt)
     constexpr bool MIXED = sizeof(Real) == 4;
     __shared__ NbrEntry<Real> s_nbr[MAX_NBR];
     __shared__ int s_nbr_a[MAX_NBR];
-    __shared__ int s_ev[3][MAX_NBR];  // net events of each neighbour and axis
+    __shared__ unsigned s_ev01[MAX_NBR];  // net events of each neighbour, axes 0 and 1 (biased halves)
+    __shared__ int s_ev2[MAX_NBR];        // and axis 2
 
     const int c = find_block_owner(bt.atom_off, bt.n_chains, blockIdx.x);
     ChainDev *cd = bt.table[c];
@@ -939,16 +945,26 @@ __global__ __launch_bounds__(WAVE) void k_force(Batch bt)
         nn += __popcll(m);
     };
 
-    // two candidates per lane per trip, both loads issued before either is used
-    for (int kb = 0; kb < T; kb += 2 * WAVE) {
-        const int k0 = kb + lane, k1 = kb + WAVE + lane;
-        const int sj0 = cand_atom(k0), sj1 = cand_atom(k1);
-        const bool v0 = k0 < T && sj0 != si, v1 = k1 < T && sj1 != si;
-        const int l0 = k0 < T ? sj0 : si, l1 = k1 < T ? sj1 : si;
-        const double4 rj0 = cd->s_r[l0], pj0 = cd->s_p[l0];
-        const double4 rj1 = cd->s_r[l1], pj1 = cd->s_p[l1];
-        visit(v0, rj0, pj0);
-        visit(v1, rj1, pj1);
+    // CPT candidates per lane per trip, every load issued before any is used
+    constexpr int CPT = 4;
+    for (int kb = 0; kb < T; kb += CPT * WAVE) {
+        int sj[CPT];
+        bool ok[CPT];
+        double4 rj[CPT], pj[CPT];
+#pragma unroll
+        for (int q = 0; q < CPT; ++q) {
+            const int k = kb + q * WAVE + lane;
+            sj[q] = cand_atom(k);
+            ok[q] = k < T && sj[q] != si;
+            if (k >= T) sj[q] = si;
+        }
+#pragma unroll
+        for (int q = 0; q < CPT; ++q) {
+            rj[q] = cd->s_r[sj[q]];
+            pj[q] = cd->s_p[sj[q]];
+        }
+#pragma unroll
+        for (int q = 0; q < CPT; ++q) visit(ok[q], rj[q], pj[q]);
     }
 
     // pair force and energies of atom i (each unordered pair is seen from both ends)
@@ -965,7 +981,10 @@ __global__ __launch_bounds__(WAVE) void k_force(Batch bt)
         // displaced copy of j along e_s covers the sample iff
         //   dot + dr Q_s - c0 - dr^2/(2 R_i) - (dr/R_i) a_s >= 0
         const Real kq = (Real)(dr * dr / (2.0 * roff_i)), k1 = (Real)(dr / roff_i);
-        for (int u = lane; u < nnc; u += WAVE) s_ev[0][u] = s_ev[1][u] = s_ev[2][u] = 0;
+        for (int u = lane; u < nnc; u += WAVE) {
+            s_ev01[u] = EV_INIT;
+            s_ev2[u] = 0;
+        }
         __syncthreads();
         int ncov = 0;
         for (int kb = 0; kb < N; kb += WAVE * SPL) {
@@ -994,11 +1013,20 @@ __global__ __launch_bounds__(WAVE) void k_force(Batch bt)
             for (int i = 0; i < SPL; ++i) {
                 const int k = kb + lane + WAVE * i;
                 const bool valid = k < N;
-                if (MIXED && valid && amin[i] <= (Real)MIXED_BAND) {
-                    int a2 = 0;
-                    for (int u = 0; u < nnc; ++u)
-                        if (cover_exact(cd, ri, roff_i, k, s_nbr_a[u], -1)) a2 += (1 << ACC_SHIFT) + u;
-                    acc[i] = a2;
+                if (MIXED) {
+                    // a test within the band of its threshold: the whole wave
+                    // recounts that sample in FP64, one lane per neighbour
+                    unsigned long long bm = __ballot(valid && amin[i] <= (Real)MIXED_BAND);
+                    while (bm) {
+                        const int l = __ffsll((long long)bm) - 1;
+                        bm &= bm - 1;
+                        const int kl = kb + l + WAVE * i;
+                        int part = 0;
+                        for (int u = lane; u < nnc; u += WAVE)
+                            if (cover_exact(cd, ri, roff_i, kl, s_nbr_a[u], -1)) part += (1 << ACC_SHIFT) + u;
+                        part = wave_sum_i(part);
+                        if (lane == l) acc[i] = part;
+                    }
                 }
                 const int C = acc[i] >> ACC_SHIFT;
                 if (valid && C == 1) {
@@ -1007,9 +1035,11 @@ __global__ __launch_bounds__(WAVE) void k_force(Batch bt)
                     const NbrEntry<Real> e = s_nbr[u];
                     const int aj = s_nbr_a[u];
                     const Real base = Qx[i] * e.ax + Qy[i] * e.ay + Qz[i] * e.az - e.c0 - kq;
-                    if (!test_cover<Real, MIXED>(base + drr * Qx[i] - k1 * e.ax, cd, ri, roff_i, k, aj, 0)) atomicAdd(&s_ev[0][u], 1);
-                    if (!test_cover<Real, MIXED>(base + drr * Qy[i] - k1 * e.ay, cd, ri, roff_i, k, aj, 1)) atomicAdd(&s_ev[1][u], 1);
-                    if (!test_cover<Real, MIXED>(base + drr * Qz[i] - k1 * e.az, cd, ri, roff_i, k, aj, 2)) atomicAdd(&s_ev[2][u], 1);
+                    unsigned inc01 = 0;
+                    if (!test_cover<Real, MIXED>(base + drr * Qx[i] - k1 * e.ax, cd, ri, roff_i, k, aj, 0)) inc01 += 1u;
+                    if (!test_cover<Real, MIXED>(base + drr * Qy[i] - k1 * e.ay, cd, ri, roff_i, k, aj, 1)) inc01 += 1u << 16;
+                    if (inc01) atomicAdd(&s_ev01[u], inc01);
+                    if (!test_cover<Real, MIXED>(base + drr * Qz[i] - k1 * e.az, cd, ri, roff_i, k, aj, 2)) atomicAdd(&s_ev2[u], 1);
                 }
                 if (valid && C >= 1) ++ncov;
                 // step 2 for the exposed samples of this slot: one lane per
@@ -1037,9 +1067,11 @@ __global__ __launch_bounds__(WAVE) void k_force(Batch bt)
                                 if (test_cover<Real, MIXED>(base + drr * qz - k1 * e.az, cd, ri, roff_i, kx, aj, 2)) --d2;
                             }
                         }
-                        if (d0) atomicAdd(&s_ev[0][u], d0);
-                        if (d1) atomicAdd(&s_ev[1][u], d1);
-                        if (d2) atomicAdd(&s_ev[2][u], d2);
+                        // the lane owns neighbour u here, but critical samples of
+                        // other lanes add to the same words: keep atomics
+                        const unsigned dec01 = (unsigned)d0 + ((unsigned)d1 << 16);
+                        if (dec01) atomicAdd(&s_ev01[u], dec01);
+                        if (d2) atomicAdd(&s_ev2[u], d2);
                     }
                 }
             }
@@ -1051,7 +1083,8 @@ __global__ __launch_bounds__(WAVE) void k_force(Batch bt)
         const long long qf = cd->qfix[ai];
         long long own0 = 0, own1 = 0, own2 = 0;
         for (int u = lane; u < nnc; u += WAVE) {
-            const int e0 = s_ev[0][u], e1 = s_ev[1][u], e2 = s_ev[2][u];
+            const unsigned w01 = s_ev01[u];
+            const int e0 = (int)(w01 & 0xffffu) - EV_BIAS, e1 = (int)(w01 >> 16) - EV_BIAS, e2 = s_ev2[u];
             if (!(e0 | e1 | e2)) continue;
             const int aj = s_nbr_a[u];
             if (e0) { const long long x = (long long)e0 * qf; own0 += x; atomicAdd((unsigned long long *)&cd->f_cav[3 * aj + 0], (unsigned long long)(-x)); }

@@ -46,14 +46,17 @@ def test_one_iteration_matches_oracle(precision, m, seed):
 
 
 @pytest.mark.parametrize("precision", PRECISIONS)
-def test_solvation_counts_are_exact(precision):
+@pytest.mark.parametrize("n_orbits", [14, 23])
+def test_solvation_counts_are_exact(precision, n_orbits):
     # the discrete sample decisions are taken in FP64 (mixed: FP32 with an FP64
     # recheck near ties), so the solvation force equals the oracle's to the
-    # fixed-point rounding of the event quantum
-    p = params(precision, terms=kcm.KCM_TERM_CAV)
+    # fixed-point rounding of the event quantum; 23 orbits give more samples
+    # than one pass of the kernel holds (ragged last pass)
+    p = params(precision, terms=kcm.KCM_TERM_CAV, n_orbits=n_orbits)
     gpu, ref, th = build_pair(40, 21, p)
     st, o, err = compare_step(gpu, ref, th, p)
-    _log(case="cav_only", precision=precision, **err)
+    _log(case="cav_only", precision=precision, n_samples=gpu.n_samples, **err)
+    assert n_orbits == 14 or gpu.n_samples > 512
     assert err["margin"] > 1e-10
     assert np.abs(st["force"] - o["F_cav"]).max() < 1e-8
     assert np.abs(st["force"].sum(axis=0)).max() < 1e-8  # every event is +-, exactly
