@@ -153,7 +153,7 @@ std::vector<V3> sample_directions(int n_orb)
 struct Layout {
     size_t desc, stats, grid, theta, dtheta, tau, mask, joint0, jcur, xform, xform_loc, blk_xf, tmax_part, bad_part;
     size_t r0, r, aparam, g0, qfix;
-    size_t cell_key, cell_count, cell_start, cell_cursor, bbox_part, wrench_part, s_r, s_p, s_tmp, s_idx, s_cell;
+    size_t cell_key, cell_count, cell_start, bbox_part, wrench_part, s_r, s_p, s_tmp, s_idx, s_cell;
     size_t f_pair, f_cav;
     size_t e_atom;
     size_t q64, q32;
@@ -200,7 +200,6 @@ Layout make_layout(int m, int n_orb)
     l.cell_key = take(4 * n);
     l.cell_count = take(4 * cap);
     l.cell_start = take(4 * (cap + 1));
-    l.cell_cursor = take(4 * cap);
     const size_t nblk = (n + ATOM_BLOCK - 1) / ATOM_BLOCK;
     l.bbox_part = take(8 * 6 * nblk);
     l.wrench_part = take(8 * WPART * nblk);
@@ -614,7 +613,6 @@ kcm_status kcm_build_chain(const kcm_chain_desc *desc, const kcm_params *params,
     PTR(cell_key, int32_t *);
     PTR(cell_count, int32_t *);
     PTR(cell_start, int32_t *);
-    PTR(cell_cursor, int32_t *);
     PTR(bbox_part, double *);
     PTR(wrench_part, double *);
     PTR(s_r, double4 *);
@@ -897,6 +895,7 @@ kcm_status kcm_set_theta(kcm_chain *c, const double *theta, void *hip_stream)
     if ((st = write_field(&c->h.stats->need_grid, 1, s)) != KCM_OK) return st;
     if ((st = write_field(&c->h.stats->pending_post, 0, s)) != KCM_OK) return st;
     if ((st = write_field(&c->h.stats->run, 1, s)) != KCM_OK) return st;
+    if ((st = write_field(&c->h.stats->grid_bad, 0, s)) != KCM_OK) return st;
     c->boot = true;
     return write_field(&c->h.stats->active, 1, s);
 }

@@ -31,6 +31,8 @@ struct ChainStats {
     int32_t pending_post;          // 1: forces of an iteration await their post phase
     int32_t post_bad;              // set by the torque kernel: a non-finite force in the pending post phase
     int32_t run;                   // 0: the kernels after the step skip this chain in this iteration
+    int32_t grid_bad;              // the next grid could not be sized: the next step stops the chain
+    int32_t pad;
 };
 // active is read by the torque and step kernels and written only at the end of
 // an iteration (or call) from run; run is written by the step kernel and the
@@ -74,9 +76,8 @@ struct ChainDev {
     double *g0;          // [n] 4 pi gamma R_off^2
     long long *qfix;     // [n] event quantum G0/(N dr) in fixed point
     int32_t *cell_key;   // [n] cell of each atom
-    int32_t *cell_count; // [cap] atoms per cell
+    int32_t *cell_count; // [cap] atoms per cell (zero between iterations)
     int32_t *cell_start; // [cap+1]
-    int32_t *cell_cursor;// [cap]
     double *bbox_part;   // [blocks][6] per-workgroup min xyz, max xyz of the placed atoms
     double *wrench_part; // [blocks][WPART] per-workgroup wrench (F, r x F), energies, failure flag
     double4 *s_r;        // [n] positions in cell order

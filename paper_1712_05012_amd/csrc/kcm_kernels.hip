@@ -296,14 +296,20 @@ __device__ bool grid_from_parts(const ChainDev *cd, Grid *out, double *s_red, in
         if (bad_w) *s_ok = 0;
     }
     __syncthreads();
+    if (w == 0) {
+        // wave 0 reduces the wave partials, lane i holding wave i's
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            lo[k] = wave_min(lane < nw ? s_red[lane * 6 + k] : DBL_MAX);
+            hi[k] = wave_max(lane < nw ? s_red[lane * 6 + 3 + k] : -DBL_MAX);
+        }
+    }
     if (tid == 0) {
         double L3[3], H3[3];
         bool ok = *s_ok != 0;
         for (int k = 0; k < 3; ++k) {
-            double l = DBL_MAX, h = -DBL_MAX;
-            for (int i = 0; i < nw; ++i) { l = fmin(l, s_red[i * 6 + k]); h = fmax(h, s_red[i * 6 + 3 + k]); }
-            L3[k] = l - GRID_MARGIN;
-            H3[k] = h + GRID_MARGIN;
+            L3[k] = lo[k] - GRID_MARGIN;
+            H3[k] = hi[k] + GRID_MARGIN;
             ok = ok && isfinite(L3[k]) && isfinite(H3[k]) && H3[k] >= L3[k] && (H3[k] - L3[k]) < 1e7;
         }
         const double reach_len = fmax(cd->cutoff, 2.0 * cd->roff_max + cd->delta_r) + 1e-7;
@@ -354,15 +360,19 @@ __global__ __launch_bounds__(JOINT_BLOCK) void k_tau(Batch bt)
     // atom workgroups blo..bhi (at most 6 of them)
     const int jlo = jb * JOINT_BLOCK, jhi = min(J, jlo + JOINT_BLOCK) - 1;
     const int blo = first_atom_of_joint(jlo) / ATOM_BLOCK, bhi = first_atom_of_joint(jhi) / ATOM_BLOCK;
+    __shared__ double s_P[8][6];
+    if (tid < 6 * (bhi - blo + 1)) s_P[tid / 6][tid % 6] = part[WPART * (blo + tid / 6) + tid % 6];
     double v[6] = {0, 0, 0, 0, 0, 0};
     for (int b = bhi + 1 + tid; b < nblk; b += JOINT_BLOCK)
 #pragma unroll
         for (int k = 0; k < 6; ++k) v[k] += part[WPART * b + k];
     block_sum<6>(v, s_red);
-    if (tid == 0) {
+    if (tid < 6) {
+        // suffix over the touched workgroups, one wrench component per thread
+        double x = v[tid];
         for (int b = bhi; b >= blo; --b) {
-            for (int k = 0; k < 6; ++k) s_S[b - blo][k] = v[k];
-            for (int k = 0; k < 6; ++k) v[k] += part[WPART * b + k];
+            s_S[b - blo][tid] = x;
+            x += s_P[b - blo][tid];
         }
     }
     __syncthreads();
@@ -435,7 +445,7 @@ __global__ __launch_bounds__(JOINT_BLOCK) void k_stepfk(Batch bt, int mode)
         }
         tm = block_max(tm, s_red);
         bad = block_max(bad, s_red);
-        if (bad > 0.0 || st->post_bad) {
+        if (bad > 0.0 || st->post_bad || st->grid_bad) {
             if (lead) {
                 st->status = -4;
                 st->run = 0;
@@ -632,23 +642,18 @@ __global__ void k_finish(Batch bt)
 }
 
 // ---------------------------------------------------------------------------
-// k_cellscan: cell_start = exclusive scan of the counts (LDS chunks, carry)
+// cell list: exclusive scan of the counts, counting-sort scatter, stable
+// order inside each cell, gather into cell order
 // ---------------------------------------------------------------------------
 constexpr int SCAN_CHUNK = 16384;
 
-__global__ __launch_bounds__(CHAIN_THREADS) void k_cellscan(Batch bt)
+// cell_start = exclusive scan of the counts of the current grid, in LDS
+// chunks with a carry.  Block-wide (CHAIN_THREADS); s_buf: SCAN_CHUNK ints.
+__device__ void scan_cells(const ChainDev *cd, int *s_buf, int *s_int)
 {
-    const ChainDev *cd = bt.table[blockIdx.x];
-    ChainStats *st = cd->stats;
-    if (!st->run) return;
-    __shared__ int s_cnt[SCAN_CHUNK];
-    __shared__ int s_int[CHAIN_THREADS / WAVE];
-    __shared__ double s_red[CHAIN_THREADS / WAVE * 6];
-    __shared__ int s_ok;
     const int nc = cd->grid->n_cells;
-    int *__restrict__ count = cd->cell_count;
+    const int *__restrict__ count = cd->cell_count;
     int *__restrict__ start = cd->cell_start;
-    int *__restrict__ cursor = cd->cell_cursor;
     const int tid = threadIdx.x, nt = blockDim.x;
     constexpr int PER = SCAN_CHUNK / CHAIN_THREADS;
     int carry = 0;
@@ -657,48 +662,73 @@ __global__ __launch_bounds__(CHAIN_THREADS) void k_cellscan(Batch bt)
 #pragma unroll
         for (int k = 0; k < PER; ++k) {
             const int i = k * nt + tid;
-            s_cnt[i] = i < m ? count[c0 + i] : 0;
+            s_buf[i] = i < m ? count[c0 + i] : 0;
         }
         __syncthreads();
         int loc = 0;
 #pragma unroll
-        for (int k = 0; k < PER; ++k) loc += s_cnt[tid * PER + k];
+        for (int k = 0; k < PER; ++k) loc += s_buf[tid * PER + k];
         int total = 0;
         int run = carry + block_excl_scan(loc, s_int, &total);
 #pragma unroll
         for (int k = 0; k < PER; ++k) {
-            const int v = s_cnt[tid * PER + k];
-            s_cnt[tid * PER + k] = run;
+            const int v = s_buf[tid * PER + k];
+            s_buf[tid * PER + k] = run;
             run += v;
         }
         __syncthreads();
 #pragma unroll
         for (int k = 0; k < PER; ++k) {
             const int i = k * nt + tid;
-            if (i < m) {
-                start[c0 + i] = s_cnt[i];
-                cursor[c0 + i] = 0;
-                count[c0 + i] = 0;  // every count is zero again for the next placement
-            }
+            if (i < m) start[c0 + i] = s_buf[i];
         }
         carry += total;
         __syncthreads();
     }
     if (tid == 0) start[nc] = carry;
-    // the next iteration's grid, from this iteration's bounding box
-    if (!grid_from_parts(cd, cd->grid_next, s_red, &s_ok) && tid == 0) {
-        st->status = -4;
-        st->run = 0;
+    __syncthreads();
+}
+
+// Slot of atom a in the cell-ordered arrays: the counting-sort scatter took
+// slots from the count (order left to the atomics); the stable slot is the
+// number of atoms of the cell with a smaller index, so everything downstream
+// is deterministic.  Gathers position (with the atom index in w) and
+// parameters into that slot.
+__device__ __forceinline__ void place_sorted(const ChainDev *cd, const int *ids, int a, int key, int b, int e)
+{
+    int rank = 0;
+    for (int s = b; s < e; ++s) rank += ids[s] < a ? 1 : 0;
+    const int pos = b + rank;
+    const double4 r = cd->r[a];
+    cd->s_idx[pos] = a;
+    cd->s_cell[pos] = key;
+    cd->s_r[pos] = make_double4(r.x, r.y, r.z, __longlong_as_double((long long)a));
+    cd->s_p[pos] = cd->aparam[a];
+}
+
+// Next iteration's grid from this iteration's bounding box; a failure stops
+// the chain at its next step.
+__device__ void next_grid(const ChainDev *cd, double *s_red, int *s_ok)
+{
+    if (!grid_from_parts(cd, cd->grid_next, s_red, s_ok) && threadIdx.x == 0) {
+        cd->stats->status = -4;
+        cd->stats->grid_bad = 1;
     }
 }
 
-// ---------------------------------------------------------------------------
-// k_scatter: counting-sort scatter by cell key (slot order inside a cell left
-// to the atomics), then k_rank: each atom takes as its slot the number of
-// atoms of its cell with a smaller index, so the final cell order is stable
-// and everything downstream is deterministic; it gathers positions and
-// parameters into that order.
-// ---------------------------------------------------------------------------
+// k_cellscan: one workgroup per chain; k_scatter and k_rank: one thread per atom.
+__global__ __launch_bounds__(CHAIN_THREADS) void k_cellscan(Batch bt)
+{
+    const ChainDev *cd = bt.table[blockIdx.x];
+    if (!cd->stats->run) return;
+    __shared__ int s_buf[SCAN_CHUNK];
+    __shared__ int s_int[CHAIN_THREADS / WAVE];
+    __shared__ double s_red[CHAIN_THREADS / WAVE * 6];
+    __shared__ int s_ok;
+    scan_cells(cd, s_buf, s_int);
+    next_grid(cd, s_red, &s_ok);
+}
+
 __global__ __launch_bounds__(ATOM_BLOCK) void k_scatter(Batch bt)
 {
     const int c = find_block_owner(bt.blk_off, bt.n_chains, blockIdx.x);
@@ -707,7 +737,7 @@ __global__ __launch_bounds__(ATOM_BLOCK) void k_scatter(Batch bt)
     const int a = (blockIdx.x - bt.blk_off[c]) * ATOM_BLOCK + threadIdx.x;
     if (a >= cd->n_atoms) return;
     const int key = cd->cell_key[a];
-    cd->s_tmp[cd->cell_start[key] + atomicAdd(&cd->cell_cursor[key], 1)] = a;
+    cd->s_tmp[cd->cell_start[key] + atomicSub(&cd->cell_count[key], 1) - 1] = a;
 }
 
 __global__ __launch_bounds__(ATOM_BLOCK) void k_rank(Batch bt)
@@ -718,19 +748,7 @@ __global__ __launch_bounds__(ATOM_BLOCK) void k_rank(Batch bt)
     const int a = (blockIdx.x - bt.blk_off[c]) * ATOM_BLOCK + threadIdx.x;
     if (a >= cd->n_atoms) return;
     const int key = cd->cell_key[a];
-    const double4 r = cd->r[a];
-    const double4 p = cd->aparam[a];
-    const int b = cd->cell_start[key], e = cd->cell_start[key + 1];
-    const int *__restrict__ tmp = cd->s_tmp;
-    int rank = 0;
-    for (int s = b; s < e; ++s) rank += tmp[s] < a ? 1 : 0;
-    const int pos = b + rank;
-    cd->s_idx[pos] = a;
-    cd->s_cell[pos] = key;
-    // the sorted copy carries the atom index in w, so the force kernel reads
-    // position and index with one load
-    cd->s_r[pos] = make_double4(r.x, r.y, r.z, __longlong_as_double((long long)a));
-    cd->s_p[pos] = p;
+    place_sorted(cd, cd->s_tmp, a, key, cd->cell_start[key], cd->cell_start[key + 1]);
 }
 
 // ---------------------------------------------------------------------------

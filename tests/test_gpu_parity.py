@@ -130,9 +130,11 @@ def test_long_chain_kinematics(m):
     gpu.free()
 
 
-def test_cell_list_is_a_valid_stable_partition():
+@pytest.mark.parametrize("m", [80, 1700])
+def test_cell_list_is_a_valid_stable_partition(m):
+    # 800 atoms, and 17000 atoms in an open coil (a larger, sparser grid)
     p = params(kcm.KCM_FP64)
-    gpu, ref, th = build_pair(80, 71, p)
+    gpu, ref, th = build_pair(m, 71, p)
     gpu.step(1)
     c = gpu.cells()
     xyz = gpu.state()["xyz"]
@@ -147,6 +149,17 @@ def test_cell_list_is_a_valid_stable_partition():
         members = order[cs[cidx]:cs[cidx + 1]]
         assert np.all(key[members] == cidx)
         assert np.all(np.diff(members) > 0)  # stable: atom order inside a cell
+    gpu.free()
+
+
+def test_large_open_chain_matches_oracle():
+    # 17000 atoms in a random coil: many atom workgroups and joint blocks
+    p = params(kcm.KCM_MIXED)
+    gpu, ref, th = build_pair(1700, 77, p)
+    st, o, err = compare_step(gpu, ref, th, p)
+    _log(case="large_chain", **err)
+    assert err["margin"] > 1e-10
+    assert err["F"] <= F_TOL and err["dtheta"] <= DTHETA_TOL[kcm.KCM_MIXED]
     gpu.free()
 
 
