@@ -179,7 +179,7 @@ Layout make_layout(int m, int n_orb)
     const size_t n = l.n, J = l.J, L = l.L, N = l.N, cap = l.cap;
     l.desc = take(sizeof(ChainDev));
     l.stats = take(sizeof(ChainStats));
-    l.grid = take(3 * sizeof(Grid));
+    l.grid = take(sizeof(Grid));
     l.theta = take(8 * J);
     l.dtheta = take(8 * J);
     l.tau = take(8 * J);
@@ -626,8 +626,6 @@ kcm_status kcm_build_chain(const kcm_chain_desc *desc, const kcm_params *params,
     PTR(q64, double4 *);
     PTR(q32, float4 *);
     PTR(grid, Grid *);
-    h.grid_next = h.grid + 1;
-    h.grid_last = h.grid + 2;
     PTR(stats, ChainStats *);
 #undef PTR
     c->d_desc = reinterpret_cast<ChainDev *>(base + l.desc);
@@ -916,7 +914,7 @@ kcm_status kcm_get_cells(const kcm_chain *c, void *hip_stream, int32_t *dims, do
     if (!c) return fail(KCM_E_INVAL, "null chain");
     HIP_TRY(hipStreamSynchronize(static_cast<hipStream_t>(hip_stream)));
     Grid g;
-    HIP_TRY(hipMemcpy(&g, c->h.grid_last, sizeof g, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(&g, c->h.grid, sizeof g, hipMemcpyDeviceToHost));
     if (dims) for (int k = 0; k < 3; ++k) dims[k] = g.dims[k];
     if (cell_size) *cell_size = g.cell;
     if (origin) for (int k = 0; k < 3; ++k) origin[k] = g.origin[k];

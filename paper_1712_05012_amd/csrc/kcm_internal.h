@@ -31,17 +31,16 @@ struct ChainStats {
     int32_t pending_post;          // 1: forces of an iteration await their post phase
     int32_t post_bad;              // set by the torque kernel: a non-finite force in the pending post phase
     int32_t run;                   // 0: the kernels after the step skip this chain in this iteration
-    int32_t grid_bad;              // the next grid could not be sized: the next step stops the chain
+    int32_t grid_bad;              // this iteration's grid could not be sized: the chain stops
     int32_t pad;
 };
 // active is read by the torque and step kernels and written only at the end of
-// an iteration (or call) from run; run is written by the step kernel and the
-// cell scan and read by every later kernel.  So no kernel reads a flag that
-// another workgroup of the same kernel may change.
+// an iteration (or call); run (set by the step) and grid_bad (set by the grid
+// workgroups of the step kernel) are read by every later kernel.  So no kernel
+// reads a flag that another workgroup of the same kernel may change.
 
-// A cell grid.  A chain holds three: the one the current iteration's cell list
-// uses, the one sized for the next iteration, and the one of the last
-// completed cell list.
+// The cell grid of the current iteration (sized at its start from the last
+// bounding box).
 struct Grid {
     double origin[3];
     double cell, inv_cell;
@@ -91,8 +90,6 @@ struct ChainDev {
     double4 *q64;        // [N] unit sample directions
     float4 *q32;         // [N]
     Grid *grid;          // grid of the current iteration
-    Grid *grid_next;     // sized from this iteration's positions, used by the next one
-    Grid *grid_last;     // grid of the last completed cell list
     ChainStats *stats;
 };
 

@@ -8,14 +8,15 @@
 //               forward kinematics of the new angles as an ordered prefix
 //               scan of rigid transforms inside each joint block (eqs
 //               kin_02-kin_04, r1; prefix computation item 1 of Sec. 3.5).
+//               One more workgroup per chain sizes the iteration's cell grid
+//               (Sec. 3.2) from the last bounding box plus a margin; atoms
+//               outside it are clamped to the border cells, which keeps every
+//               neighbour within the stencil.
 //   k_place     one thread per atom: link transforms (products of the
 //               earlier joint blocks composed in front of the block-local
 //               ones), r_a = G_link(a) r0_a, cell key on the grid of Sec. 3.2,
 //               cell count, bounding box of the new positions.
-//   k_cellscan  one workgroup per chain: cell starts by an exclusive scan,
-//               and the next iteration's grid, sized from this bounding box
-//               plus a margin (atoms outside it are clamped to the border
-//               cells, which keeps every neighbour within the stencil).
+//   k_cellscan  one workgroup per chain: cell starts by an exclusive scan.
 //   k_scatter   one thread per atom: counting-sort scatter by cell key.
 //   k_rank      one thread per atom: stable slot inside the cell, gather.
 //   k_force     one wave per atom, atoms in cell order: stencil candidates
@@ -201,6 +202,10 @@ __device__ __forceinline__ int find_block_owner(const int32_t *off, int n, int b
     }
     return lo;
 }
+
+// The kernels after the step run a chain iff the step kept it running and its
+// grid for this iteration could be sized.
+__device__ __forceinline__ bool running(const ChainStats *st) { return st->run && !st->grid_bad; }
 
 __device__ __forceinline__ int cell_of(const Grid &g, const double4 &r)
 {
@@ -421,6 +426,21 @@ __global__ __launch_bounds__(JOINT_BLOCK) void k_tau(Batch bt)
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(JOINT_BLOCK) void k_stepfk(Batch bt, int mode)
 {
+    if (blockIdx.x >= bt.total_jblocks) {
+        // one workgroup per chain: this iteration's grid of Sec. 3.2, sized
+        // from the bounding box of the last placement plus a margin, while
+        // the other workgroups step and scan the joints
+        const ChainDev *cg = bt.table[blockIdx.x - bt.total_jblocks];
+        ChainStats *sg = cg->stats;
+        if (mode != MODE_ITER || !sg->active) return;
+        __shared__ double s_gred[JOINT_BLOCK / WAVE * 6];
+        __shared__ int s_ok;
+        if (!grid_from_parts(cg, cg->grid, s_gred, &s_ok) && threadIdx.x == 0) {
+            sg->status = -4;
+            sg->grid_bad = 1;
+        }
+        return;
+    }
     const int c = find_block_owner(bt.jblk_off, bt.n_chains, blockIdx.x);
     const ChainDev *cd = bt.table[c];
     ChainStats *st = cd->stats;
@@ -445,7 +465,7 @@ __global__ __launch_bounds__(JOINT_BLOCK) void k_stepfk(Batch bt, int mode)
         }
         tm = block_max(tm, s_red);
         bad = block_max(bad, s_red);
-        if (bad > 0.0 || st->post_bad || st->grid_bad) {
+        if (bad > 0.0 || st->post_bad) {
             if (lead) {
                 st->status = -4;
                 st->run = 0;
@@ -516,7 +536,7 @@ __global__ __launch_bounds__(ATOM_BLOCK) void k_place(Batch bt, int mode)
     const int lb = blockIdx.x - bt.blk_off[c];
     // the step and torque kernels of this iteration have consumed the pending forces
     if (mode == MODE_ITER && lb == 0 && threadIdx.x == 0) st->pending_post = 0;
-    if (mode == MODE_BOOT ? !(st->active && st->need_grid) : !st->run) return;
+    if (mode == MODE_BOOT ? !(st->active && st->need_grid) : !running(st)) return;
     __shared__ double s_G[LINKS_PER_BLOCK][12];
     __shared__ double s_c[2][12];
     __shared__ double s_bb[ATOM_BLOCK / WAVE][6];
@@ -638,7 +658,7 @@ __global__ void k_finish(Batch bt)
     if (c >= bt.n_chains) return;
     ChainStats *st = bt.table[c]->stats;
     st->pending_post = 0;
-    st->active = st->run;
+    st->active = running(st);
 }
 
 // ---------------------------------------------------------------------------
@@ -646,9 +666,13 @@ __global__ void k_finish(Batch bt)
 // order inside each cell, gather into cell order
 // ---------------------------------------------------------------------------
 constexpr int SCAN_CHUNK = 16384;
+// LDS index of scan element i: one pad word per 32 elements, so the threads of
+// a wave reading their runs of consecutive elements hit different banks
+__device__ __forceinline__ int scan_pad(int i) { return i + (i >> 5); }
+constexpr int SCAN_LDS = SCAN_CHUNK + SCAN_CHUNK / 32;
 
 // cell_start = exclusive scan of the counts of the current grid, in LDS
-// chunks with a carry.  Block-wide (CHAIN_THREADS); s_buf: SCAN_CHUNK ints.
+// chunks with a carry.  Block-wide (CHAIN_THREADS); s_buf: SCAN_LDS ints.
 __device__ void scan_cells(const ChainDev *cd, int *s_buf, int *s_int)
 {
     const int nc = cd->grid->n_cells;
@@ -662,25 +686,25 @@ __device__ void scan_cells(const ChainDev *cd, int *s_buf, int *s_int)
 #pragma unroll
         for (int k = 0; k < PER; ++k) {
             const int i = k * nt + tid;
-            s_buf[i] = i < m ? count[c0 + i] : 0;
+            s_buf[scan_pad(i)] = i < m ? count[c0 + i] : 0;
         }
         __syncthreads();
         int loc = 0;
 #pragma unroll
-        for (int k = 0; k < PER; ++k) loc += s_buf[tid * PER + k];
+        for (int k = 0; k < PER; ++k) loc += s_buf[scan_pad(tid * PER + k)];
         int total = 0;
         int run = carry + block_excl_scan(loc, s_int, &total);
 #pragma unroll
         for (int k = 0; k < PER; ++k) {
-            const int v = s_buf[tid * PER + k];
-            s_buf[tid * PER + k] = run;
+            const int v = s_buf[scan_pad(tid * PER + k)];
+            s_buf[scan_pad(tid * PER + k)] = run;
             run += v;
         }
         __syncthreads();
 #pragma unroll
         for (int k = 0; k < PER; ++k) {
             const int i = k * nt + tid;
-            if (i < m) start[c0 + i] = s_buf[i];
+            if (i < m) start[c0 + i] = s_buf[scan_pad(i)];
         }
         carry += total;
         __syncthreads();
@@ -706,34 +730,21 @@ __device__ __forceinline__ void place_sorted(const ChainDev *cd, const int *ids,
     cd->s_p[pos] = cd->aparam[a];
 }
 
-// Next iteration's grid from this iteration's bounding box; a failure stops
-// the chain at its next step.
-__device__ void next_grid(const ChainDev *cd, double *s_red, int *s_ok)
-{
-    if (!grid_from_parts(cd, cd->grid_next, s_red, s_ok) && threadIdx.x == 0) {
-        cd->stats->status = -4;
-        cd->stats->grid_bad = 1;
-    }
-}
-
 // k_cellscan: one workgroup per chain; k_scatter and k_rank: one thread per atom.
 __global__ __launch_bounds__(CHAIN_THREADS) void k_cellscan(Batch bt)
 {
     const ChainDev *cd = bt.table[blockIdx.x];
-    if (!cd->stats->run) return;
-    __shared__ int s_buf[SCAN_CHUNK];
+    if (!running(cd->stats)) return;
+    __shared__ int s_buf[SCAN_LDS];
     __shared__ int s_int[CHAIN_THREADS / WAVE];
-    __shared__ double s_red[CHAIN_THREADS / WAVE * 6];
-    __shared__ int s_ok;
     scan_cells(cd, s_buf, s_int);
-    next_grid(cd, s_red, &s_ok);
 }
 
 __global__ __launch_bounds__(ATOM_BLOCK) void k_scatter(Batch bt)
 {
     const int c = find_block_owner(bt.blk_off, bt.n_chains, blockIdx.x);
     const ChainDev *cd = bt.table[c];
-    if (!cd->stats->run) return;
+    if (!running(cd->stats)) return;
     const int a = (blockIdx.x - bt.blk_off[c]) * ATOM_BLOCK + threadIdx.x;
     if (a >= cd->n_atoms) return;
     const int key = cd->cell_key[a];
@@ -744,7 +755,7 @@ __global__ __launch_bounds__(ATOM_BLOCK) void k_rank(Batch bt)
 {
     const int c = find_block_owner(bt.blk_off, bt.n_chains, blockIdx.x);
     const ChainDev *cd = bt.table[c];
-    if (!cd->stats->run) return;
+    if (!running(cd->stats)) return;
     const int a = (blockIdx.x - bt.blk_off[c]) * ATOM_BLOCK + threadIdx.x;
     if (a >= cd->n_atoms) return;
     const int key = cd->cell_key[a];
@@ -846,7 +857,7 @@ __global__ __launch_bounds__(WAVE) void k_force(Batch bt)
 
     const int c = find_block_owner(bt.atom_off, bt.n_chains, blockIdx.x);
     ChainDev *cd = bt.table[c];
-    if (!cd->stats->run) return;
+    if (!running(cd->stats)) return;
     const int si = blockIdx.x - bt.atom_off[c];
     const int lane = threadIdx.x;
     const unsigned long long below = (1ull << lane) - 1ull;
@@ -1138,17 +1149,13 @@ __global__ __launch_bounds__(ATOM_BLOCK) void k_wrench(Batch bt)
     ChainStats *st = cd->stats;
     const int lb = blockIdx.x - bt.blk_off[c];
     if (lb == 0 && threadIdx.x == 0) {
-        // end of the iteration: the chain stays active iff it ran; its forces
-        // await the post phase, and the next grid becomes current
-        const int go = st->run;
+        // end of the iteration: the chain stays active iff it ran, and its
+        // forces await the post phase
+        const int go = running(st);
         st->active = go;
-        if (go) {
-            st->pending_post = 1;
-            *cd->grid_last = *cd->grid;
-            *cd->grid = *cd->grid_next;
-        }
+        if (go) st->pending_post = 1;
     }
-    if (!st->run) return;
+    if (!running(st)) return;
     __shared__ double s_w[ATOM_BLOCK / WAVE][WPART];
     const int a = lb * ATOM_BLOCK + threadIdx.x;
     const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE, nw = ATOM_BLOCK / WAVE;
@@ -1219,7 +1226,7 @@ hipError_t launch_tau(const Batch &b, hipStream_t s)
 hipError_t launch_stepfk(const Batch &b, int mode, hipStream_t s)
 {
     if (b.total_jblocks <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_stepfk, dim3(b.total_jblocks), dim3(JOINT_BLOCK), 0, s, b, mode);
+    hipLaunchKernelGGL(k_stepfk, dim3(b.total_jblocks + b.n_chains), dim3(JOINT_BLOCK), 0, s, b, mode);
     return hipGetLastError();
 }
 
