@@ -44,6 +44,7 @@ struct ChainStats {
 struct Grid {
     double origin[3];
     double cell, inv_cell;
+    double reach_len;     // largest interaction distance (pair cutoff or solvation neighbour limit)
     int32_t dims[3];
     int32_t reach;        // stencil half width in cells
     int32_t n_cells;

@@ -331,6 +331,7 @@ __device__ bool grid_from_parts(const ChainDev *cd, Grid *out, double *s_red, in
         g.cell = cell;
         g.inv_cell = 1.0 / cell;
         g.reach = max(1, (int)ceil(reach_len / cell - 1e-9));
+        g.reach_len = reach_len;
         g.n_cells = ok ? (int)(dims[0] * dims[1] * dims[2]) : 1;
         g.pad = 0;
         *out = g;
@@ -872,15 +873,36 @@ __global__ __launch_bounds__(WAVE) void k_force(Batch bt)
     const int R = g.reach, side = 2 * R + 1, nrows = side * side;
 
     // stencil rows, one per lane: for each (dy, dz) one contiguous run of
-    // cells along x, i.e. one contiguous run of the cell-ordered atoms
+    // cells along x, i.e. one contiguous run of the cell-ordered atoms.  The
+    // run keeps only the cells that can hold an atom within reach of atom i:
+    // a row whose y-z slab is farther than the reach is empty, and the x run
+    // covers [x_i - ext, x_i + ext] with ext^2 = reach^2 - (y-z distance)^2.
+    // Border cells reach to infinity outward (atoms outside the grid are
+    // clamped into them); the pad on the reach absorbs rounding.
     int beg = 0, cnt = 0;
     if (lane < nrows) {
         const int y = cy + (lane % side) - R, z = cz + (lane / side) - R;
         if (y >= 0 && y < dyn && z >= 0 && z < dzn) {
-            const int xl = max(0, cx - R), xh = min(dxn - 1, cx + R);
-            const int base = (z * dyn + y) * dxn;
-            beg = cd->cell_start[base + xl];
-            cnt = cd->cell_start[base + xh + 1] - beg;
+            const double reach = g.reach_len + 1e-6;
+            const double ylo = y == 0 ? -DBL_MAX : g.origin[1] + y * g.cell;
+            const double yhi = y == dyn - 1 ? DBL_MAX : g.origin[1] + (y + 1) * g.cell;
+            const double zlo = z == 0 ? -DBL_MAX : g.origin[2] + z * g.cell;
+            const double zhi = z == dzn - 1 ? DBL_MAX : g.origin[2] + (z + 1) * g.cell;
+            const double gy = fmax(0.0, fmax(ylo - ri.y, ri.y - yhi));
+            const double gz = fmax(0.0, fmax(zlo - ri.z, ri.z - zhi));
+            const double rest = reach * reach - gy * gy - gz * gz;
+            if (rest >= 0.0) {
+                const double ext = sqrt(rest);
+                const int xa = (int)floor((ri.x - ext - g.origin[0]) * g.inv_cell);
+                const int xb = (int)floor((ri.x + ext - g.origin[0]) * g.inv_cell);
+                const int xl = max(max(0, cx - R), min(xa, dxn - 1));
+                const int xh = min(min(dxn - 1, cx + R), max(xb, 0));
+                if (xl <= xh) {
+                    const int base = (z * dyn + y) * dxn;
+                    beg = cd->cell_start[base + xl];
+                    cnt = cd->cell_start[base + xh + 1] - beg;
+                }
+            }
         }
     }
     int off = cnt;

@@ -207,8 +207,13 @@ def test_resynchronised_trajectory(precision):
     gpu.free()
 
 
-def test_checkpoint_resume_is_identical():
-    p = params(kcm.KCM_MIXED)
+@pytest.mark.parametrize("precision,tol", [(kcm.KCM_MIXED, 1e-9), (kcm.KCM_FP64, 1e-13)])
+def test_checkpoint_resume(precision, tol):
+    # a chain rebuilt from the angles of iteration 3 continues the trajectory.
+    # Its first grid is sized from its own positions rather than from the
+    # previous iteration's, so the candidate order (and with it the rounding
+    # of the pair sums) may differ: agreement to rounding, not bitwise.
+    p = params(precision)
     seq = synth.sequence(30, 111)
     th = synth.random_dihedrals(30, 111)
     a = kcm.Chain(seq, TYPES, p, theta0=th)
@@ -219,7 +224,9 @@ def test_checkpoint_resume_is_identical():
     mid = b.state()["theta"]
     c = kcm.Chain(seq, TYPES, p, theta0=mid)
     c.step(3)
-    assert np.array_equal(c.state()["theta"], ref)
+    diff = float(np.abs(np.angle(np.exp(1j * (c.state()["theta"] - ref)))).max())
+    _log(case="resume", precision=precision, dtheta=diff)
+    assert diff <= tol
     for x in (a, b, c):
         x.free()
 
