@@ -1032,6 +1032,13 @@ __global__ __launch_bounds__(WAVE) void k_force(Batch bt)
         // displaced copy of j along e_s covers the sample iff
         //   dot + dr Q_s - c0 - dr^2/(2 R_i) - (dr/R_i) a_s >= 0
         const Real kq = (Real)(dr * dr / (2.0 * roff_i)), k1 = (Real)(dr / roff_i);
+        // The shift moves the tested value by drr Q_s - k1 a_s, at most
+        // span = drr + k1 max_s |a_s| either way: an exposed sample whose
+        // undisplaced value is below -span - guard stays exposed for every
+        // axis, a critical one above span + guard stays covered, and their
+        // three tests can be skipped with the same decisions.  guard holds
+        // the FP32 decision band (mixed) or a rounding pad (FP64).
+        const Real guard = MIXED ? (Real)(2.0f * MIXED_BAND) : (Real)1e-9;
         for (int u = lane; u < nnc; u += WAVE) {
             s_ev01[u] = EV_INIT;
             s_ev2[u] = 0;
@@ -1086,11 +1093,14 @@ __global__ __launch_bounds__(WAVE) void k_force(Batch bt)
                     const NbrEntry<Real> e = s_nbr[u];
                     const int aj = s_nbr_a[u];
                     const Real base = Qx[i] * e.ax + Qy[i] * e.ay + Qz[i] * e.az - e.c0 - kq;
-                    unsigned inc01 = 0;
-                    if (!test_cover<Real, MIXED>(base + drr * Qx[i] - k1 * e.ax, cd, ri, roff_i, k, aj, 0)) inc01 += 1u;
-                    if (!test_cover<Real, MIXED>(base + drr * Qy[i] - k1 * e.ay, cd, ri, roff_i, k, aj, 1)) inc01 += 1u << 16;
-                    if (inc01) atomicAdd(&s_ev01[u], inc01);
-                    if (!test_cover<Real, MIXED>(base + drr * Qz[i] - k1 * e.az, cd, ri, roff_i, k, aj, 2)) atomicAdd(&s_ev2[u], 1);
+                    const Real span = drr + k1 * fmax(fabs(e.ax), fmax(fabs(e.ay), fabs(e.az)));
+                    if (base - span <= guard) {
+                        unsigned inc01 = 0;
+                        if (!test_cover<Real, MIXED>(base + drr * Qx[i] - k1 * e.ax, cd, ri, roff_i, k, aj, 0)) inc01 += 1u;
+                        if (!test_cover<Real, MIXED>(base + drr * Qy[i] - k1 * e.ay, cd, ri, roff_i, k, aj, 1)) inc01 += 1u << 16;
+                        if (inc01) atomicAdd(&s_ev01[u], inc01);
+                        if (!test_cover<Real, MIXED>(base + drr * Qz[i] - k1 * e.az, cd, ri, roff_i, k, aj, 2)) atomicAdd(&s_ev2[u], 1);
+                    }
                 }
                 if (valid && C >= 1) ++ncov;
                 // step 2 for the exposed samples of this slot: one lane per
@@ -1104,15 +1114,16 @@ __global__ __launch_bounds__(WAVE) void k_force(Batch bt)
                         const bool own = u < nnc;
                         const NbrEntry<Real> e = s_nbr[own ? u : 0];
                         const int aj = s_nbr_a[own ? u : 0];
+                        const Real lim = -(drr + k1 * fmax(fabs(e.ax), fmax(fabs(e.ay), fabs(e.az)))) - guard;
                         int d0 = 0, d1 = 0, d2 = 0;
                         unsigned long long em = em0;
                         while (em) {
                             const int l = __ffsll((long long)em) - 1;
                             em &= em - 1;
                             const Real qx = bcast(Qx[i], l), qy = bcast(Qy[i], l), qz = bcast(Qz[i], l);
-                            if (own) {
+                            const Real base = qx * e.ax + qy * e.ay + qz * e.az - e.c0 - kq;
+                            if (own && base >= lim) {
                                 const int kx = kb + l + WAVE * i;
-                                const Real base = qx * e.ax + qy * e.ay + qz * e.az - e.c0 - kq;
                                 if (test_cover<Real, MIXED>(base + drr * qx - k1 * e.ax, cd, ri, roff_i, kx, aj, 0)) --d0;
                                 if (test_cover<Real, MIXED>(base + drr * qy - k1 * e.ay, cd, ri, roff_i, kx, aj, 1)) --d1;
                                 if (test_cover<Real, MIXED>(base + drr * qz - k1 * e.az, cd, ri, roff_i, kx, aj, 2)) --d2;
