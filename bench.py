@@ -238,6 +238,9 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=100, help="iterations of the 256-chain batch (0: skip)")
     ap.add_argument("--serve-jobs", type=int, default=48, help="jobs of the serving run (0: skip)")
     ap.add_argument("--serve-max-iter", type=int, default=2000)
+    ap.add_argument("--legs", default="main,companion,batch,serving,cpu",
+                    help="comma-separated legs to run (main, companion, batch, serving, cpu); "
+                         "profiling runs use a subset, the benchmark line needs main")
     ap.add_argument("--no-graphs", action="store_true",
                     help="launch each iteration's kernels directly instead of replaying a HIP graph")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -270,9 +273,28 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
+    legs = set(args.legs.split(","))
+    if args.no_companion:
+        legs.discard("companion")
+    if args.batch_steps <= 0:
+        legs.discard("batch")
+    if args.serve_jobs <= 0:
+        legs.discard("serving")
+    if args.no_cpu_baseline:
+        legs.discard("cpu")
+    if "main" not in legs:
+        # a profiling run of the other legs only
+        line = {"legs": sorted(legs)}
+        if "batch" in legs:
+            line["batched"] = run_batch(args.batch_steps, 5)
+        if "serving" in legs:
+            line["serving"] = run_serving(args.serve_jobs, args.serve_max_iter, 64.0)
+        print(json.dumps(line), flush=True)
+        return
+
     main_run = run_gpu(args.precision, args.steps, args.warmup, args.residues)
     other = "fp64" if args.precision == "mixed" else "mixed"
-    companion = None if args.no_companion else run_gpu(other, args.steps, args.warmup, args.residues)
+    companion = run_gpu(other, args.steps, args.warmup, args.residues) if "companion" in legs else None
 
     u = main_run["units"]
     achieved = u["flops"] / (main_run["force_ms_mean"] * 1e-3) / 1e12
@@ -316,15 +338,15 @@ def main():
                        "force_ms": companion["force_ms_mean"],
                        "frac": companion["units"]["flops"] / (companion["force_ms_mean"] * 1e-3) / 1e12
                        / PEAK_TFLOPS[other]}
-    if args.batch_steps > 0:
+    if "batch" in legs:
         b = run_batch(args.batch_steps, 5)
         fp64 = run_per_chain_fp64(max(5, args.batch_steps // 10))
         b["plain_fp64_per_chain"] = fp64
         b["speedup_vs_plain_fp64_per_chain"] = b["value"] / fp64["value"]
         line["batched"] = b
-    if args.serve_jobs > 0:
+    if "serving" in legs:
         line["serving"] = run_serving(args.serve_jobs, args.serve_max_iter, 64.0)
-    if not args.no_cpu_baseline:
+    if "cpu" in legs:
         line["cpu_baseline"] = cpu_baseline(args.cpu_seconds, args.residues)
     print(json.dumps(line), flush=True)
 

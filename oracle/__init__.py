@@ -12,6 +12,7 @@ from .oracle import (  # noqa: F401
     StepRule,
     build,
     fk,
+    fk_extend,
     fk_prefix,
     iterate,
     pair_forces,

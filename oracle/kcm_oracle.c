@@ -256,6 +256,56 @@ int or_fk(int m, const double *r0, const double *theta, double *r, double *u, do
     return 0;
 }
 
+/* The same kinematics one residue at a time, for preparing inputs (growing a
+ * start conformation): given the rotation Mk of link 2k and the current point
+ * pk of joint 2k (atom N of residue k), place the atoms of links 2k+1 and 2k+2
+ * for angles (phi, psi) = (theta_2k, theta_2k+1): slots 2..9 of residue k and,
+ * if k+1 < m, slots 0..1 of residue k+1, written to pos[10][3] in that order.
+ * Returns in Mn, pn the rotation of link 2k+2 and the point of joint 2k+2.
+ * Each value is computed by the operations of or_fk in the same order, so a
+ * chain grown residue by residue equals or_fk of its angles. */
+int or_fk_extend(int m, const double *r0, int k, const double *Mk, const double *pk, double phi, double psi,
+                 double *pos, double *Mn, double *pn)
+{
+    if (k < 0 || k >= m) return -1;
+    const double *N = r0 + 3 * (APR * k + A_N), *CA = r0 + 3 * (APR * k + A_CA), *Cc = r0 + 3 * (APR * k + A_C);
+    double u0a[3], u0b[3], d[3];
+    v_sub(CA, N, d); v_unit(d, u0a);   /* joint 2k: N -> CA, point N */
+    v_sub(Cc, CA, d); v_unit(d, u0b);  /* joint 2k+1: CA -> C, point CA */
+    double Ra[9], Rb[9], M1[9], M2[9];
+    m_rot(u0a, phi - OR_PI, Ra);
+    m_mul(Mk, Ra, M1);
+    m_rot(u0b, psi - OR_PI, Rb);
+    m_mul(M1, Rb, M2);
+    double b0[3], b[3], p1[3];
+    v_sub(CA, N, b0);
+    m_vec(M1, b0, b);
+    for (int q = 0; q < 3; ++q) p1[q] = pk[q] + b[q];
+    int w = 0;
+    for (int a = APR * k; a < APR * (k + 1) + 2 && a < APR * m; ++a) {
+        const int l = or_link_of_atom(a);
+        if (l != 2 * k + 1 && l != 2 * k + 2) continue;
+        const double *M = l == 2 * k + 1 ? M1 : M2;
+        const double *pc = l == 2 * k + 1 ? pk : p1;
+        const double *p0 = l == 2 * k + 1 ? N : CA;
+        double d0[3], dd[3];
+        v_sub(r0 + 3 * a, p0, d0);
+        m_vec(M, d0, dd);
+        for (int q = 0; q < 3; ++q) pos[3 * w + q] = pc[q] + dd[q];
+        ++w;
+    }
+    memcpy(Mn, M2, sizeof M2);
+    if (k + 1 < m) {
+        double c0[3], c[3];
+        v_sub(r0 + 3 * (APR * (k + 1) + A_N), CA, c0);
+        m_vec(M2, c0, c);
+        for (int q = 0; q < 3; ++q) pn[q] = p1[q] + c[q];
+    } else {
+        memcpy(pn, p1, sizeof p1);
+    }
+    return w;
+}
+
 /* ------------------------------------------------------------------ */
 /* Interaction classes by shortest bond path (Sec. 3.3)                 */
 /* ------------------------------------------------------------------ */

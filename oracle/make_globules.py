@@ -6,7 +6,9 @@ radius has radius of gyration Rg_target), with Rg_target = 2.2 m^0.38 A.  For
 each residue K (phi, psi) candidates are drawn around the Ramachandran basins;
 the candidate with the fewest contacts closer than ``clash`` A to earlier
 non-excluded atoms (then the least excursion beyond the sphere) is kept.
-Positions come from the oracle's forward kinematics only.  The radius is
+Positions come from the oracle's kinematics: one residue at a time while
+growing (``fk_extend``, the same operations as the whole-chain form), and the
+finished chain is measured with the whole-chain ``fk``.  The radius is
 rescaled until the final Rg is within 5 % of the target.
 
 Usage: python -m oracle.make_globules 1000 10000
@@ -89,20 +91,27 @@ def grow(m: int, radius: float, seed: int, K: int = 24, clash: float = 2.0):
         return bad
 
     fails = np.zeros(m, dtype=np.int64)
+    # kinematic state before residue k: rotation of link 2k, point of joint 2k
+    # (atom N of residue k), and the already placed atoms N, H of residue k
+    rot = np.zeros((m + 1, 3, 3))
+    pnt = np.zeros((m + 1, 3))
+    nh = np.zeros((m + 1, 2, 3))
+    rot[0] = np.eye(3)
+    pnt[0] = ch.r0[0]
+    nh[0] = ch.r0[0:2]
     k = 0
     while k < m:
-        best, best_key = None, None
+        best, best_key, best_state = None, None, None
         for width in (K, 4 * K):
             b = BASINS[rng.integers(0, len(BASINS), width)]
             cand = b[:, :2] + rng.normal(size=(width, 2)) * b[:, 2:3]
             for c in range(width):
-                theta[2 * k: 2 * k + 2] = cand[c]
-                r = oracle.fk_prefix(ch, theta, min(k + 2, m))
-                new = r[10 * k: 10 * k + 10]
-                tip = r[10 * (k + 1)] if k + 1 < m else r[10 * k + 8]  # N_{k+1} moves with phi_k and psi_k
+                ext, Mn, pn = oracle.fk_extend(ch, k, rot[k], pnt[k], cand[c][0], cand[c][1])
+                new = np.concatenate([nh[k], ext[:8]])
+                tip = ext[8] if k + 1 < m else ext[6]  # N_{k+1} moves with phi_k and psi_k
                 key = (clashes(k, new), max(0.0, np.linalg.norm(tip) - radius))
                 if best_key is None or key < best_key:
-                    best, best_key = cand[c].copy(), key
+                    best, best_key, best_state = cand[c].copy(), key, (new, Mn, pn, ext[8:10])
             if best_key[0] == 0:
                 break
         if best_key[0] > 0:
@@ -116,11 +125,17 @@ def grow(m: int, radius: float, seed: int, K: int = 24, clash: float = 2.0):
             k -= back
             continue
         theta[2 * k: 2 * k + 2] = best
-        r = oracle.fk_prefix(ch, theta, k + 1)
-        pos[10 * k: 10 * k + 10] = r[10 * k: 10 * k + 10]
+        new, Mn, pn, nh_next = best_state
+        pos[10 * k: 10 * k + 10] = new
         for a in range(10 * k, 10 * k + 10):
             insert(a)
+        rot[k + 1], pnt[k + 1] = Mn, pn
+        if k + 1 < m:
+            nh[k + 1] = nh_next
         k += 1
+    # the whole-chain kinematics reproduces the grown chain
+    r, _, _ = oracle.fk(ch, theta)
+    assert np.array_equal(r, pos)
     return theta, pos, ch
 
 

@@ -60,6 +60,7 @@ def _load():
     lib.or_link_of_atom.argtypes = [C.c_int]
     lib.or_atom_params.argtypes = [C.c_int, _ip, _dp, _dp, _dp, _dp, C.c_double, _dp, _dp, _dp, _dp]
     lib.or_fk.argtypes = [C.c_int, _dp, _dp, _dp, vp, vp]
+    lib.or_fk_extend.argtypes = [C.c_int, _dp, C.c_int, _dp, _dp, C.c_double, C.c_double, _dp, _dp, _dp]
     lib.or_pair_forces.argtypes = [C.c_int, _dp, _dp, _dp, _dp, C.POINTER(_PairP), vp, C.c_int, _dp, vp]
     lib.or_samples.argtypes = [C.c_int, vp]
     lib.or_sasa_forces.argtypes = [C.c_int, _dp, _dp, _dp, _dp, C.c_int, C.POINTER(_SasaP), _dp, vp, vp, vp]
@@ -284,6 +285,19 @@ def iterate(chain: OracleChain, theta, pp: PairParams = PairParams(), sp: SasaPa
 
 def threads() -> int:
     return int(_load().or_threads())
+
+
+def fk_extend(chain: OracleChain, k: int, M, p, phi: float, psi: float):
+    """One residue of the kinematics (for growing start conformations): atoms of
+    links 2k+1 and 2k+2 (slots 2..9 of residue k, then slots 0..1 of residue
+    k+1) from the rotation M of link 2k and the point p of joint 2k; returns
+    (positions, rotation of link 2k+2, point of joint 2k+2)."""
+    pos = np.zeros((10, 3))
+    Mn = np.zeros(9)
+    pn = np.zeros(3)
+    w = _load().or_fk_extend(chain.m, chain.r0, int(k), np.ascontiguousarray(M, dtype=np.float64).reshape(9),
+                             np.ascontiguousarray(p, dtype=np.float64), float(phi), float(psi), pos, Mn, pn)
+    return pos[:w], Mn.reshape(3, 3), pn
 
 
 def fk_prefix(chain: OracleChain, theta, k: int):

@@ -920,6 +920,7 @@ __global__ __launch_bounds__(WAVE) void k_force(Batch bt)
     const bool do_pair = do_elec || do_vdw;
     const double cut2 = cd->cutoff * cd->cutoff;
     const double roff_i = pi.w;
+    const double inv_2roff = 0.5 / roff_i;
     const double dr = cd->delta_r;
     const int res_i = ai / APR, slot_i = ai - res_i * APR;
     const uint32_t m12 = cd->m12[slot_i], m13 = cd->m13[slot_i], m14 = cd->m14[slot_i];
@@ -959,7 +960,8 @@ __global__ __launch_bounds__(WAVE) void k_force(Batch bt)
             }
             if (we != (Real)0 || wv != (Real)0) {
                 const Real rx = (Real)ddx, ry = (Real)ddy, rz = (Real)ddz;
-                const Real inv2 = (Real)1 / (Real)d2;
+                // mixed form: hardware reciprocal (1 ulp), far inside the force tolerance
+                const Real inv2 = MIXED ? (Real)__builtin_amdgcn_rcpf((float)d2) : (Real)1 / (Real)d2;
                 // eq 02 with eps = k_d d: E = (C/k_d) q_i q_j / d^2
                 const Real eel = we * coul * qi * (Real)pj.x * inv2;
                 // eq 03: E = eps_ij [(D/d)^12 - 2 (D/d)^6], D = R_i + R_j, eps_ij = sqrt(eps_i eps_j)
@@ -988,7 +990,7 @@ __global__ __launch_bounds__(WAVE) void k_force(Batch bt)
                 const double Rj = pj.w;
                 NbrEntry<Real> e;
                 e.ax = (Real)ddx; e.ay = (Real)ddy; e.az = (Real)ddz;
-                e.c0 = (Real)((roff_i * roff_i + d2 - Rj * Rj) / (2.0 * roff_i));
+                e.c0 = (Real)((roff_i * roff_i + d2 - Rj * Rj) * inv_2roff);
                 s_nbr[pos] = e;
                 s_nbr_a[pos] = aj;
             }

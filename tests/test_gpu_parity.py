@@ -207,6 +207,27 @@ def test_resynchronised_trajectory(precision):
     gpu.free()
 
 
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_free_trajectory_100_iterations(precision):
+    # the 64-residue workload: 100 iterations on the device in one call against
+    # 100 oracle iterations, each side from its own previous angles.  Per-step
+    # errors add up over the trajectory, so the bound is 100 x the per-step
+    # tolerance of the form.
+    p = params(precision)
+    m = 64
+    seed = synth.config_seed(1)
+    gpu, ref, th = build_pair(m, seed, p)
+    rep = gpu.step(100)
+    assert rep.status == 0 and rep.iterations == 100
+    t = th.copy()
+    for _ in range(100):
+        t = oracle_step(ref, t, p)["theta"]
+    err = float(np.abs(np.angle(np.exp(1j * (gpu.state()["theta"] - t)))).max())
+    _log(case="trajectory100", precision=precision, dtheta=err)
+    assert err <= 100 * DTHETA_TOL[precision]
+    gpu.free()
+
+
 @pytest.mark.parametrize("precision,tol", [(kcm.KCM_MIXED, 1e-9), (kcm.KCM_FP64, 1e-13)])
 def test_checkpoint_resume(precision, tol):
     # a chain rebuilt from the angles of iteration 3 continues the trajectory.

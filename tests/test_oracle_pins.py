@@ -469,3 +469,19 @@ def test_coulomb_constant_from_si_units():
     r[j] = r[i] + np.array([d, 0.0, 0.0])
     _, Ee, _ = oracle.pair_forces(ch, r, oracle.PairParams())
     assert abs(Ee - C * ch.q[i] * ch.q[j] / (4.0 * d * d)) < 1e-5 * abs(Ee)
+
+
+def test_fk_extend_grows_the_same_chain_as_fk():
+    # the residue-by-residue kinematics used to grow start conformations is the
+    # same sequence of operations as the whole-chain kinematics: equal bit for bit
+    m = 30
+    ch = oracle.OracleChain(synth.sequence(m, 5), synth.residue_types())
+    th = synth.random_dihedrals(m, 5)
+    r, _, _ = oracle.fk(ch, th)
+    grown = np.zeros_like(r)
+    grown[0:2] = ch.r0.reshape(-1, 3)[0:2]
+    M, p = np.eye(3), ch.r0.reshape(-1, 3)[0].copy()
+    for k in range(m):
+        pos, M, p = oracle.fk_extend(ch, k, M, p, th[2 * k], th[2 * k + 1])
+        grown[10 * k + 2: 10 * k + 2 + len(pos)] = pos
+    assert np.array_equal(grown, r)
