@@ -118,29 +118,40 @@ def batch_workload(n_chains: int = 256):
     return T, chains
 
 
-def run_batch(steps: int, warmup: int, n_chains: int = 256):
-    """Ragged batch in mixed precision: all chains advanced by one graph replay per iteration."""
+def run_batch(steps: int, warmup: int, n_chains: int = 256, tune: bool = True, direct: bool = False):
+    """Ragged batch in mixed precision: all chains advanced together by replayed
+    HIP graphs, with the cell edge and the iterations per graph picked by the
+    autotuner on the same batch first."""
     import torch
 
-    from paper_1712_05012_amd import kcm
+    from paper_1712_05012_amd import autotune, kcm
 
     T, items = batch_workload(n_chains)
-    p = kcm.kcm_default_params(precision=kcm.KCM_MIXED)
+    stream = torch.cuda.current_stream()
+    tuned = autotune.tune(T, items, kcm.KCM_MIXED, stream=stream) if tune and not direct else None
+    p = kcm.kcm_default_params(precision=kcm.KCM_MIXED, cell_size=tuned.cell_size if tuned else 0.0)
+    depth = 0 if direct else (tuned.graph_depth if tuned else 1)
     chains = [kcm.Chain(seq, T, p, theta0=th) for seq, th in items]
     atoms = sum(c.n_atoms for c in chains)
-    stream = torch.cuda.current_stream()
-    kcm.kcm_step(chains, warmup, stream, report=False)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    kcm.kcm_step(chains, steps, stream, report=False)
-    torch.cuda.synchronize()
-    secs = time.perf_counter() - t0
+    kcm.kcm_set_graphs(depth)
+    try:
+        kcm.kcm_step(chains, warmup + depth, stream, report=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        kcm.kcm_step(chains, steps, stream, report=False)
+        torch.cuda.synchronize()
+        secs = time.perf_counter() - t0
+    finally:
+        kcm.kcm_set_graphs(0 if direct else 1)
     _, reps = kcm.kcm_step(chains, 0, stream, report=True, check=False)
     bad = sum(r.status != 0 for r in reps)
     for c in chains:
         c.free()
-    return {"chains": len(items), "atoms": atoms, "steps": steps, "ms_per_step": 1e3 * secs / steps,
-            "value": atoms * steps / secs, "failed_chains": int(bad)}
+    out = {"chains": len(items), "atoms": atoms, "steps": steps, "ms_per_step": 1e3 * secs / steps,
+           "value": atoms * steps / secs, "failed_chains": int(bad), "cell_size": p.cell_size, "graph_depth": depth}
+    if tuned:
+        out["autotune"] = tuned.as_dict()
+    return out
 
 
 def run_per_chain_fp64(steps: int, n_sample: int = 16, n_chains: int = 256):
@@ -241,6 +252,8 @@ def main():
     ap.add_argument("--legs", default="main,companion,batch,serving,cpu",
                     help="comma-separated legs to run (main, companion, batch, serving, cpu); "
                          "profiling runs use a subset, the benchmark line needs main")
+    ap.add_argument("--graph-depth", type=int, default=8,
+                    help="iterations per replayed HIP graph in the single-chain legs")
     ap.add_argument("--no-graphs", action="store_true",
                     help="launch each iteration's kernels directly instead of replaying a HIP graph")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -261,10 +274,9 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     torch.cuda.set_device(0)
-    if args.no_graphs:
-        from paper_1712_05012_amd import kcm
+    from paper_1712_05012_amd import kcm
 
-        kcm.kcm_set_graphs(0)
+    kcm.kcm_set_graphs(0 if args.no_graphs else args.graph_depth)
     if args.copy_probe > 0:
         src = torch.empty(args.copy_probe << 18, dtype=torch.float32, device="cuda").fill_(1.0)
         dst = torch.empty_like(src)
@@ -286,7 +298,7 @@ def main():
         # a profiling run of the other legs only
         line = {"legs": sorted(legs)}
         if "batch" in legs:
-            line["batched"] = run_batch(args.batch_steps, 5)
+            line["batched"] = run_batch(args.batch_steps, 5, direct=args.no_graphs)
         if "serving" in legs:
             line["serving"] = run_serving(args.serve_jobs, args.serve_max_iter, 64.0)
         print(json.dumps(line), flush=True)
@@ -327,6 +339,7 @@ def main():
             "frac": achieved / peak,
             "traffic": traffic_for(args.precision),
         },
+        "graph_depth": 0 if args.no_graphs else args.graph_depth,
         "kernel_ms": {"force": main_run["force_ms_mean"],
                       "iteration": main_run["iter_ms_mean"],
                       "chain_kernels": main_run["iter_ms_mean"] - main_run["force_ms_mean"]},
@@ -339,7 +352,7 @@ def main():
                        "frac": companion["units"]["flops"] / (companion["force_ms_mean"] * 1e-3) / 1e12
                        / PEAK_TFLOPS[other]}
     if "batch" in legs:
-        b = run_batch(args.batch_steps, 5)
+        b = run_batch(args.batch_steps, 5, direct=args.no_graphs)
         fp64 = run_per_chain_fp64(max(5, args.batch_steps // 10))
         b["plain_fp64_per_chain"] = fp64
         b["speedup_vs_plain_fp64_per_chain"] = b["value"] / fp64["value"]

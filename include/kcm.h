@@ -196,11 +196,13 @@ kcm_status kcm_chain_info(const kcm_chain *chain, int32_t *n_atoms, int32_t *n_j
  * force kernel and of the iteration since the last reset (synchronises every
  * stream it recorded on). */
 kcm_status kcm_set_timing(int every);
-/* Launch mode of kcm_step: enable != 0 (the default) captures one iteration
- * of a call's chains as a HIP graph (on a private stream, once per batch
- * composition) and replays it on hip_stream; enable = 0 launches the kernels
- * directly.  Both modes give identical results. */
-kcm_status kcm_set_graphs(int enable);
+/* Launch mode of kcm_step (process-wide): iterations >= 1 (default 1)
+ * captures that many consecutive iterations of a call's chains as one HIP
+ * graph (on a private stream, once per batch composition and depth) and
+ * replays it on hip_stream, with single-iteration replays for the rest of a
+ * call; iterations = 0 launches the kernels directly.  Every mode gives
+ * identical results.  KCM_E_INVAL unless 0 <= iterations <= 64. */
+kcm_status kcm_set_graphs(int iterations);
 
 kcm_status kcm_get_timing(double *force_ms, int64_t *force_launches, double *iter_ms,
                           int64_t *iterations, int reset);

@@ -249,11 +249,14 @@ struct Table {
     Batch batch{};
     hipGraphExec_t graph = nullptr;  // one iteration, captured for this batch
     int graph_prec = -1;
+    hipGraphExec_t graph_n = nullptr;  // graph_n_depth iterations in one graph
+    int graph_n_prec = -1, graph_n_depth = 0;
 };
 
 std::mutex g_mu;
 std::vector<Table> g_tables;
-int g_graphs = 1;                       // replay the iteration as a captured graph
+int g_graphs = 1;                       // iterations per captured graph (0: direct launches)
+constexpr int kMaxGraphDepth = 64;
 std::vector<std::pair<int, hipStream_t>> g_capture_streams;  // per device
 
 hipError_t capture_stream(hipStream_t *out)
@@ -314,6 +317,28 @@ hipError_t launch_final(const Batch &bt, hipStream_t stream)
     if ((e = launch_tau(bt, stream)) != hipSuccess) return e;
     if ((e = launch_stepfk(bt, MODE_FINAL, stream)) != hipSuccess) return e;
     return launch_finish(bt, stream);
+}
+
+// Captures `iters` consecutive iterations of the batch as one executable graph.
+hipError_t capture_iterations(const Batch &bt, int prec, int iters, hipGraphExec_t *out)
+{
+    hipStream_t cs = nullptr;
+    hipError_t e = capture_stream(&cs);
+    if (e != hipSuccess) return e;
+    hipGraph_t g = nullptr;
+    if ((e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal)) != hipSuccess) return e;
+    hipError_t le = hipSuccess;
+    for (int i = 0; i < iters && le == hipSuccess; ++i) le = launch_iteration(bt, prec, cs);
+    hipError_t ee = hipStreamEndCapture(cs, &g);
+    if (le != hipSuccess) return le;
+    if (ee != hipSuccess) return ee;
+    e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+    hipError_t de = hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        *out = nullptr;
+        return e;
+    }
+    return de;
 }
 std::vector<TimedIter> g_timed;
 std::vector<hipEvent_t> g_event_pool;
@@ -414,6 +439,10 @@ kcm_status ensure_table(kcm_chain *const *chains, int n_chains, hipStream_t stre
         if (t->graph) {
             HIP_TRY(hipGraphExecDestroy(t->graph));
             t->graph = nullptr;
+        }
+        if (t->graph_n) {
+            HIP_TRY(hipGraphExecDestroy(t->graph_n));
+            t->graph_n = nullptr;
         }
     }
     *out = t;
@@ -677,26 +706,25 @@ kcm_status kcm_step(kcm_chain *const *chains, int n_chains, int n_iter, void *hi
     s = ensure_table(chains, n_chains, stream, &t);
     if (s != KCM_OK) return s;
     const Batch &bt = t->batch;
-    if (g_graphs && n_iter > 0 && (!t->graph || t->graph_prec != prec)) {
+    const int depth = g_graphs;
+    if (depth > 0 && n_iter > 0 && (!t->graph || t->graph_prec != prec)) {
         if (t->graph) {
             HIP_TRY(hipGraphExecDestroy(t->graph));
             t->graph = nullptr;
         }
-        hipStream_t cs = nullptr;
-        HIP_TRY(capture_stream(&cs));
-        hipGraph_t g = nullptr;
-        HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-        hipError_t le = launch_iteration(bt, prec, cs);
-        hipError_t ee = hipStreamEndCapture(cs, &g);
-        if (le != hipSuccess) return fail(KCM_E_DEVICE, std::string("capture: ") + hipGetErrorString(le));
-        if (ee != hipSuccess) return fail(KCM_E_DEVICE, std::string("end capture: ") + hipGetErrorString(ee));
-        hipError_t ie = hipGraphInstantiate(&t->graph, g, nullptr, nullptr, 0);
-        HIP_TRY(hipGraphDestroy(g));
-        if (ie != hipSuccess) {
-            t->graph = nullptr;
-            return fail(KCM_E_DEVICE, std::string("instantiate: ") + hipGetErrorString(ie));
-        }
+        hipError_t e = capture_iterations(bt, prec, 1, &t->graph);
+        if (e != hipSuccess) return fail(KCM_E_DEVICE, std::string("graph capture: ") + hipGetErrorString(e));
         t->graph_prec = prec;
+    }
+    if (depth > 1 && n_iter >= depth && (!t->graph_n || t->graph_n_prec != prec || t->graph_n_depth != depth)) {
+        if (t->graph_n) {
+            HIP_TRY(hipGraphExecDestroy(t->graph_n));
+            t->graph_n = nullptr;
+        }
+        hipError_t e = capture_iterations(bt, prec, depth, &t->graph_n);
+        if (e != hipSuccess) return fail(KCM_E_DEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+        t->graph_n_prec = prec;
+        t->graph_n_depth = depth;
     }
     if (n_iter > 0) {
         bool boot = false;
@@ -706,13 +734,26 @@ kcm_status kcm_step(kcm_chain *const *chains, int n_chains, int n_iter, void *hi
             for (int i = 0; i < n_chains; ++i) chains[i]->boot = false;
         }
     }
-    for (int it = 0; it < n_iter; ++it) {
-        const bool timed = g_timing > 0 && (g_timing_count++ % g_timing) == 0;
+    for (int it = 0; it < n_iter;) {
+        const bool timed = g_timing > 0 && (g_timing_count % g_timing) == 0;
         if (!timed) {
-            if (g_graphs) HIP_TRY(hipGraphLaunch(t->graph, stream));
-            else HIP_TRY(launch_iteration(bt, prec, stream));
+            // iterations until the next sampled one (or the end of the call)
+            int run = n_iter - it;
+            if (g_timing > 0) run = std::min<int64_t>(run, g_timing - g_timing_count % g_timing);
+            if (depth > 1 && run >= depth && t->graph_n) {
+                HIP_TRY(hipGraphLaunch(t->graph_n, stream));
+                it += depth;
+                g_timing_count += depth;
+            } else {
+                if (depth > 0) HIP_TRY(hipGraphLaunch(t->graph, stream));
+                else HIP_TRY(launch_iteration(bt, prec, stream));
+                ++it;
+                ++g_timing_count;
+            }
             continue;
         }
+        ++it;
+        ++g_timing_count;
         // a sampled iteration: direct launches bracketed by events
         TimedIter ti = {pooled_event(), pooled_event(), pooled_event(), pooled_event()};
         if (!ti.it0 || !ti.f0 || !ti.f1 || !ti.it1) return fail(KCM_E_DEVICE, "event creation failed");
@@ -927,10 +968,11 @@ kcm_status kcm_get_cells(const kcm_chain *c, void *hip_stream, int32_t *dims, do
     return KCM_OK;
 }
 
-kcm_status kcm_set_graphs(int enable)
+kcm_status kcm_set_graphs(int iterations)
 {
+    if (iterations < 0 || iterations > kMaxGraphDepth) return fail(KCM_E_INVAL, "iterations per graph must be in 0..64");
     std::lock_guard<std::mutex> lock(g_mu);
-    g_graphs = enable != 0;
+    g_graphs = iterations;
     return KCM_OK;
 }
 
@@ -983,6 +1025,10 @@ kcm_status kcm_chain_free(kcm_chain *c)
                 if (t.graph) {
                     (void)hipGraphExecDestroy(t.graph);
                     t.graph = nullptr;
+                }
+                if (t.graph_n) {
+                    (void)hipGraphExecDestroy(t.graph_n);
+                    t.graph_n = nullptr;
                 }
                 break;
             }

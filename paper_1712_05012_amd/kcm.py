@@ -264,8 +264,11 @@ def kcm_get_cells(handle, stream=None):
     return {"dims": dims, "cell": cell.value, "origin": origin, "order": order, "cell_start": cs}
 
 
-def kcm_set_graphs(enable: bool):
-    _check(load_library().kcm_set_graphs(1 if enable else 0))
+def kcm_set_graphs(iterations):
+    """Iterations per replayed HIP graph (True = 1, False = 0: direct launches)."""
+    if isinstance(iterations, bool):
+        iterations = 1 if iterations else 0
+    _check(load_library().kcm_set_graphs(int(iterations)))
 
 
 def kcm_set_timing(every: int):

@@ -82,3 +82,13 @@ def _load_missing(path):
         kcm.load_library(path)
     finally:
         kcm._lib = saved
+
+
+def test_launch_mode_settings_are_validated():
+    lib = kcm.load_library()
+    assert lib.kcm_set_graphs(-1) == kcm.KCM_E_INVAL
+    assert lib.kcm_set_graphs(65) == kcm.KCM_E_INVAL
+    for depth in (0, 8, 1):
+        assert lib.kcm_set_graphs(depth) == kcm.KCM_OK
+    assert lib.kcm_set_timing(-1) == kcm.KCM_E_INVAL
+    assert lib.kcm_set_timing(0) == kcm.KCM_OK

@@ -282,8 +282,10 @@ def test_fold_converges_and_reports():
     gpu.free()
 
 
-def test_graph_replay_equals_direct_launches():
-    # replays of the captured iteration, with eager work and synchronisations
+@pytest.mark.parametrize("depth", [1, 4])
+def test_graph_replay_equals_direct_launches(depth):
+    # replays of the captured iterations (one, or four per graph plus single
+    # ones for the rest of a call), with eager work and synchronisations
     # between calls, must match direct launches bit for bit after every call
     p = params(kcm.KCM_MIXED)
     seqs = [(synth.sequence(m, 140 + m), synth.random_dihedrals(m, 140 + m)) for m in (9, 27, 14)]
@@ -291,12 +293,12 @@ def test_graph_replay_equals_direct_launches():
     b = [kcm.Chain(s, TYPES, p, theta0=t) for s, t in seqs]
     try:
         for rep in range(4):
-            kcm.kcm_set_graphs(True)
-            kcm.kcm_step(a, 3)
+            kcm.kcm_set_graphs(depth)
+            kcm.kcm_step(a, 3 + 3 * rep)
             x = torch.ones(1000, device="cuda").sum().item()  # eager work in between
             assert x == 1000.0
             kcm.kcm_set_graphs(False)
-            kcm.kcm_step(b, 3)
+            kcm.kcm_step(b, 3 + 3 * rep)
             torch.cuda.synchronize()
             for ca, cb in zip(a, b):
                 sa, sb = ca.state(), cb.state()
@@ -340,3 +342,20 @@ def test_served_job_result_same_alone_and_in_mix():
         a, b = st.jobs[0], [j for j in mix.jobs if j.job_id == target][0]
         assert a.iterations == b.iterations
         assert np.array_equal(a.theta, b.theta)
+
+
+def test_autotune_picks_a_measured_setting_with_unchanged_results():
+    from paper_1712_05012_amd import autotune
+
+    items = [(synth.sequence(m, 300 + m), synth.random_dihedrals(m, 300 + m)) for m in (12, 30, 21)]
+    res = autotune.tune(TYPES, items, kcm.KCM_MIXED, cell_sizes=(0.0, 3.6), depths=(1, 2), iters=2, warmup=1)
+    assert len(res.table) == 4
+    assert (res.cell_size, res.graph_depth) in [(c, d) for c, d, _, _ in res.table]
+    assert res.atom_steps_per_s == max(r for *_, r in res.table) > 0
+    # the chosen cell edge changes only the candidate order: parity holds
+    p = params(kcm.KCM_MIXED, cell_size=res.cell_size)
+    gpu, ref, th = build_pair(30, 330, p)
+    st, o, err = compare_step(gpu, ref, th, p)
+    _log(case="autotuned", cell_size=res.cell_size, depth=res.graph_depth, **err)
+    assert err["F"] <= F_TOL and err["dtheta"] <= DTHETA_TOL[kcm.KCM_MIXED]
+    gpu.free()
