@@ -102,7 +102,10 @@ def grow(m: int, radius: float, seed: int, K: int = 24, clash: float = 2.0):
     k = 0
     while k < m:
         best, best_key, best_state = None, None, None
-        for width in (K, 4 * K):
+        # a residue that has failed more than 50 times (only ever in long
+        # chains) also gets a wider draw and deeper backtracking
+        widths = (K, 4 * K) if fails[k] <= 50 else (K, 4 * K, 16 * K)
+        for width in widths:
             b = BASINS[rng.integers(0, len(BASINS), width)]
             cand = b[:, :2] + rng.normal(size=(width, 2)) * b[:, 2:3]
             for c in range(width):
@@ -116,9 +119,9 @@ def grow(m: int, radius: float, seed: int, K: int = 24, clash: float = 2.0):
                 break
         if best_key[0] > 0:
             fails[k] += 1
-            if fails[k] > 50:
+            if fails[k] > 400:
                 raise RuntimeError(f"stuck at residue {k}")
-            back = min(k, 1 + int(fails[k]) // 3)
+            back = min(k, 1 + int(fails[k]) // (3 if fails[k] <= 50 else 2))
             for kk in range(k - back, k):
                 for a in range(10 * kk, 10 * kk + 10):
                     remove(a)
@@ -133,6 +136,8 @@ def grow(m: int, radius: float, seed: int, K: int = 24, clash: float = 2.0):
         if k + 1 < m:
             nh[k + 1] = nh_next
         k += 1
+        if k % 1000 == 0:
+            print(f"  grown {k} of {m} residues", flush=True)
     # the whole-chain kinematics reproduces the grown chain
     r, _, _ = oracle.fk(ch, theta)
     assert np.array_equal(r, pos)

@@ -6,7 +6,7 @@ torch = pytest.importorskip("torch")
 
 import oracle  # noqa: E402
 import synth  # noqa: E402
-from gpu_common import DTHETA_TOL, F_TOL, TYPES, build_pair, compare_step, oracle_step, params  # noqa: E402
+from gpu_common import DTHETA_TOL, F_TOL, TYPES, build_pair, compare_step, oracle_params, oracle_step, params  # noqa: E402
 from paper_1712_05012_amd import kcm  # noqa: E402
 
 pytestmark = pytest.mark.gpu
@@ -358,4 +358,52 @@ def test_autotune_picks_a_measured_setting_with_unchanged_results():
     st, o, err = compare_step(gpu, ref, th, p)
     _log(case="autotuned", cell_size=res.cell_size, depth=res.graph_depth, **err)
     assert err["F"] <= F_TOL and err["dtheta"] <= DTHETA_TOL[kcm.KCM_MIXED]
+    gpu.free()
+
+
+def test_large_globule_sampled_parity():
+    # the 10,000-residue compact globule (100,000 atoms) in mixed precision.
+    # The oracle's brute force is quadratic, so parity is checked on samples:
+    # every position against the oracle kinematics; the pair force of 256
+    # sampled atoms against the oracle over all atoms; the solvation force and
+    # exposure of 64 sampled atoms against the oracle on the cluster of atoms
+    # within 16 A (an atom's solvation force depends only on atoms within two
+    # offset radii plus the shift, at most 7.4 A, of it and of its neighbours);
+    # and Newton's third law over the whole chain.
+    from scipy.spatial import cKDTree
+
+    m = 10000
+    seq = synth.sequence(m, synth.config_seed(4))
+    th = synth.load_globule(m)
+    p = params(kcm.KCM_MIXED)
+    gpu = kcm.Chain(seq, TYPES, p, theta0=th)
+    ref = oracle.OracleChain(seq, TYPES, g_hydro=p.g_hydro)
+    rep = gpu.step(1)
+    assert rep.status == 0
+    st = gpu.state()
+    fp, fc = gpu.forces()
+    terms = gpu.atom_terms()
+    r, _, _ = oracle.fk(ref, th)
+    assert np.abs(st["xyz"] - r).max() < 1e-8
+    pp, sp = oracle_params(p)
+    rng = np.random.default_rng(4)
+    pick = np.sort(rng.choice(10 * m, 256, replace=False)).astype(np.int32)
+    F_pair, _, _ = oracle.pair_forces(ref, r, pp, subset=pick)
+    fmax = max(np.abs(F_pair[pick]).max(), 1e-300)
+    err_pair = float(np.abs(fp[pick] - F_pair[pick]).max() / fmax)
+    tree = cKDTree(r)
+    err_cav = 0.0
+    for a in pick[:64]:
+        cl = np.array(sorted(tree.query_ball_point(r[a], 16.0)))
+        Fc, f, _ = oracle.sasa_atoms(r[cl], ref.R[cl], ref.gamma[cl], sp)
+        i = int(np.searchsorted(cl, a))
+        err_cav = max(err_cav, float(np.abs(fc[a] - Fc[i]).max()))
+        assert terms["n_exposed"][a] == round(f[i] * gpu.n_samples), a
+    net = np.abs(fp.sum(axis=0)).max() / np.abs(fp).max()
+    _log(case="globule10000", err_pair=err_pair, err_cav=err_cav, net_pair=net,
+         net_cav=float(np.abs(fc.sum(axis=0)).max()))
+    assert err_pair <= F_TOL
+    assert err_cav < 1e-8
+    assert net <= 1e-6
+    assert np.abs(fc.sum(axis=0)).max() < 1e-6
     gpu.free()
