@@ -1,4 +1,6 @@
 """Parity of the HIP path with the FP64 oracle (needs an MI355X)."""
+import os
+
 import numpy as np
 import pytest
 
@@ -373,6 +375,8 @@ def test_large_globule_sampled_parity():
     from scipy.spatial import cKDTree
 
     m = 10000
+    if not os.path.exists(os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "data", f"globule_m{m}.npy")):
+        pytest.skip("no stored 10,000-residue start conformation (python -m oracle.make_globules 10000)")
     seq = synth.sequence(m, synth.config_seed(4))
     th = synth.load_globule(m)
     p = params(kcm.KCM_MIXED)
