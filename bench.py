@@ -178,8 +178,13 @@ def run_per_chain_fp64(steps: int, n_sample: int = 16, n_chains: int = 256):
             "one chain per call"}
 
 
-def run_serving(n_jobs: int, max_iter: int, budget_gib: float):
-    """Poisson arrivals at 50 jobs/s, lognormal lengths; continuous batching by HBM budget."""
+def run_serving(n_jobs: int, max_iter: int, budget_gib: float, skip: int):
+    """Poisson arrivals at 50 jobs/s, lognormal lengths; continuous batching by HBM budget.
+
+    Latency percentiles leave out the first ``skip`` jobs (warm-up); the queue
+    growth rate says whether one GPU keeps up with the offered load."""
+    import numpy as np
+
     import synth
     from paper_1712_05012_amd import kcm
     from paper_1712_05012_amd.serve import FoldService, Job, KcmEngine
@@ -194,11 +199,18 @@ def run_serving(n_jobs: int, max_iter: int, budget_gib: float):
                         arrival=float(a), tol=1e-4, max_iter=max_iter))
     eng = KcmEngine(T, kcm.kcm_default_params(precision=kcm.KCM_MIXED))
     svc = FoldService(eng, hbm_budget=int(budget_gib * (1 << 30)), max_slots=1024, check_every=20)
-    st = svc.run(jobs)
-    out = st.summary()
+    def progress(job, n_done):
+        if n_done % 250 == 0 or n_done == n_jobs:
+            print(f"serving: {n_done} of {n_jobs} jobs done", file=sys.stderr, flush=True)
+
+    st = svc.run(jobs, on_retire=progress)
+    out = st.summary(skip=min(skip, max(0, n_jobs - 1)))
+    offered = 50.0 * 10.0 * float(np.mean(lengths)) * max_iter
     out.update({"arrival_rate_per_s": 50.0, "max_iter": max_iter, "tol_dtheta": 1e-4,
                 "hbm_budget_gib": budget_gib,
-                "note": "offered load exceeds one GPU's throughput, so latency includes queueing"})
+                "offered_atom_steps_per_s_at_iteration_cap": offered,
+                "note": "latency is finish minus arrival and includes queueing; a positive queue "
+                        "growth means the offered load exceeds what one GPU serves"})
     return out
 
 
@@ -247,7 +259,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-companion", action="store_true", help="skip the other precision's measurement")
     ap.add_argument("--batch-steps", type=int, default=100, help="iterations of the 256-chain batch (0: skip)")
-    ap.add_argument("--serve-jobs", type=int, default=48, help="jobs of the serving run (0: skip)")
+    ap.add_argument("--serve-jobs", type=int, default=2000, help="jobs of the serving run (0: skip)")
+    ap.add_argument("--serve-warmup", type=int, default=100,
+                    help="earliest jobs left out of the serving latency percentiles")
     ap.add_argument("--serve-max-iter", type=int, default=2000)
     ap.add_argument("--legs", default="main,companion,batch,serving,cpu",
                     help="comma-separated legs to run (main, companion, batch, serving, cpu); "
@@ -300,7 +314,7 @@ def main():
         if "batch" in legs:
             line["batched"] = run_batch(args.batch_steps, 5, direct=args.no_graphs)
         if "serving" in legs:
-            line["serving"] = run_serving(args.serve_jobs, args.serve_max_iter, 64.0)
+            line["serving"] = run_serving(args.serve_jobs, args.serve_max_iter, 64.0, args.serve_warmup)
         print(json.dumps(line), flush=True)
         return
 
@@ -358,7 +372,7 @@ def main():
         b["speedup_vs_plain_fp64_per_chain"] = b["value"] / fp64["value"]
         line["batched"] = b
     if "serving" in legs:
-        line["serving"] = run_serving(args.serve_jobs, args.serve_max_iter, 64.0)
+        line["serving"] = run_serving(args.serve_jobs, args.serve_max_iter, 64.0, args.serve_warmup)
     if "cpu" in legs:
         line["cpu_baseline"] = cpu_baseline(args.cpu_seconds, args.residues)
     print(json.dumps(line), flush=True)

@@ -11,7 +11,10 @@ growing (``fk_extend``, the same operations as the whole-chain form), and the
 finished chain is measured with the whole-chain ``fk``.  The radius is
 rescaled until the final Rg is within 5 % of the target.
 
-Usage: python -m oracle.make_globules 1000 10000
+Usage: python -m oracle.make_globules 1000 10000 [--seed S] [--out-dir DIR]
+
+The stored files were written with the default seed (1000 residues) and with
+the seed their design notes give (10,000 residues).
 """
 from __future__ import annotations
 
@@ -155,11 +158,15 @@ def min_nonexcluded_distance(ch, pos, limit=2.5):
     return best
 
 
-def make(m: int, seed: int = 0):
+def make(m: int, seed: int = 0, out_dir: str | None = None):
     target = 2.2 * m ** 0.38
     radius = np.sqrt(5.0 / 3.0) * target
+    # long chains pack with a smaller contact distance while growing: at 2 A
+    # the tip of a 10,000-residue chain gets trapped deep inside the ball;
+    # the acceptance test below still asks for 1.5 A between any two atoms
+    clash = 2.0 if m <= 2000 else 1.6
     for attempt in range(6):
-        theta, pos, ch = grow(m, radius, seed + attempt)
+        theta, pos, ch = grow(m, radius, seed + attempt, clash=clash)
         rg = float(np.sqrt(((pos - pos.mean(0)) ** 2).sum(1).mean()))
         dmin = min_nonexcluded_distance(ch, pos)
         print(f"m={m} radius={radius:.2f} Rg={rg:.2f} target={target:.2f} min_d={dmin:.3f}", flush=True)
@@ -170,11 +177,18 @@ def make(m: int, seed: int = 0):
         raise RuntimeError(f"no acceptable globule for m={m}")
     theta = (theta + np.pi) % (2 * np.pi) - np.pi
     theta[theta <= -np.pi] += 2 * np.pi
-    out = os.path.join(ROOT, "data", f"globule_m{m}.npy")
+    out = os.path.join(out_dir or os.path.join(ROOT, "data"), f"globule_m{m}.npy")
     np.save(out, theta)
-    print("wrote", out, flush=True)
+    print("wrote", out, f"(seed {seed + attempt})", flush=True)
 
 
 if __name__ == "__main__":
-    for arg in sys.argv[1:] or ["1000"]:
-        make(int(arg))
+    import argparse
+
+    ap = argparse.ArgumentParser(description="write compact-globule start conformations")
+    ap.add_argument("m", type=int, nargs="*", default=[1000], help="residue counts")
+    ap.add_argument("--seed", type=int, default=0, help="growth seed of the first attempt")
+    ap.add_argument("--out-dir", default=None, help="directory of the .npy files (default: data/)")
+    a = ap.parse_args()
+    for m in a.m:
+        make(m, a.seed, a.out_dir)

@@ -88,21 +88,52 @@ class ServiceStats:
     max_live: int = 0
     max_bytes: int = 0
     queue_peak: int = 0
+    queue_trace: list = field(default_factory=list)  # (service time, waiting, live) before each tick
+    last_arrival: float = 0.0
+
+    def growth(self, t_from: float = 0.0, live: bool = False):
+        """Least-squares slope (jobs/s) of the waiting queue (``live``: of the
+        jobs in the system, waiting plus live) while jobs still arrive.
+
+        Ticks from ``t_from`` up to the last arrival count; a slope well above
+        zero means the offered load exceeds what the device serves."""
+        pts = [(t, q + (n if live else 0)) for t, q, n in self.queue_trace if t_from <= t <= self.last_arrival]
+        if len(pts) < 2:
+            return None
+        t = np.array([p[0] for p in pts])
+        q = np.array([p[1] for p in pts], dtype=np.float64)
+        if np.ptp(t) <= 0:
+            return None
+        return float(np.polyfit(t, q, 1)[0])
 
     def summary(self, skip: int = 0):
+        """Latency over the jobs after the first ``skip`` (by job id, i.e. arrival order)."""
         done = [j for j in self.jobs[skip:]]
         lat = np.array([j.latency for j in done]) if done else np.zeros(0)
+        t_warm = min((j.arrival for j in done), default=0.0)
+        q_end = [q for t, q, _ in self.queue_trace if t <= self.last_arrival]
         return {
             "jobs": len(done),
+            "warmup_jobs_discarded": int(min(skip, len(self.jobs))),
             "p50_latency_s": float(np.percentile(lat, 50)) if lat.size else None,
             "p99_latency_s": float(np.percentile(lat, 99)) if lat.size else None,
+            "mean_iterations": float(np.mean([j.iterations for j in done])) if done else None,
             "atom_steps_per_s": self.atom_steps / self.wall if self.wall > 0 else None,
+            "wall_s": self.wall,
             "converged": int(sum(j.converged for j in done)),
             "failed": int(sum(j.status != 0 for j in done)),
+            "failed_jobs": [{"job_id": j.job_id, "status": j.status, "iterations": j.iterations,
+                             "residues": int(len(j.res_type))} for j in self.jobs if j.status != 0][:20],
+            "status_counts": {str(k): int(v) for k, v in
+                              zip(*np.unique([j.status for j in done], return_counts=True))} if done else {},
             "ticks": self.ticks,
             "max_live": self.max_live,
             "max_bytes": self.max_bytes,
             "queue_peak": self.queue_peak,
+            "queue_at_last_arrival": int(q_end[-1]) if q_end else 0,
+            "queue_growth_jobs_per_s": self.growth(t_warm),
+            "backlog_growth_jobs_per_s": self.growth(t_warm, live=True),
+            "served_jobs_per_s": len(self.jobs) / self.wall if self.wall > 0 else None,
         }
 
 
@@ -120,8 +151,10 @@ class FoldService:
         self.clock = clock
         self.sleep = sleep
 
-    def run(self, jobs):
-        """Serve ``jobs`` (arrival times relative to the start) to completion."""
+    def run(self, jobs, on_retire=None):
+        """Serve ``jobs`` (arrival times relative to the start) to completion.
+
+        ``on_retire(job, n_done)``, if given, is called as each job retires."""
         pending = sorted(jobs, key=lambda j: (j.arrival, j.job_id))
         for j in pending:
             j.bytes = self.engine.bytes_for(j)
@@ -131,6 +164,7 @@ class FoldService:
         live: dict = {}                    # job_id -> (job, chain, start_iterations)
         used = 0
         stats = ServiceStats()
+        stats.last_arrival = max((j.arrival for j in pending), default=0.0)
         t0 = self.clock()
         nxt = 0
         while nxt < len(pending) or waiting or live:
@@ -155,6 +189,7 @@ class FoldService:
                 continue
             order = sorted(live)
             chains = [live[k][1] for k in order]
+            stats.queue_trace.append((now, len(waiting), len(live)))
             reports = self.engine.step(chains, self.check_every)
             stats.ticks += 1
             now = self.clock() - t0
@@ -171,6 +206,8 @@ class FoldService:
                     used -= j.bytes
                     del live[k]
                     stats.jobs.append(j)
+                    if on_retire is not None:
+                        on_retire(j, len(stats.jobs))
         stats.wall = self.clock() - t0
         stats.jobs.sort(key=lambda j: j.job_id)
         return stats

@@ -65,6 +65,100 @@ def test_solvation_counts_are_exact(precision, n_orbits):
     gpu.free()
 
 
+def _max_solvation_neighbours(ref, r, p):
+    """Largest per-atom count of offset spheres within reach (brute force)."""
+    roff = ref.R + p.r_probe
+    d = np.sqrt(((r[:, None, :] - r[None, :, :]) ** 2).sum(-1))
+    lim = roff[:, None] + roff[None, :] + p.delta_r
+    np.fill_diagonal(d, np.inf)
+    return int((d <= lim).sum(axis=1).max())
+
+
+# A random-dihedral start with a dense self-overlap: one atom has more
+# solvation neighbours (418) than the kernel's LDS list holds (384), so its
+# neighbours are processed in two chunks.  The chain is job 1792 of the
+# serving stream (304 residues).
+OVERFLOW_M = 304
+OVERFLOW_SEED = synth.config_seed(5) + 1000 * (1792 + 1)
+
+
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_neighbour_list_overflow_is_processed_in_chunks(precision):
+    p = params(precision, terms=kcm.KCM_TERM_CAV)
+    gpu, ref, th = build_pair(OVERFLOW_M, OVERFLOW_SEED, p)
+    r0 = oracle.fk(ref, th)[0]
+    nmax = _max_solvation_neighbours(ref, r0, p)
+    assert nmax > 384
+    st, o, err = compare_step(gpu, ref, th, p)
+    _log(case="nbr_overflow", precision=precision, max_neighbours=nmax, **err)
+    assert err["status"] == 0
+    assert err["margin"] > 1e-10
+    assert np.abs(st["force"] - o["F_cav"]).max() < 1e-8
+    assert err["E_cav"] < 1e-12
+    gpu.free()
+    # and the whole iteration with every term
+    p = params(precision)
+    gpu, ref, th = build_pair(OVERFLOW_M, OVERFLOW_SEED, p)
+    st, o, err = compare_step(gpu, ref, th, p)
+    _log(case="nbr_overflow_full", precision=precision, **err)
+    assert err["status"] == 0
+    assert err["F"] <= F_TOL
+    assert err["dtheta"] <= DTHETA_TOL[precision]
+    gpu.free()
+
+
+def _close_contact_start():
+    """A start with two non-bonded atoms 0.001 A apart.
+
+    Job 1933 of the serving stream (179 residues, random dihedrals) has atoms
+    1187 and 1244 (residues 118 and 124) 0.0118 A apart; three dihedrals
+    between them are adjusted by least squares (oracle kinematics) to bring
+    atom 1244 to 0.001 A from atom 1187 along the line that joins them."""
+    from scipy.optimize import least_squares
+
+    seed = synth.config_seed(5) + 1000 * (1933 + 1)
+    m, a, b, joints = 179, 1187, 1244, [240, 243, 246]
+    th0 = synth.random_dihedrals(m, seed)
+    ref = oracle.OracleChain(synth.sequence(m, seed), TYPES)
+    r = oracle.fk(ref, th0)[0]
+    u = (r[b] - r[a]) / np.linalg.norm(r[b] - r[a])
+    target = r[a] + 1e-3 * u
+
+    def resid(x):
+        th = th0.copy()
+        th[joints] += x
+        return oracle.fk(ref, th)[0][b] - target
+
+    sol = least_squares(resid, np.zeros(3), xtol=1e-15, ftol=1e-15, gtol=1e-15)
+    th = th0.copy()
+    th[joints] += sol.x
+    return m, seed, th, a, b
+
+
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_close_contact_beyond_fp32_range(precision):
+    # (D/d)^12 and the force of a pair 0.001 A apart exceed the FP32 range:
+    # the mixed form takes those atoms' pair terms in FP64
+    m, seed, th, a, b = _close_contact_start()
+    p = params(precision)
+    gpu, ref, _ = build_pair(m, seed, p, theta=th)
+    r0 = oracle.fk(ref, th)[0]
+    assert abs(np.linalg.norm(r0[a] - r0[b]) - 1e-3) < 1e-9
+    st, o, err = compare_step(gpu, ref, th, p)
+    F, Fo = st["force"], o["F"]
+    _log(case="close_contact", precision=precision, fmax=float(np.abs(Fo).max()), **err)
+    assert np.abs(Fo).max() > 3.5e38  # above the largest FP32 value
+    assert err["status"] == 0
+    for k in (a, b):
+        assert np.abs(F[k] - Fo[k]).max() <= 1e-9 * np.abs(Fo[k]).max()
+    rest = np.ones(len(F), bool)
+    rest[[a, b]] = False
+    assert np.abs(F[rest] - Fo[rest]).max() <= F_TOL * np.abs(Fo[rest]).max()
+    assert err["E_vdw"] <= 1e-9
+    assert err["dtheta"] <= DTHETA_TOL[precision]
+    gpu.free()
+
+
 @pytest.mark.parametrize("precision", PRECISIONS)
 def test_pair_only_and_newton_third_law(precision):
     p = params(precision, terms=kcm.KCM_TERM_ELEC | kcm.KCM_TERM_VDW)

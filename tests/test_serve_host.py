@@ -21,9 +21,9 @@ class HostEngine:
     """Each job converges after `conv[job_id]` iterations (or never if None);
     a job listed in `fail` reports a numeric failure on its first tick."""
 
-    def __init__(self, clock, conv, fail=(), bytes_per_atom=1000, tick_seconds=0.01):
+    def __init__(self, clock, conv, fail=(), bytes_per_atom=1000, tick_seconds=0.01, chain_seconds=0.0):
         self.clock, self.conv, self.fail = clock, conv, set(fail)
-        self.bpa, self.dt = bytes_per_atom, tick_seconds
+        self.bpa, self.dt, self.dc = bytes_per_atom, tick_seconds, chain_seconds
         self.open_bytes = 0
         self.peak_bytes = 0
         self.events = []
@@ -38,7 +38,7 @@ class HostEngine:
         return {"job": job, "iters": 0}
 
     def step(self, chains, n_iter):
-        self.clock.t += self.dt
+        self.clock.t += self.dt + self.dc * len(chains)
         out = []
         for c in chains:
             j = c["job"]
@@ -126,3 +126,60 @@ def test_job_larger_than_budget_is_refused():
     svc = FoldService(eng, hbm_budget=1000, max_slots=4, clock=clk, sleep=clk.sleep)
     with pytest.raises(ValueError):
         svc.run(make_jobs(1, [50], [0.0]))
+
+
+def _stream(n, gap, max_iter):
+    return make_jobs(n, [50] * n, [k * gap for k in range(n)], max_iter=max_iter)
+
+
+def test_queue_growth_reports_overload_and_not_underload():
+    # each job needs 5 ticks (50 iterations / 10 per tick) of 0.01 s on one slot
+    clk = SimClock()
+    over = FoldService(HostEngine(clk, {}), hbm_budget=10**9, max_slots=1, check_every=10,
+                       clock=clk, sleep=clk.sleep)
+    st = over.run(_stream(60, 0.01, 50))        # 100 jobs/s offered, 20 jobs/s served
+    s = st.summary(skip=10)
+    assert s["jobs"] == 50 and s["warmup_jobs_discarded"] == 10
+    # the waiting queue grows by about 100 - 20 = 80 jobs/s while jobs arrive
+    assert 60.0 < s["queue_growth_jobs_per_s"] < 100.0
+    assert s["queue_at_last_arrival"] > 30
+    assert s["backlog_growth_jobs_per_s"] >= s["queue_growth_jobs_per_s"] - 1e-9
+
+
+def test_backlog_growth_sees_jobs_held_in_slots():
+    # enough slots to admit everything: the queue stays short while the live
+    # set grows by the excess of arrivals over completions.  A tick costs
+    # 0.01 s + 1 ms per live chain and a job needs 5 ticks, so at most
+    # 1 / (5 * 1 ms) = 200 jobs/s complete while 500 jobs/s arrive.
+    clk = SimClock()
+    svc = FoldService(HostEngine(clk, {}, chain_seconds=1e-3), hbm_budget=10**9, max_slots=10000,
+                      check_every=10, clock=clk, sleep=clk.sleep)
+    st = svc.run(_stream(400, 0.002, 50))
+    s = st.summary()
+    assert s["backlog_growth_jobs_per_s"] > 200.0
+    assert s["queue_growth_jobs_per_s"] < s["backlog_growth_jobs_per_s"] / 4
+    assert s["served_jobs_per_s"] < 200.0
+
+    clk = SimClock()
+    under = FoldService(HostEngine(clk, {}), hbm_budget=10**9, max_slots=8, check_every=10,
+                        clock=clk, sleep=clk.sleep)
+    st = under.run(_stream(60, 0.02, 50))       # 50 jobs/s offered, up to 160 jobs/s served
+    s = st.summary(skip=10)
+    assert abs(s["queue_growth_jobs_per_s"]) < 5.0
+    assert s["queue_at_last_arrival"] <= 1
+    assert abs(s["backlog_growth_jobs_per_s"]) < 5.0
+    # latency is the service time alone: 5 ticks
+    assert s["p99_latency_s"] == pytest.approx(0.05, abs=0.011)
+
+
+def test_warmup_discard_drops_the_earliest_arrivals():
+    clk = SimClock()
+    svc = FoldService(HostEngine(clk, {}), hbm_budget=10**9, max_slots=1, check_every=10,
+                      clock=clk, sleep=clk.sleep)
+    st = svc.run(_stream(20, 0.001, 20))
+    all_lat = sorted(j.latency for j in st.jobs)
+    kept = sorted(j.latency for j in st.jobs if j.job_id >= 5)
+    s = st.summary(skip=5)
+    assert s["jobs"] == 15
+    assert s["p50_latency_s"] == pytest.approx(float(np.percentile(kept, 50)))
+    assert s["p50_latency_s"] > float(np.percentile(all_lat[:5], 50))
