@@ -4,7 +4,8 @@
 One step is one full KCM iteration of the chain (forward kinematics, cell
 list, Coulomb + LJ + SASA solvation forces, torques, compliance step) on the
 single 1000-residue chain (10,000 atoms) in a compact-globule start, 10 A
-cutoff, 250 samples per offset sphere.  Inputs are built once and stay in
+cutoff, 250 samples per offset sphere (--workload globule10000: the
+10,000-residue chain, 100,000 atoms, 200 steps).  Inputs are built once and stay in
 HBM; the timed region covers exactly --steps iterations between two device
 synchronisations.  Prints one JSON line.
 
@@ -33,11 +34,20 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "force_kernel_traffic.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_1712_05012_amd", "csrc", "kcm_kernels.hip")
 
 
+# Single-chain workloads: residues and the sequence-seed config number.  Both
+# start from a stored compact globule (radius of gyration 2.2 m^0.38 A).
+WORKLOADS = {
+    "globule1000": (1000, 2, 1000),    # (residues, seed config, default steps)
+    "globule10000": (10000, 4, 200),
+}
+
+
 def workload(m: int = 1000):
     import synth
 
     T = synth.residue_types()
-    seq = synth.sequence(m, synth.config_seed(2))
+    cfg = {res: c for res, c, _ in WORKLOADS.values()}.get(m, 2)
+    seq = synth.sequence(m, synth.config_seed(cfg))
     th = synth.load_globule(m)
     return T, seq, th
 
@@ -214,13 +224,15 @@ def run_serving(n_jobs: int, max_iter: int, budget_gib: float, skip: int):
     return out
 
 
-def traffic_for(precision: str):
+def traffic_for(precision: str, workload_name: str = "globule1000"):
     """HBM bytes per force launch from committed rocprofv3 counters, if still current."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     try:
         rec = json.load(open(TRAFFIC_FILE))
         sha = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+        if rec.get("workload", "globule1000") != workload_name:
+            return None
         entry = rec.get(precision)
         if not entry or rec.get("kernel_sha256") != sha:
             return None
@@ -245,16 +257,17 @@ def cpu_baseline(seconds: float, m: int):
             break
     dt = time.perf_counter() - t0
     return {"value": ch.n * iters / dt, "unit": "atom-steps/s", "cores": oracle.threads(), "kind": "oracle",
-            "sample": f"{iters} FP64 KCM iterations of the 1000-residue globule ({ch.n} atoms), {dt:.1f} s"}
+            "sample": f"{iters} FP64 KCM iterations of the {m}-residue globule ({ch.n} atoms), {dt:.1f} s"}
 
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--steps", type=int, default=None, help="timed iterations (default: the workload's)")
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed")
-    ap.add_argument("--residues", type=int, default=1000)
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="globule1000",
+                    help="single-chain workload: 1,000 residues (10,000 atoms) or 10,000 residues (100,000 atoms)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-companion", action="store_true", help="skip the other precision's measurement")
@@ -279,8 +292,9 @@ def main():
               "(how chains would shard over several GPUs is described in the design notes); "
               "run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
-    if args.residues != 1000:
-        print("note: non-default --residues needs a stored globule for that length", file=sys.stderr)
+    residues, _, default_steps = WORKLOADS[args.workload]
+    if args.steps is None:
+        args.steps = default_steps
 
     import torch
 
@@ -318,9 +332,9 @@ def main():
         print(json.dumps(line), flush=True)
         return
 
-    main_run = run_gpu(args.precision, args.steps, args.warmup, args.residues)
+    main_run = run_gpu(args.precision, args.steps, args.warmup, residues)
     other = "fp64" if args.precision == "mixed" else "mixed"
-    companion = run_gpu(other, args.steps, args.warmup, args.residues) if "companion" in legs else None
+    companion = run_gpu(other, args.steps, args.warmup, residues) if "companion" in legs else None
 
     u = main_run["units"]
     achieved = u["flops"] / (main_run["force_ms_mean"] * 1e-3) / 1e12
@@ -339,8 +353,9 @@ def main():
         "dtype": "f32+f64" if args.precision == "mixed" else "f64",
         "data": "synthetic",
         "config": {
-            "workload": "single chain, 1000 residues (10,000 atoms), compact random globule, "
+            "workload": f"single chain, {residues} residues ({10 * residues:,} atoms), compact random globule, "
                         "10 A cutoff, 250 samples per offset sphere, 1 KCM iteration per step",
+            "name": args.workload,
             "precision": args.precision,
             "n_atoms": main_run["n_atoms"],
             "n_samples": main_run["n_samples"],
@@ -351,7 +366,7 @@ def main():
             "peak": peak,
             "unit": "TFLOP/s",
             "frac": achieved / peak,
-            "traffic": traffic_for(args.precision),
+            "traffic": traffic_for(args.precision, args.workload),
         },
         "graph_depth": 0 if args.no_graphs else args.graph_depth,
         "kernel_ms": {"force": main_run["force_ms_mean"],
@@ -374,7 +389,7 @@ def main():
     if "serving" in legs:
         line["serving"] = run_serving(args.serve_jobs, args.serve_max_iter, 64.0, args.serve_warmup)
     if "cpu" in legs:
-        line["cpu_baseline"] = cpu_baseline(args.cpu_seconds, args.residues)
+        line["cpu_baseline"] = cpu_baseline(args.cpu_seconds, residues)
     print(json.dumps(line), flush=True)
 
 

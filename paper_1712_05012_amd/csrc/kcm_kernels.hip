@@ -908,11 +908,226 @@ __device__ __noinline__ PairSums pair_terms_fp64(const ChainDev *cd, int si, int
     return out;
 }
 
-// Mixed form: four waves per SIMD, the register budget (128) its common path
-// fits in; the rarely taken chunked-neighbour path spills a few values rather
-// than raise it.  The FP64 form's LDS list already limits it to fewer waves.
+// Solvation of one atom with more neighbours than the LDS list holds (dense
+// self-overlaps of random starts).  Called, out of line, by the force kernel's
+// wave for that atom; the common path keeps its list in LDS in one piece.
+// The neighbours are numbered in candidate order, as the kernel numbers them,
+// and taken in chunks of MAX_NBR, each enumerated again from the candidates
+// (the wave's stencil rows: off, rbase, nrows, T) into the kernel's LDS
+// arrays when needed.  Step 1 runs over every chunk; a sample's count
+// saturates at 2 (only 0, 1 and more matter) and keeps the single
+// overlapper's number.  Step 2 and the event scatter go chunk by chunk.  The
+// decisions are those of one list, so the results are the same.
+struct ChunkedSasa {
+    int ncov;                 // covered samples of this lane
+    long long own[3];         // this lane's share of the atom's own event sums
+};
+struct ChunkArgs {
+    int si, off, rbase, nrows, T, nn;
+};
 template <typename Real>
-__global__ __launch_bounds__(WAVE, sizeof(Real) == 4 ? 4 : 2) void k_force(Batch bt)
+__device__ __noinline__ ChunkedSasa sasa_chunked(const ChainDev *cd, const ChunkArgs c, NbrEntry<Real> *s_nbr,
+                                                 int *s_nbr_a, unsigned *s_ev01, int *s_ev2)
+{
+    constexpr bool MIXED = sizeof(Real) == 4;
+    const int lane = threadIdx.x & (WAVE - 1);
+    const unsigned long long below = (1ull << lane) - 1ull;
+    // the atom's quantities, read again rather than passed (the call then
+    // keeps few of the kernel's registers live)
+    struct {
+        int si, off, rbase, nrows, T, nn, N;
+        double4 ri;
+        double roff_i, inv_2roff, dr;
+        long long qf;
+    } a;
+    a.si = c.si; a.off = c.off; a.rbase = c.rbase; a.nrows = c.nrows; a.T = c.T; a.nn = c.nn;
+    a.N = cd->n_samples;
+    a.ri = cd->s_r[c.si];
+    a.roff_i = cd->s_p[c.si].w;
+    a.inv_2roff = 0.5 / a.roff_i;
+    a.dr = cd->delta_r;
+    a.qf = cd->qfix[(int)__double_as_longlong(a.ri.w)];
+    const Real drr = (Real)a.dr, kq = (Real)(a.dr * a.dr / (2.0 * a.roff_i)), k1 = (Real)(a.dr / a.roff_i);
+    const Real guard = MIXED ? (Real)(2.0f * MIXED_BAND) : (Real)1e-9;
+    ChunkedSasa out = {0, {0, 0, 0}};
+
+    // neighbours numbered [lo, lo + len) into LDS positions 0 .. len-1
+    auto enum_window = [&](int lo, int len) {
+        int nb = 0;
+#pragma unroll 1
+        for (int kb = 0; kb < a.T; kb += WAVE) {
+            const int k = kb + lane;
+            int r = 0;
+#pragma unroll
+            for (int step = 32; step >= 1; step >>= 1) {
+                const int t = r + step;
+                const int o = __shfl(a.off, t & (WAVE - 1), WAVE);
+                if (t < a.nrows && o <= k) r = t;
+            }
+            int sj = __shfl(a.rbase, r, WAVE) + k;
+            const bool valid = k < a.T && sj != a.si;
+            if (k >= a.T) sj = a.si;
+            const double4 rj = cd->s_r[sj];
+            const double4 pj = cd->s_p[sj];
+            const double ddx = rj.x - a.ri.x, ddy = rj.y - a.ri.y, ddz = rj.z - a.ri.z;
+            const double d2 = ddx * ddx + ddy * ddy + ddz * ddz;
+            const double lim = a.roff_i + pj.w + a.dr;
+            const bool in_cav = valid && d2 <= lim * lim;
+            const unsigned long long m = __ballot(in_cav);
+            if (in_cav) {
+                const int pos = nb + __popcll(m & below) - lo;
+                if (pos >= 0 && pos < len) {
+                    NbrEntry<Real> e;
+                    e.ax = (Real)ddx; e.ay = (Real)ddy; e.az = (Real)ddz;
+                    e.c0 = (Real)((a.roff_i * a.roff_i + d2 - pj.w * pj.w) * a.inv_2roff);
+                    s_nbr[pos] = e;
+                    s_nbr_a[pos] = (int)__double_as_longlong(rj.w);
+                }
+            }
+            nb += __popcll(m);
+        }
+    };
+
+#pragma unroll 1
+    for (int kb = 0; kb < a.N; kb += WAVE * SPL) {
+        Real Qx[SPL], Qy[SPL], Qz[SPL];
+        int cnt[SPL], who[SPL];
+#pragma unroll
+        for (int i = 0; i < SPL; ++i) {
+            const int k = kb + lane + WAVE * i;
+            Qx[i] = Qy[i] = Qz[i] = (Real)0;
+            if (k < a.N) load_q<Real>(cd, k, Qx[i], Qy[i], Qz[i]);
+            cnt[i] = who[i] = 0;
+        }
+        // step 1 over every chunk
+        for (int lo = 0; lo < a.nn; lo += MAX_NBR) {
+            const int len = min(a.nn - lo, MAX_NBR);
+            __syncthreads();
+            enum_window(lo, len);
+            __syncthreads();
+            int acc[SPL];
+            Real amin[SPL];
+#pragma unroll
+            for (int i = 0; i < SPL; ++i) {
+                acc[i] = 0;
+                amin[i] = (Real)1e30;
+            }
+            for (int u = 0; u < len; ++u) {
+                const NbrEntry<Real> e = s_nbr[u];
+                const int inc = (1 << ACC_SHIFT) + u;
+#pragma unroll
+                for (int i = 0; i < SPL; ++i) {
+                    const Real t = fma(Qz[i], e.az, fma(Qy[i], e.ay, fma(Qx[i], e.ax, -e.c0)));
+                    acc[i] += (t >= (Real)0) ? inc : 0;
+                    if (MIXED) amin[i] = fmin(amin[i], fabs(t));
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < SPL; ++i) {
+                if (MIXED) {
+                    // a test within the band of its threshold: the whole wave
+                    // recounts that sample in FP64, one lane per neighbour
+                    unsigned long long bm = __ballot(kb + lane + WAVE * i < a.N && amin[i] <= (Real)MIXED_BAND);
+                    while (bm) {
+                        const int l = __ffsll((long long)bm) - 1;
+                        bm &= bm - 1;
+                        const int kl = kb + l + WAVE * i;
+                        int part = 0;
+                        for (int u = lane; u < len; u += WAVE)
+                            if (cover_exact(cd, a.ri, a.roff_i, kl, s_nbr_a[u], -1)) part += (1 << ACC_SHIFT) + u;
+                        part = wave_sum_i(part);
+                        if (lane == l) acc[i] = part;
+                    }
+                }
+                const int cc = acc[i] >> ACC_SHIFT;
+                if (cc == 1) who[i] = lo + (acc[i] & ((1 << ACC_SHIFT) - 1));
+                cnt[i] = min(cnt[i] + cc, 2);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < SPL; ++i)
+            if (kb + lane + WAVE * i < a.N && cnt[i] >= 1) ++out.ncov;
+        // step 2 and the events, chunk by chunk
+        for (int lo = 0; lo < a.nn; lo += MAX_NBR) {
+            const int len = min(a.nn - lo, MAX_NBR);
+            __syncthreads();
+            enum_window(lo, len);
+            for (int u = lane; u < len; u += WAVE) {
+                s_ev01[u] = EV_INIT;
+                s_ev2[u] = 0;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int i = 0; i < SPL; ++i) {
+                const int k = kb + lane + WAVE * i;
+                const bool valid = k < a.N;
+                if (valid && cnt[i] == 1 && who[i] >= lo && who[i] < lo + len) {
+                    // critically overlapped: only the overlapper's shifted copies can expose it
+                    const int u = who[i] - lo;
+                    const NbrEntry<Real> e = s_nbr[u];
+                    const int aj = s_nbr_a[u];
+                    const Real base = Qx[i] * e.ax + Qy[i] * e.ay + Qz[i] * e.az - e.c0 - kq;
+                    const Real span = drr + k1 * fmax(fabs(e.ax), fmax(fabs(e.ay), fabs(e.az)));
+                    if (base - span <= guard) {
+                        unsigned inc01 = 0;
+                        if (!test_cover<Real, MIXED>(base + drr * Qx[i] - k1 * e.ax, cd, a.ri, a.roff_i, k, aj, 0)) inc01 += 1u;
+                        if (!test_cover<Real, MIXED>(base + drr * Qy[i] - k1 * e.ay, cd, a.ri, a.roff_i, k, aj, 1)) inc01 += 1u << 16;
+                        if (inc01) atomicAdd(&s_ev01[u], inc01);
+                        if (!test_cover<Real, MIXED>(base + drr * Qz[i] - k1 * e.az, cd, a.ri, a.roff_i, k, aj, 2)) atomicAdd(&s_ev2[u], 1);
+                    }
+                }
+                // exposed samples: one lane per neighbour, the samples broadcast
+                const unsigned long long em0 = __ballot(valid && cnt[i] == 0);
+                if (!em0) continue;
+                for (int v = 0; WAVE * v < len; ++v) {
+                    const int u = lane + WAVE * v;
+                    const bool own = u < len;
+                    const NbrEntry<Real> e = s_nbr[own ? u : 0];
+                    const int aj = s_nbr_a[own ? u : 0];
+                    const Real lim = -(drr + k1 * fmax(fabs(e.ax), fmax(fabs(e.ay), fabs(e.az)))) - guard;
+                    int d0 = 0, d1 = 0, d2 = 0;
+                    unsigned long long em = em0;
+                    while (em) {
+                        const int l = __ffsll((long long)em) - 1;
+                        em &= em - 1;
+                        const Real qx = bcast(Qx[i], l), qy = bcast(Qy[i], l), qz = bcast(Qz[i], l);
+                        const Real base = qx * e.ax + qy * e.ay + qz * e.az - e.c0 - kq;
+                        if (own && base >= lim) {
+                            const int kx = kb + l + WAVE * i;
+                            if (test_cover<Real, MIXED>(base + drr * qx - k1 * e.ax, cd, a.ri, a.roff_i, kx, aj, 0)) --d0;
+                            if (test_cover<Real, MIXED>(base + drr * qy - k1 * e.ay, cd, a.ri, a.roff_i, kx, aj, 1)) --d1;
+                            if (test_cover<Real, MIXED>(base + drr * qz - k1 * e.az, cd, a.ri, a.roff_i, kx, aj, 2)) --d2;
+                        }
+                    }
+                    const unsigned dec01 = (unsigned)d0 + ((unsigned)d1 << 16);
+                    if (own && dec01) atomicAdd(&s_ev01[u], dec01);
+                    if (own && d2) atomicAdd(&s_ev2[u], d2);
+                }
+            }
+            __syncthreads();
+            // eq F_cav_patch: atom i gains G0_i ev / (N dr) per axis, neighbour j the opposite
+            for (int u = lane; u < len; u += WAVE) {
+                const unsigned w01 = s_ev01[u];
+                const int e0 = (int)(w01 & 0xffffu) - EV_BIAS, e1 = (int)(w01 >> 16) - EV_BIAS, e2 = s_ev2[u];
+                const int aj = s_nbr_a[u];
+                const int ev[3] = {e0, e1, e2};
+#pragma unroll
+                for (int x = 0; x < 3; ++x) {
+                    if (!ev[x]) continue;
+                    const long long f = (long long)ev[x] * a.qf;
+                    out.own[x] += f;
+                    atomicAdd((unsigned long long *)&cd->f_cav[3 * aj + x], (unsigned long long)(-f));
+                }
+            }
+        }
+    }
+    return out;
+}
+
+// Mixed form: four waves per SIMD, the register budget (128) it fits in.  The
+// FP64 form's LDS list already limits it to fewer waves.
+template <typename Real>
+__global__ __launch_bounds__(WAVE, sizeof(Real) == 4 ? 4 : 3) void k_force(Batch bt)
 {
     constexpr bool MIXED = sizeof(Real) == 4;
     __shared__ NbrEntry<Real> s_nbr[MAX_NBR];
@@ -1004,30 +1219,6 @@ __global__ __launch_bounds__(WAVE, sizeof(Real) == 4 ? 4 : 2) void k_force(Batch
         return __shfl(rbase, lo, WAVE) + k;
     };
 
-    // One candidate for the solvation list (offset spheres within reach of
-    // each other, eq F_cav_patch's neighbour set): the neighbours are
-    // numbered in candidate order from nb; those numbered in [lo, hi) are
-    // stored at LDS position (number - lo).  Returns the next number.
-    auto add_cav = [&](bool valid, const double4 &rj, const double4 &pj, int nb, int lo, int hi) -> int {
-        const double ddx = rj.x - ri.x, ddy = rj.y - ri.y, ddz = rj.z - ri.z;
-        const double d2 = ddx * ddx + ddy * ddy + ddz * ddz;
-        const double lim = roff_i + pj.w + dr;
-        const bool in_cav = valid && d2 <= lim * lim;
-        const unsigned long long m = __ballot(in_cav);
-        if (in_cav) {
-            const int pos = nb + __popcll(m & below);
-            if (pos >= lo && pos < hi) {
-                const double Rj = pj.w;
-                NbrEntry<Real> e;
-                e.ax = (Real)ddx; e.ay = (Real)ddy; e.az = (Real)ddz;
-                e.c0 = (Real)((roff_i * roff_i + d2 - Rj * Rj) * inv_2roff);
-                s_nbr[pos - lo] = e;
-                s_nbr_a[pos - lo] = (int)__double_as_longlong(rj.w);
-            }
-        }
-        return nb + __popcll(m);
-    };
-
     Real fx = 0, fy = 0, fz = 0;
     double ee = 0.0, evw = 0.0;
     int nn = 0;
@@ -1066,13 +1257,32 @@ __global__ __launch_bounds__(WAVE, sizeof(Real) == 4 ? 4 : 2) void k_force(Batch
                 evw += (double)elj;
             }
         }
-        if (do_cav) nn = add_cav(valid, rj, pj, nn, 0, MAX_NBR);
+        bool in_cav = false;
+        if (do_cav) {
+            const double lim = roff_i + pj.w + dr;
+            in_cav = valid && d2 <= lim * lim;
+        }
+        const unsigned long long m = __ballot(in_cav);
+        if (in_cav) {
+            const int pos = nn + __popcll(m & below);
+            if (pos < MAX_NBR) {
+                const double Rj = pj.w;
+                NbrEntry<Real> e;
+                e.ax = (Real)ddx; e.ay = (Real)ddy; e.az = (Real)ddz;
+                e.c0 = (Real)((roff_i * roff_i + d2 - Rj * Rj) * inv_2roff);
+                s_nbr[pos] = e;
+                s_nbr_a[pos] = aj;
+            }
+        }
+        nn += __popcll(m);
     };
 
     // CPT candidates per lane per trip, every load issued before any is used
     constexpr int CPT = 4;
-    auto fetch = [&](int kb, bool (&ok)[CPT], double4 (&rj)[CPT], double4 (&pj)[CPT]) {
+    for (int kb = 0; kb < T; kb += CPT * WAVE) {
         int sj[CPT];
+        bool ok[CPT];
+        double4 rj[CPT], pj[CPT];
 #pragma unroll
         for (int q = 0; q < CPT; ++q) {
             const int k = kb + q * WAVE + lane;
@@ -1085,37 +1295,15 @@ __global__ __launch_bounds__(WAVE, sizeof(Real) == 4 ? 4 : 2) void k_force(Batch
             rj[q] = cd->s_r[sj[q]];
             pj[q] = cd->s_p[sj[q]];
         }
-    };
-    for (int kb = 0; kb < T; kb += CPT * WAVE) {
-        bool ok[CPT];
-        double4 rj[CPT], pj[CPT];
-        fetch(kb, ok, rj, pj);
 #pragma unroll
         for (int q = 0; q < CPT; ++q) visit(ok[q], rj[q], pj[q]);
     }
-    // the solvation neighbours numbered [lo, hi) again, into LDS positions
-    // 0 .. hi-lo-1: same candidates in the same order (one per lane per
-    // trip, which keeps this rarely taken path light on registers), same
-    // decisions
-    auto enum_window = [&](int lo, int hi) {
-        int nb = 0;
-#pragma unroll 1
-        for (int kb = 0; kb < T; kb += WAVE) {
-            const int k = kb + lane;
-            int sj = cand_atom(k);
-            const bool ok = k < T && sj != si;
-            if (k >= T) sj = si;
-            const double4 rj = cd->s_r[sj];
-            const double4 pj = cd->s_p[sj];
-            nb = add_cav(ok, rj, pj, nb, lo, hi);
-        }
-    };
 
     // pair force and energies of atom i (each unordered pair is seen from both ends)
     double pv[5] = {(double)fx, (double)fy, (double)fz, ee, evw};
     const bool overflow = !(isfinite(pv[0]) && isfinite(pv[1]) && isfinite(pv[2]) && isfinite(ee) && isfinite(evw));
     if (MIXED && __any(overflow)) {
-        // Atoms a few hundredths of an angstrom apart drive (D/d)^12 and the
+        // Atoms a few thousandths of an angstrom apart drive (D/d)^12 and the
         // force past the FP32 range: this atom's pair terms are taken again,
         // all in FP64 (a non-finite result then is a true one)
         const PairSums ps = pair_terms_fp64(cd, si, off, rbase, T, nrows, res_i, m12, m13, m14, terms);
@@ -1131,14 +1319,11 @@ __global__ __launch_bounds__(WAVE, sizeof(Real) == 4 ? 4 : 2) void k_force(Batch
 
     double e_cav = 0.0, n_exp = -1.0;
     if (do_cav) {
-        // More neighbours than the LDS list holds: they are taken in chunks
-        // of MAX_NBR, each enumerated again from the candidates when needed.
         // The overlapper's number must fit the low field of acc.
         if (nn >= (1 << ACC_SHIFT)) {
             if (lane == 0) cd->stats->nbr_overflow = 1;
             nn = 0;
         }
-        const int nch = (nn + MAX_NBR - 1) / MAX_NBR;
         const int nnc = min(nn, MAX_NBR);
         const int N = cd->n_samples;
         const Real drr = (Real)dr;
@@ -1152,18 +1337,120 @@ __global__ __launch_bounds__(WAVE, sizeof(Real) == 4 ? 4 : 2) void k_force(Batch
         // three tests can be skipped with the same decisions.  guard holds
         // the FP32 decision band (mixed) or a rounding pad (FP64).
         const Real guard = MIXED ? (Real)(2.0f * MIXED_BAND) : (Real)1e-9;
-        auto clear_events = [&](int len) {
-            for (int u = lane; u < len; u += WAVE) {
+        int ncov = 0;
+        long long own0 = 0, own1 = 0, own2 = 0;
+        if (nn > MAX_NBR) {
+            // more neighbours than the LDS list holds: chunks, out of line
+            const ChunkArgs ca = {si, off, rbase, nrows, T, nn};
+            const ChunkedSasa cs = sasa_chunked<Real>(cd, ca, s_nbr, s_nbr_a, s_ev01, s_ev2);
+            ncov = cs.ncov;
+            own0 = cs.own[0];
+            own1 = cs.own[1];
+            own2 = cs.own[2];
+        } else {
+            for (int u = lane; u < nnc; u += WAVE) {
                 s_ev01[u] = EV_INIT;
                 s_ev2[u] = 0;
             }
-        };
-        // eq F_cav_patch: atom i gains G0_i ev / (N dr) per axis, neighbour j
-        // the opposite; own sums stay in registers until the end
-        const long long qf = cd->qfix[ai];
-        long long own0 = 0, own1 = 0, own2 = 0;
-        auto flush_events = [&](int len) {
-            for (int u = lane; u < len; u += WAVE) {
+            __syncthreads();
+            for (int kb = 0; kb < N; kb += WAVE * SPL) {
+                // step 1: coverage counts of SPL samples per lane
+                Real Qx[SPL], Qy[SPL], Qz[SPL], amin[SPL];
+                int acc[SPL];
+#pragma unroll
+                for (int i = 0; i < SPL; ++i) {
+                    const int k = kb + lane + WAVE * i;
+                    Qx[i] = Qy[i] = Qz[i] = (Real)0;
+                    if (k < N) load_q<Real>(cd, k, Qx[i], Qy[i], Qz[i]);
+                    acc[i] = 0;
+                    amin[i] = (Real)1e30;
+                }
+                for (int u = 0; u < nnc; ++u) {
+                    const NbrEntry<Real> e = s_nbr[u];
+                    const int inc = (1 << ACC_SHIFT) + u;
+#pragma unroll
+                    for (int i = 0; i < SPL; ++i) {
+                        const Real t = fma(Qz[i], e.az, fma(Qy[i], e.ay, fma(Qx[i], e.ax, -e.c0)));
+                        acc[i] += (t >= (Real)0) ? inc : 0;
+                        if (MIXED) amin[i] = fmin(amin[i], fabs(t));
+                    }
+                }
+#pragma unroll
+                for (int i = 0; i < SPL; ++i) {
+                    const int k = kb + lane + WAVE * i;
+                    const bool valid = k < N;
+                    if (MIXED) {
+                        // a test within the band of its threshold: the whole wave
+                        // recounts that sample in FP64, one lane per neighbour
+                        unsigned long long bm = __ballot(valid && amin[i] <= (Real)MIXED_BAND);
+                        while (bm) {
+                            const int l = __ffsll((long long)bm) - 1;
+                            bm &= bm - 1;
+                            const int kl = kb + l + WAVE * i;
+                            int part = 0;
+                            for (int u = lane; u < nnc; u += WAVE)
+                                if (cover_exact(cd, ri, roff_i, kl, s_nbr_a[u], -1)) part += (1 << ACC_SHIFT) + u;
+                            part = wave_sum_i(part);
+                            if (lane == l) acc[i] = part;
+                        }
+                    }
+                    const int C = acc[i] >> ACC_SHIFT;
+                    if (valid && C == 1) {
+                        // critically overlapped: only the overlapper's shifted copies can expose it
+                        const int u = acc[i] & ((1 << ACC_SHIFT) - 1);
+                        const NbrEntry<Real> e = s_nbr[u];
+                        const int aj = s_nbr_a[u];
+                        const Real base = Qx[i] * e.ax + Qy[i] * e.ay + Qz[i] * e.az - e.c0 - kq;
+                        const Real span = drr + k1 * fmax(fabs(e.ax), fmax(fabs(e.ay), fabs(e.az)));
+                        if (base - span <= guard) {
+                            unsigned inc01 = 0;
+                            if (!test_cover<Real, MIXED>(base + drr * Qx[i] - k1 * e.ax, cd, ri, roff_i, k, aj, 0)) inc01 += 1u;
+                            if (!test_cover<Real, MIXED>(base + drr * Qy[i] - k1 * e.ay, cd, ri, roff_i, k, aj, 1)) inc01 += 1u << 16;
+                            if (inc01) atomicAdd(&s_ev01[u], inc01);
+                            if (!test_cover<Real, MIXED>(base + drr * Qz[i] - k1 * e.az, cd, ri, roff_i, k, aj, 2)) atomicAdd(&s_ev2[u], 1);
+                        }
+                    }
+                    if (valid && C >= 1) ++ncov;
+                    // step 2 for the exposed samples of this slot: one lane per
+                    // neighbour, the samples broadcast from their lanes
+                    const unsigned long long em0 = __ballot(valid && C == 0);
+                    if (em0) {
+#pragma unroll
+                        for (int v = 0; v < NSLOT; ++v) {
+                            if (WAVE * v >= nnc) break;
+                            const int u = lane + WAVE * v;
+                            const bool own = u < nnc;
+                            const NbrEntry<Real> e = s_nbr[own ? u : 0];
+                            const int aj = s_nbr_a[own ? u : 0];
+                            const Real lim = -(drr + k1 * fmax(fabs(e.ax), fmax(fabs(e.ay), fabs(e.az)))) - guard;
+                            int d0 = 0, d1 = 0, d2 = 0;
+                            unsigned long long em = em0;
+                            while (em) {
+                                const int l = __ffsll((long long)em) - 1;
+                                em &= em - 1;
+                                const Real qx = bcast(Qx[i], l), qy = bcast(Qy[i], l), qz = bcast(Qz[i], l);
+                                const Real base = qx * e.ax + qy * e.ay + qz * e.az - e.c0 - kq;
+                                if (own && base >= lim) {
+                                    const int kx = kb + l + WAVE * i;
+                                    if (test_cover<Real, MIXED>(base + drr * qx - k1 * e.ax, cd, ri, roff_i, kx, aj, 0)) --d0;
+                                    if (test_cover<Real, MIXED>(base + drr * qy - k1 * e.ay, cd, ri, roff_i, kx, aj, 1)) --d1;
+                                    if (test_cover<Real, MIXED>(base + drr * qz - k1 * e.az, cd, ri, roff_i, kx, aj, 2)) --d2;
+                                }
+                            }
+                            // the lane owns neighbour u here, but critical samples of
+                            // other lanes add to the same words: keep atomics
+                            const unsigned dec01 = (unsigned)d0 + ((unsigned)d1 << 16);
+                            if (dec01) atomicAdd(&s_ev01[u], dec01);
+                            if (d2) atomicAdd(&s_ev2[u], d2);
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+
+            // eq F_cav_patch: atom i gains G0_i ev / (N dr) per axis, neighbour j the opposite
+            const long long qf = cd->qfix[ai];
+            for (int u = lane; u < nnc; u += WAVE) {
                 const unsigned w01 = s_ev01[u];
                 const int e0 = (int)(w01 & 0xffffu) - EV_BIAS, e1 = (int)(w01 >> 16) - EV_BIAS, e2 = s_ev2[u];
                 if (!(e0 | e1 | e2)) continue;
@@ -1171,166 +1458,6 @@ __global__ __launch_bounds__(WAVE, sizeof(Real) == 4 ? 4 : 2) void k_force(Batch
                 if (e0) { const long long x = (long long)e0 * qf; own0 += x; atomicAdd((unsigned long long *)&cd->f_cav[3 * aj + 0], (unsigned long long)(-x)); }
                 if (e1) { const long long x = (long long)e1 * qf; own1 += x; atomicAdd((unsigned long long *)&cd->f_cav[3 * aj + 1], (unsigned long long)(-x)); }
                 if (e2) { const long long x = (long long)e2 * qf; own2 += x; atomicAdd((unsigned long long *)&cd->f_cav[3 * aj + 2], (unsigned long long)(-x)); }
-            }
-        };
-        int ncov = 0;
-        // coverage counts of SPL samples per lane over the len neighbours now
-        // in LDS: acc = (covering count << ACC_SHIFT) + (sum of their LDS
-        // positions); amin: the smallest |tested value| (mixed form)
-        auto count_chunk = [&](const Real (&Qx)[SPL], const Real (&Qy)[SPL], const Real (&Qz)[SPL], int len,
-                               int (&acc)[SPL], Real (&amin)[SPL]) {
-#pragma unroll
-            for (int i = 0; i < SPL; ++i) {
-                acc[i] = 0;
-                amin[i] = (Real)1e30;
-            }
-            for (int u = 0; u < len; ++u) {
-                const NbrEntry<Real> e = s_nbr[u];
-                const int inc = (1 << ACC_SHIFT) + u;
-#pragma unroll
-                for (int i = 0; i < SPL; ++i) {
-                    const Real t = fma(Qz[i], e.az, fma(Qy[i], e.ay, fma(Qx[i], e.ax, -e.c0)));
-                    acc[i] += (t >= (Real)0) ? inc : 0;
-                    if (MIXED) amin[i] = fmin(amin[i], fabs(t));
-                }
-            }
-        };
-        // a test within the band of its threshold: the whole wave recounts
-        // sample kb + l + WAVE i in FP64, one lane per neighbour
-        auto recount = [&](int kb, int i, int len, int &acc, Real amin) {
-            unsigned long long bm = __ballot(kb + lane + WAVE * i < N && amin <= (Real)MIXED_BAND);
-            while (bm) {
-                const int l = __ffsll((long long)bm) - 1;
-                bm &= bm - 1;
-                const int kl = kb + l + WAVE * i;
-                int part = 0;
-                for (int u = lane; u < len; u += WAVE)
-                    if (cover_exact(cd, ri, roff_i, kl, s_nbr_a[u], -1)) part += (1 << ACC_SHIFT) + u;
-                part = wave_sum_i(part);
-                if (lane == l) acc = part;
-            }
-        };
-        // step 2 of the samples in slot i against the neighbours numbered
-        // [lo, lo + len), held at LDS positions 0 .. len-1.  acc: count of
-        // the sample's overlappers (0, 1 or more) << ACC_SHIFT, plus the
-        // single overlapper's number when the count is 1.
-        auto step2_slot = [&](int kb, int i, Real qxi, Real qyi, Real qzi, int acc, int lo, int len) {
-            const int k = kb + lane + WAVE * i;
-            const bool valid = k < N;
-            const int C = acc >> ACC_SHIFT, U = acc & ((1 << ACC_SHIFT) - 1);
-            if (lo == 0 && valid && C >= 1) ++ncov;
-            if (valid && C == 1 && U >= lo && U < lo + len) {
-                // critically overlapped: only the overlapper's shifted copies can expose it
-                const int u = U - lo;
-                const NbrEntry<Real> e = s_nbr[u];
-                const int aj = s_nbr_a[u];
-                const Real base = qxi * e.ax + qyi * e.ay + qzi * e.az - e.c0 - kq;
-                const Real span = drr + k1 * fmax(fabs(e.ax), fmax(fabs(e.ay), fabs(e.az)));
-                if (base - span <= guard) {
-                    unsigned inc01 = 0;
-                    if (!test_cover<Real, MIXED>(base + drr * qxi - k1 * e.ax, cd, ri, roff_i, k, aj, 0)) inc01 += 1u;
-                    if (!test_cover<Real, MIXED>(base + drr * qyi - k1 * e.ay, cd, ri, roff_i, k, aj, 1)) inc01 += 1u << 16;
-                    if (inc01) atomicAdd(&s_ev01[u], inc01);
-                    if (!test_cover<Real, MIXED>(base + drr * qzi - k1 * e.az, cd, ri, roff_i, k, aj, 2)) atomicAdd(&s_ev2[u], 1);
-                }
-            }
-            // the exposed samples of this slot: one lane per neighbour, the
-            // samples broadcast from their lanes
-            const unsigned long long em0 = __ballot(valid && C == 0);
-            if (em0) {
-#pragma unroll
-                for (int v = 0; v < NSLOT; ++v) {
-                    if (WAVE * v >= len) break;
-                    const int u = lane + WAVE * v;
-                    const bool own = u < len;
-                    const NbrEntry<Real> e = s_nbr[own ? u : 0];
-                    const int aj = s_nbr_a[own ? u : 0];
-                    const Real lim = -(drr + k1 * fmax(fabs(e.ax), fmax(fabs(e.ay), fabs(e.az)))) - guard;
-                    int d0 = 0, d1 = 0, d2 = 0;
-                    unsigned long long em = em0;
-                    while (em) {
-                        const int l = __ffsll((long long)em) - 1;
-                        em &= em - 1;
-                        const Real qx = bcast(qxi, l), qy = bcast(qyi, l), qz = bcast(qzi, l);
-                        const Real base = qx * e.ax + qy * e.ay + qz * e.az - e.c0 - kq;
-                        if (own && base >= lim) {
-                            const int kx = kb + l + WAVE * i;
-                            if (test_cover<Real, MIXED>(base + drr * qx - k1 * e.ax, cd, ri, roff_i, kx, aj, 0)) --d0;
-                            if (test_cover<Real, MIXED>(base + drr * qy - k1 * e.ay, cd, ri, roff_i, kx, aj, 1)) --d1;
-                            if (test_cover<Real, MIXED>(base + drr * qz - k1 * e.az, cd, ri, roff_i, kx, aj, 2)) --d2;
-                        }
-                    }
-                    // the lane owns neighbour u here, but critical samples of
-                    // other lanes add to the same words: keep atomics
-                    const unsigned dec01 = (unsigned)d0 + ((unsigned)d1 << 16);
-                    if (dec01) atomicAdd(&s_ev01[u], dec01);
-                    if (d2) atomicAdd(&s_ev2[u], d2);
-                }
-            }
-        };
-        auto load_slots = [&](int kb, Real (&Qx)[SPL], Real (&Qy)[SPL], Real (&Qz)[SPL]) {
-#pragma unroll
-            for (int i = 0; i < SPL; ++i) {
-                const int k = kb + lane + WAVE * i;
-                Qx[i] = Qy[i] = Qz[i] = (Real)0;
-                if (k < N) load_q<Real>(cd, k, Qx[i], Qy[i], Qz[i]);
-            }
-        };
-        if (nch == 1) {
-            // the whole list is in LDS: step 1 and step 2 per pass of samples
-            clear_events(nnc);
-            __syncthreads();
-            for (int kb = 0; kb < N; kb += WAVE * SPL) {
-                Real Qx[SPL], Qy[SPL], Qz[SPL], amin[SPL];
-                int acc[SPL];
-                load_slots(kb, Qx, Qy, Qz);
-                count_chunk(Qx, Qy, Qz, nnc, acc, amin);
-#pragma unroll
-                for (int i = 0; i < SPL; ++i) {
-                    if (MIXED) recount(kb, i, nnc, acc[i], amin[i]);
-                    step2_slot(kb, i, Qx[i], Qy[i], Qz[i], acc[i], 0, nnc);
-                }
-            }
-            __syncthreads();
-            flush_events(nnc);
-        } else {
-            // chunks of MAX_NBR neighbours, enumerated again for each use:
-            // step 1 over every chunk (the count saturates at 2, only 0, 1
-            // and more matter), then step 2 and the events chunk by chunk
-            for (int kb = 0; kb < N; kb += WAVE * SPL) {
-                Real Qx[SPL], Qy[SPL], Qz[SPL], amin[SPL];
-                int acc[SPL];
-                load_slots(kb, Qx, Qy, Qz);
-                int cnt[SPL], who[SPL];
-#pragma unroll
-                for (int i = 0; i < SPL; ++i) cnt[i] = who[i] = 0;
-                for (int ch = 0; ch < nch; ++ch) {
-                    const int lo = ch * MAX_NBR, len = min(nn - lo, MAX_NBR);
-                    __syncthreads();
-                    enum_window(lo, lo + len);
-                    __syncthreads();
-                    count_chunk(Qx, Qy, Qz, len, acc, amin);
-#pragma unroll
-                    for (int i = 0; i < SPL; ++i) {
-                        if (MIXED) recount(kb, i, len, acc[i], amin[i]);
-                        const int cc = acc[i] >> ACC_SHIFT;
-                        if (cc == 1) who[i] = lo + (acc[i] & ((1 << ACC_SHIFT) - 1));
-                        cnt[i] = min(cnt[i] + cc, 2);
-                    }
-                }
-#pragma unroll
-                for (int i = 0; i < SPL; ++i) acc[i] = (cnt[i] << ACC_SHIFT) + (cnt[i] == 1 ? who[i] : 0);
-                for (int ch = 0; ch < nch; ++ch) {
-                    const int lo = ch * MAX_NBR, len = min(nn - lo, MAX_NBR);
-                    __syncthreads();
-                    enum_window(lo, lo + len);
-                    clear_events(len);
-                    __syncthreads();
-#pragma unroll
-                    for (int i = 0; i < SPL; ++i) step2_slot(kb, i, Qx[i], Qy[i], Qz[i], acc[i], lo, len);
-                    __syncthreads();
-                    flush_events(len);
-                }
             }
         }
         __syncthreads();
