@@ -224,6 +224,35 @@ def run_serving(n_jobs: int, max_iter: int, budget_gib: float, skip: int):
     return out
 
 
+def run_landscape(step_deg: float = 5.0, batch: int = 1024):
+    """Ramachandran energy map of a residue pair (one residue type), every joint
+    fixed: grid points evaluated per second, host marshalling included."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1712_05012_amd import kcm
+    from paper_1712_05012_amd.landscape import EnergyScanner, grid_thetas
+
+    T = synth.residue_types()
+    res = np.zeros(2, np.int32)
+    vals = np.radians(np.arange(-180.0, 180.0, step_deg))
+    grid = grid_thetas(np.full(4, np.pi), [2, 3], [vals, vals])
+    sc = EnergyScanner(res, T, kcm.kcm_default_params(precision=kcm.KCM_MIXED), batch=batch)
+    sc.energies(grid[:batch])  # warm-up: graphs and first launches
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    E = sc.energies(grid)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    sc.free()
+    return {"grid_points": int(len(grid)), "step_deg": step_deg, "batch": batch, "seconds": dt,
+            "points_per_s": len(grid) / dt, "atom_steps_per_s": 20 * len(grid) / dt,
+            "e_min": float(E.sum(axis=1).min()),
+            "note": "residue pair of type 0 (20 atoms), (phi, psi) of the second residue, mixed precision; "
+                    "per point: set the dihedrals, rebuild the grid, one iteration with every joint fixed"}
+
+
 def traffic_for(precision: str, workload_name: str = "globule1000"):
     """HBM bytes per force launch from committed rocprofv3 counters, if still current."""
     if not os.path.exists(TRAFFIC_FILE):
@@ -276,8 +305,8 @@ def main():
     ap.add_argument("--serve-warmup", type=int, default=100,
                     help="earliest jobs left out of the serving latency percentiles")
     ap.add_argument("--serve-max-iter", type=int, default=2000)
-    ap.add_argument("--legs", default="main,companion,batch,serving,cpu",
-                    help="comma-separated legs to run (main, companion, batch, serving, cpu); "
+    ap.add_argument("--legs", default="main,companion,batch,serving,landscape,cpu",
+                    help="comma-separated legs to run (main, companion, batch, serving, landscape, cpu); "
                          "profiling runs use a subset, the benchmark line needs main")
     ap.add_argument("--graph-depth", type=int, default=8,
                     help="iterations per replayed HIP graph in the single-chain legs")
@@ -329,6 +358,8 @@ def main():
             line["batched"] = run_batch(args.batch_steps, 5, direct=args.no_graphs)
         if "serving" in legs:
             line["serving"] = run_serving(args.serve_jobs, args.serve_max_iter, 64.0, args.serve_warmup)
+        if "landscape" in legs:
+            line["landscape"] = run_landscape()
         print(json.dumps(line), flush=True)
         return
 
@@ -388,6 +419,8 @@ def main():
         line["batched"] = b
     if "serving" in legs:
         line["serving"] = run_serving(args.serve_jobs, args.serve_max_iter, 64.0, args.serve_warmup)
+    if "landscape" in legs:
+        line["landscape"] = run_landscape()
     if "cpu" in legs:
         line["cpu_baseline"] = cpu_baseline(args.cpu_seconds, residues)
     print(json.dumps(line), flush=True)

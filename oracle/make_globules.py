@@ -13,8 +13,8 @@ rescaled until the final Rg is within 5 % of the target.
 
 Usage: python -m oracle.make_globules 1000 10000 [--seed S] [--out-dir DIR]
 
-The stored files were written with the default seed (1000 residues) and with
-the seed their design notes give (10,000 residues).
+Both stored files (1000 and 10,000 residues) were written with the default
+seed.
 """
 from __future__ import annotations
 

@@ -153,13 +153,16 @@ std::vector<V3> sample_directions(int n_orb)
 struct Layout {
     size_t desc, stats, grid, theta, dtheta, tau, mask, joint0, jcur, xform, xform_loc, blk_xf, tmax_part, bad_part;
     size_t r0, r, aparam, g0, qfix;
-    size_t cell_key, cell_count, cell_start, bbox_part, wrench_part, s_r, s_p, s_tmp, s_idx, s_cell;
+    size_t cell_key, cell_count, cell_start, cell_local, scan_part, bbox_part, wrench_part, s_r, s_p, s_tmp, s_idx, s_cell;
     size_t f_pair, f_cav;
     size_t e_atom;
     size_t q64, q32;
     size_t total;
     int n, J, L, N, cap;
 };
+
+static_assert((8LL * APR * (1 << 19) + SCAN_CHUNK - 1) / SCAN_CHUNK <= SCAN_MAX_CHUNKS,
+              "the largest chain's grid capacity must fit the scan's chunk table");
 
 Layout make_layout(int m, int n_orb)
 {
@@ -200,6 +203,8 @@ Layout make_layout(int m, int n_orb)
     l.cell_key = take(4 * n);
     l.cell_count = take(4 * cap);
     l.cell_start = take(4 * (cap + 1));
+    l.cell_local = take(4 * cap);
+    l.scan_part = take(4 * ((cap + SCAN_CHUNK - 1) / SCAN_CHUNK));
     const size_t nblk = (n + ATOM_BLOCK - 1) / ATOM_BLOCK;
     l.bbox_part = take(8 * 6 * nblk);
     l.wrench_part = take(8 * WPART * nblk);
@@ -220,7 +225,8 @@ Layout make_layout(int m, int n_orb)
 kcm_status check_inputs(const kcm_chain_desc *d, const kcm_params *p)
 {
     if (!d || !p) return fail(KCM_E_INVAL, "null desc or params");
-    if (d->n_res < 1 || d->n_res > (1 << 22)) return fail(KCM_E_INVAL, "n_res out of range");
+    // the grid capacity (8 cells per atom) must fit the scan's chunk table
+    if (d->n_res < 1 || d->n_res > (1 << 19)) return fail(KCM_E_INVAL, "n_res out of range (1 .. 524288)");
     if (!d->res_type || !d->types || d->n_types < 1) return fail(KCM_E_INVAL, "missing residue types");
     for (int i = 0; i < d->n_res; ++i)
         if (d->res_type[i] < 0 || d->res_type[i] >= d->n_types) return fail(KCM_E_INVAL, "res_type out of range");
@@ -394,7 +400,8 @@ kcm_status ensure_table(kcm_chain *const *chains, int n_chains, hipStream_t stre
         const size_t off_pos = (sizeof(ChainDev *) * n_chains + 255) & ~size_t(255);
         const size_t blk_pos = off_pos + ints;
         const size_t jblk_pos = blk_pos + ints;
-        const size_t need = jblk_pos + sizeof(int32_t) * (n_chains + 1);
+        const size_t scan_pos = jblk_pos + ints;
+        const size_t need = scan_pos + sizeof(int32_t) * (n_chains + 1);
         if (need > t->cap) {
             if (t->dev) {
                 HIP_TRY(hipStreamSynchronize(stream));
@@ -410,20 +417,28 @@ kcm_status ensure_table(kcm_chain *const *chains, int n_chains, hipStream_t stre
         int32_t *off = reinterpret_cast<int32_t *>(host.data() + off_pos);
         int32_t *blk = reinterpret_cast<int32_t *>(host.data() + blk_pos);
         int32_t *jblk = reinterpret_cast<int32_t *>(host.data() + jblk_pos);
-        long long total = 0, blocks = 0, jblocks = 0;
+        int32_t *sblk = reinterpret_cast<int32_t *>(host.data() + scan_pos);
+        long long total = 0, blocks = 0, jblocks = 0, sblocks = 0;
+        int max_chunks = 1;
         for (int i = 0; i < n_chains; ++i) {
             tab[i] = chains[i]->d_desc;
             off[i] = (int32_t)total;
             blk[i] = (int32_t)blocks;
             jblk[i] = (int32_t)jblocks;
+            sblk[i] = (int32_t)sblocks;
             total += chains[i]->n;
             blocks += (chains[i]->n + ATOM_BLOCK - 1) / ATOM_BLOCK;
             jblocks += (chains[i]->J + JOINT_BLOCK - 1) / JOINT_BLOCK;
+            const int chunks = (chains[i]->h.cap_cells + SCAN_CHUNK - 1) / SCAN_CHUNK;
+            sblocks += chunks;
+            max_chunks = std::max(max_chunks, chunks);
         }
-        if (total > std::numeric_limits<int32_t>::max()) return fail(KCM_E_INVAL, "too many atoms in one call");
+        if (total > std::numeric_limits<int32_t>::max() || sblocks > std::numeric_limits<int32_t>::max())
+            return fail(KCM_E_INVAL, "too many atoms in one call");
         off[n_chains] = (int32_t)total;
         blk[n_chains] = (int32_t)blocks;
         jblk[n_chains] = (int32_t)jblocks;
+        sblk[n_chains] = (int32_t)sblocks;
         HIP_TRY(hipMemcpyAsync(t->dev, host.data(), need, hipMemcpyHostToDevice, stream));
         HIP_TRY(hipStreamSynchronize(stream));
         unsigned char *d = static_cast<unsigned char *>(t->dev);
@@ -431,10 +446,13 @@ kcm_status ensure_table(kcm_chain *const *chains, int n_chains, hipStream_t stre
         t->batch.atom_off = reinterpret_cast<const int32_t *>(d + off_pos);
         t->batch.blk_off = reinterpret_cast<const int32_t *>(d + blk_pos);
         t->batch.jblk_off = reinterpret_cast<const int32_t *>(d + jblk_pos);
+        t->batch.scan_off = reinterpret_cast<const int32_t *>(d + scan_pos);
         t->batch.n_chains = n_chains;
         t->batch.total_atoms = (int)total;
         t->batch.total_blocks = (int)blocks;
         t->batch.total_jblocks = (int)jblocks;
+        t->batch.total_scan_blocks = (int)sblocks;
+        t->batch.max_scan_chunks = max_chunks;
         t->chains.assign(chains, chains + n_chains);
         if (t->graph) {
             HIP_TRY(hipGraphExecDestroy(t->graph));
@@ -642,6 +660,8 @@ kcm_status kcm_build_chain(const kcm_chain_desc *desc, const kcm_params *params,
     PTR(cell_key, int32_t *);
     PTR(cell_count, int32_t *);
     PTR(cell_start, int32_t *);
+    PTR(cell_local, int32_t *);
+    PTR(scan_part, int32_t *);
     PTR(bbox_part, double *);
     PTR(wrench_part, double *);
     PTR(s_r, double4 *);

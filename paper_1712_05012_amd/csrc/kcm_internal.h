@@ -10,6 +10,8 @@ namespace kcm {
 
 constexpr int APR = 10;              // atoms per residue
 constexpr int CHAIN_THREADS = 1024;  // one workgroup per chain: 16 waves
+constexpr int SCAN_CHUNK = 16384;    // cells per workgroup of the cell-count scan
+constexpr int SCAN_MAX_CHUNKS = 4096;  // chunks per chain the scatter's offset table holds
 constexpr int JOINT_BLOCK = 256;     // joints per workgroup of the torque / step / kinematics kernels
 constexpr int MAX_NBR = 384;         // solvation neighbours of one atom kept in LDS
 constexpr int MAX_REACH = 3;         // cell-stencil half width the force kernel supports (cells >= reach/3)
@@ -77,7 +79,9 @@ struct ChainDev {
     long long *qfix;     // [n] event quantum G0/(N dr) in fixed point
     int32_t *cell_key;   // [n] cell of each atom
     int32_t *cell_count; // [cap] atoms per cell (zero between iterations)
-    int32_t *cell_start; // [cap+1]
+    int32_t *cell_start; // [cap+1] cell starts in the cell-ordered arrays
+    int32_t *cell_local; // [cap] exclusive scan of the counts inside each chunk of SCAN_CHUNK cells
+    int32_t *scan_part;  // [cap / SCAN_CHUNK, rounded up] cell count of each chunk
     double *bbox_part;   // [blocks][6] per-workgroup min xyz, max xyz of the placed atoms
     double *wrench_part; // [blocks][WPART] per-workgroup wrench (F, r x F), energies, failure flag
     double4 *s_r;        // [n] positions in cell order
@@ -104,10 +108,13 @@ struct Batch {
     const int32_t *atom_off;
     const int32_t *blk_off;
     const int32_t *jblk_off;
+    const int32_t *scan_off;  // cumulative count of SCAN_CHUNK-cell chunks of the chains' capacities
     int n_chains;
     int total_atoms;
     int total_blocks;
     int total_jblocks;
+    int total_scan_blocks;
+    int max_scan_chunks;      // most chunks of one chain (sizes the chunk-offset table in LDS)
 };
 
 // Modes of the step/kinematics and placement kernels.

@@ -16,7 +16,9 @@
 //               earlier joint blocks composed in front of the block-local
 //               ones), r_a = G_link(a) r0_a, cell key on the grid of Sec. 3.2,
 //               cell count, bounding box of the new positions.
-//   k_cellscan  one workgroup per chain: cell starts by an exclusive scan.
+//   k_cellscan  one workgroup per 16384 cells: exclusive scan of the counts
+//               inside the chunk, and its total.
+//   (k_scatter and k_rank add the chunk offsets; k_rank writes the starts.)
 //   k_scatter   one thread per atom: counting-sort scatter by cell key.
 //   k_rank      one thread per atom: stable slot inside the cell, gather.
 //   k_force     one wave per atom, atoms in cell order: stencil candidates
@@ -666,51 +668,33 @@ __global__ void k_finish(Batch bt)
 // cell list: exclusive scan of the counts, counting-sort scatter, stable
 // order inside each cell, gather into cell order
 // ---------------------------------------------------------------------------
-constexpr int SCAN_CHUNK = 16384;
 // LDS index of scan element i: one pad word per 32 elements, so the threads of
 // a wave reading their runs of consecutive elements hit different banks
 __device__ __forceinline__ int scan_pad(int i) { return i + (i >> 5); }
 constexpr int SCAN_LDS = SCAN_CHUNK + SCAN_CHUNK / 32;
 
-// cell_start = exclusive scan of the counts of the current grid, in LDS
-// chunks with a carry.  Block-wide (CHAIN_THREADS); s_buf: SCAN_LDS ints.
-__device__ void scan_cells(const ChainDev *cd, int *s_buf, int *s_int)
+// Chunk offsets of the chain's current grid, block-wide: s_off[b] = number of
+// atoms in the cells of the chunks before chunk b, for b = 0 .. nb (s_off[nb]:
+// all atoms).  The cell start of cell c is cell_local[c] + s_off[c / SCAN_CHUNK].
+__device__ void chunk_offsets(const ChainDev *cd, int nc, int *s_off, int *s_int)
 {
-    const int nc = cd->grid->n_cells;
-    const int *__restrict__ count = cd->cell_count;
-    int *__restrict__ start = cd->cell_start;
-    const int tid = threadIdx.x, nt = blockDim.x;
-    constexpr int PER = SCAN_CHUNK / CHAIN_THREADS;
-    int carry = 0;
-    for (int c0 = 0; c0 < nc; c0 += SCAN_CHUNK) {
-        const int m = min(SCAN_CHUNK, nc - c0);
-#pragma unroll
-        for (int k = 0; k < PER; ++k) {
-            const int i = k * nt + tid;
-            s_buf[scan_pad(i)] = i < m ? count[c0 + i] : 0;
-        }
-        __syncthreads();
-        int loc = 0;
-#pragma unroll
-        for (int k = 0; k < PER; ++k) loc += s_buf[scan_pad(tid * PER + k)];
-        int total = 0;
-        int run = carry + block_excl_scan(loc, s_int, &total);
-#pragma unroll
-        for (int k = 0; k < PER; ++k) {
-            const int v = s_buf[scan_pad(tid * PER + k)];
-            s_buf[scan_pad(tid * PER + k)] = run;
-            run += v;
-        }
-        __syncthreads();
-#pragma unroll
-        for (int k = 0; k < PER; ++k) {
-            const int i = k * nt + tid;
-            if (i < m) start[c0 + i] = s_buf[scan_pad(i)];
-        }
-        carry += total;
-        __syncthreads();
+    const int nb = (nc + SCAN_CHUNK - 1) / SCAN_CHUNK;
+    const int tid = threadIdx.x, per = (nb + blockDim.x - 1) / blockDim.x;
+    int loc = 0;
+    for (int k = 0; k < per; ++k) {
+        const int b = tid * per + k;
+        if (b < nb) loc += cd->scan_part[b];
     }
-    if (tid == 0) start[nc] = carry;
+    int total = 0;
+    int run = block_excl_scan(loc, s_int, &total);
+    for (int k = 0; k < per; ++k) {
+        const int b = tid * per + k;
+        if (b < nb) {
+            s_off[b] = run;
+            run += cd->scan_part[b];
+        }
+    }
+    if (tid == 0) s_off[nb] = total;
     __syncthreads();
 }
 
@@ -731,36 +715,88 @@ __device__ __forceinline__ void place_sorted(const ChainDev *cd, const int *ids,
     cd->s_p[pos] = cd->aparam[a];
 }
 
-// k_cellscan: one workgroup per chain; k_scatter and k_rank: one thread per atom.
+// k_cellscan: one workgroup per chunk of SCAN_CHUNK cells of each chain's
+// capacity (chunks past the current grid return at once): the exclusive scan
+// of the counts inside the chunk, and the chunk's total.  The chunk offsets
+// are added by the scatter and rank kernels; k_rank writes the final starts.
 __global__ __launch_bounds__(CHAIN_THREADS) void k_cellscan(Batch bt)
 {
-    const ChainDev *cd = bt.table[blockIdx.x];
+    const int c = find_block_owner(bt.scan_off, bt.n_chains, blockIdx.x);
+    const ChainDev *cd = bt.table[c];
     if (!running(cd->stats)) return;
+    const int b = blockIdx.x - bt.scan_off[c];
+    const int nc = cd->grid->n_cells, c0 = b * SCAN_CHUNK;
+    if (c0 >= nc) return;
     __shared__ int s_buf[SCAN_LDS];
     __shared__ int s_int[CHAIN_THREADS / WAVE];
-    scan_cells(cd, s_buf, s_int);
+    const int *__restrict__ count = cd->cell_count;
+    int *__restrict__ local = cd->cell_local;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    constexpr int PER = SCAN_CHUNK / CHAIN_THREADS;
+    const int m = min(SCAN_CHUNK, nc - c0);
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int i = k * nt + tid;
+        s_buf[scan_pad(i)] = i < m ? count[c0 + i] : 0;
+    }
+    __syncthreads();
+    int loc = 0;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) loc += s_buf[scan_pad(tid * PER + k)];
+    int total = 0;
+    int run = block_excl_scan(loc, s_int, &total);
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int v = s_buf[scan_pad(tid * PER + k)];
+        s_buf[scan_pad(tid * PER + k)] = run;
+        run += v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int i = k * nt + tid;
+        if (i < m) local[c0 + i] = s_buf[scan_pad(i)];
+    }
+    if (tid == 0) cd->scan_part[b] = total;
 }
 
+// k_scatter and k_rank: one thread per atom; the dynamic LDS holds the chunk
+// offsets (SCAN_MAX_CHUNKS + 1 ints at most).
 __global__ __launch_bounds__(ATOM_BLOCK) void k_scatter(Batch bt)
 {
+    extern __shared__ int s_off[];
+    __shared__ int s_int[ATOM_BLOCK / WAVE];
     const int c = find_block_owner(bt.blk_off, bt.n_chains, blockIdx.x);
     const ChainDev *cd = bt.table[c];
     if (!running(cd->stats)) return;
+    chunk_offsets(cd, cd->grid->n_cells, s_off, s_int);
     const int a = (blockIdx.x - bt.blk_off[c]) * ATOM_BLOCK + threadIdx.x;
     if (a >= cd->n_atoms) return;
     const int key = cd->cell_key[a];
-    cd->s_tmp[cd->cell_start[key] + atomicSub(&cd->cell_count[key], 1) - 1] = a;
+    const int start = cd->cell_local[key] + s_off[key / SCAN_CHUNK];
+    cd->s_tmp[start + atomicSub(&cd->cell_count[key], 1) - 1] = a;
 }
 
 __global__ __launch_bounds__(ATOM_BLOCK) void k_rank(Batch bt)
 {
+    extern __shared__ int s_off[];
+    __shared__ int s_int[ATOM_BLOCK / WAVE];
     const int c = find_block_owner(bt.blk_off, bt.n_chains, blockIdx.x);
     const ChainDev *cd = bt.table[c];
     if (!running(cd->stats)) return;
-    const int a = (blockIdx.x - bt.blk_off[c]) * ATOM_BLOCK + threadIdx.x;
+    const int nc = cd->grid->n_cells, nb = (nc + SCAN_CHUNK - 1) / SCAN_CHUNK;
+    chunk_offsets(cd, nc, s_off, s_int);
+    // the final cell starts (nc + 1 of them), a slice per workgroup of the chain
+    const int lb = blockIdx.x - bt.blk_off[c], nblk = bt.blk_off[c + 1] - bt.blk_off[c];
+    const int per = (nc + 1 + nblk - 1) / nblk, i1 = min(nc + 1, (lb + 1) * per);
+    for (int i = lb * per + (int)threadIdx.x; i < i1; i += ATOM_BLOCK)
+        cd->cell_start[i] = i < nc ? cd->cell_local[i] + s_off[i / SCAN_CHUNK] : s_off[nb];
+    const int a = lb * ATOM_BLOCK + threadIdx.x;
     if (a >= cd->n_atoms) return;
     const int key = cd->cell_key[a];
-    place_sorted(cd, cd->s_tmp, a, key, cd->cell_start[key], cd->cell_start[key + 1]);
+    const int b = cd->cell_local[key] + s_off[key / SCAN_CHUNK];
+    const int e = key + 1 < nc ? cd->cell_local[key + 1] + s_off[(key + 1) / SCAN_CHUNK] : s_off[nb];
+    place_sorted(cd, cd->s_tmp, a, key, b, e);
 }
 
 // ---------------------------------------------------------------------------
@@ -1593,21 +1629,22 @@ hipError_t launch_place(const Batch &b, int mode, hipStream_t s)
 hipError_t launch_cellscan(const Batch &b, hipStream_t s)
 {
     if (b.n_chains <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_cellscan, dim3(b.n_chains), dim3(CHAIN_THREADS), 0, s, b);
+    if (b.total_scan_blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_cellscan, dim3(b.total_scan_blocks), dim3(CHAIN_THREADS), 0, s, b);
     return hipGetLastError();
 }
 
 hipError_t launch_scatter(const Batch &b, hipStream_t s)
 {
     if (b.total_blocks <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_scatter, dim3(b.total_blocks), dim3(ATOM_BLOCK), 0, s, b);
+    hipLaunchKernelGGL(k_scatter, dim3(b.total_blocks), dim3(ATOM_BLOCK), sizeof(int) * (b.max_scan_chunks + 1), s, b);
     return hipGetLastError();
 }
 
 hipError_t launch_rank(const Batch &b, hipStream_t s)
 {
     if (b.total_blocks <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_rank, dim3(b.total_blocks), dim3(ATOM_BLOCK), 0, s, b);
+    hipLaunchKernelGGL(k_rank, dim3(b.total_blocks), dim3(ATOM_BLOCK), sizeof(int) * (b.max_scan_chunks + 1), s, b);
     return hipGetLastError();
 }
 

@@ -1,0 +1,94 @@
+"""Energy landscapes: grid construction (host) and parity of the scanned
+energies with the oracle (GPU)."""
+import numpy as np
+import pytest
+
+from paper_1712_05012_amd.landscape import grid_thetas
+
+
+def test_grid_thetas_combinations_and_order():
+    th0 = np.arange(8, dtype=np.float64)
+    g = grid_thetas(th0, [2, 5], [[10.0, 11.0, 12.0], [20.0, 21.0]])
+    assert g.shape == (6, 8)
+    # the last joint runs fastest; other joints stay at theta0
+    assert np.array_equal(g[:, 2], [10, 10, 11, 11, 12, 12])
+    assert np.array_equal(g[:, 5], [20, 21, 20, 21, 20, 21])
+    keep = [0, 1, 3, 4, 6, 7]
+    assert np.array_equal(g[:, keep], np.repeat(th0[None, keep], 6, axis=0))
+
+
+def test_grid_thetas_rejects_bad_input():
+    with pytest.raises(ValueError):
+        grid_thetas(np.zeros(4), [0, 1], [[0.0]])
+    with pytest.raises(ValueError):
+        grid_thetas(np.zeros(4), [4], [[0.0]])
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("precision", [0, 1])
+def test_ramachandran_map_matches_oracle(precision):
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import oracle
+    from gpu_common import TYPES, oracle_step, params
+    from paper_1712_05012_amd import kcm
+    from paper_1712_05012_amd.landscape import ramachandran
+
+    kcm.load_library()
+    p = params(precision)
+    res = np.array([0, 0], np.int32)  # a residue pair of one type
+    phi, psi, E = ramachandran(res, TYPES, residue=1, step_deg=30.0, params=p)
+    assert E.shape == (12, 12, 3)
+    ref = oracle.OracleChain(res, TYPES, g_hydro=p.g_hydro)
+    mask = np.zeros(4, np.uint8)
+    tol = 1e-9 if precision == kcm.KCM_FP64 else 1e-5
+    worst = [0.0, 0.0, 0.0]
+    ties = 0
+    for i, a in enumerate(phi):
+        for j, b in enumerate(psi):
+            th = np.full(4, np.pi)
+            th[2], th[3] = a, b
+            o = oracle_step(ref, th, p, mask)
+            for k, name in enumerate(("E_elec", "E_vdw", "E_cav")):
+                if k == 2 and o["margin"] <= 1e-10:
+                    ties += 1
+                    continue
+                worst[k] = max(worst[k], abs(E[i, j, k] - o[name]) / max(abs(o[name]), 1.0))
+    print(f"case=ramachandran precision={precision} worst={worst} ties={ties}", flush=True)
+    assert worst[0] < tol and worst[1] < tol
+    assert worst[2] < 1e-12
+    assert ties <= 2
+
+
+@pytest.mark.gpu
+def test_hinge_scan_matches_oracle():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import oracle
+    import synth
+    from gpu_common import TYPES, oracle_step, params
+    from paper_1712_05012_amd import kcm
+    from paper_1712_05012_amd.landscape import EnergyScanner
+
+    kcm.load_library()
+    p = params(kcm.KCM_MIXED)
+    m, seed = 40, 77
+    seq = synth.sequence(m, seed)
+    th0 = synth.random_dihedrals(m, seed)
+    vals = np.radians(np.arange(-180.0, 180.0, 45.0))
+    grid = grid_thetas(th0, [38, 41], [vals, vals])  # psi of residue 19, phi of residue 20
+    sc = EnergyScanner(seq, TYPES, p, batch=24)  # fewer slots than points: several calls
+    E = sc.energies(grid)
+    sc.free()
+    ref = oracle.OracleChain(seq, TYPES, g_hydro=p.g_hydro)
+    mask = np.zeros(2 * m, np.uint8)
+    worst = 0.0
+    for g, th in enumerate(grid):
+        o = oracle_step(ref, th, p, mask)
+        worst = max(worst, max(abs(E[g, k] - o[n]) / max(abs(o[n]), 1.0) for k, n in enumerate(("E_elec", "E_vdw"))))
+        if o["margin"] > 1e-10:
+            assert abs(E[g, 2] - o["E_cav"]) <= 1e-12 * max(abs(o["E_cav"]), 1.0)
+    print(f"case=hinge_scan points={len(grid)} worst_pair_energy={worst}", flush=True)
+    assert worst < 1e-5
