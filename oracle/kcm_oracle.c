@@ -703,6 +703,52 @@ int or_sasa_atoms(int n, const double *r, const double *R, const double *gamma, 
 }
 
 /* ------------------------------------------------------------------ */
+/* Side-chain joints (Sec. 2.1: chi dihedrals of the side-chain branch) */
+/* ------------------------------------------------------------------ */
+/* chi_i is the dihedral N-CA-CB-HB1 of residue i (60 degrees in the zero
+ * position).  The branch it turns is HB1..HB3, which turn rigidly about the
+ * CA->CB bond; nothing else moves.  Given the positions r of or_fk (the
+ * branch at its zero-position chi), turn each residue's branch by
+ * chi_i - 60 degrees about its current CA->CB axis (right-handed, so the
+ * dihedral grows with chi) and return that axis and the point CA. */
+int or_fk_chi(int m, const double *chi, double *r, double *u, double *p)
+{
+    for (int i = 0; i < m; ++i) {
+        const double *CA = r + 3 * (APR * i + A_CA), *CB = r + 3 * (APR * i + A_CB);
+        double d[3], ax[3], R[9];
+        v_sub(CB, CA, d);
+        v_unit(d, ax);
+        m_rot(ax, chi[i] - deg(60.0), R);
+        for (int h = A_HB1; h <= A_HB3; ++h) {
+            double *x = r + 3 * (APR * i + h), e[3], f[3];
+            v_sub(x, CB, e);
+            m_vec(R, e, f);
+            for (int k = 0; k < 3; ++k) x[k] = CB[k] + f[k];
+        }
+        if (u) memcpy(u + 3 * i, ax, sizeof ax);
+        if (p) memcpy(p + 3 * i, CA, sizeof(double) * 3);
+    }
+    return 0;
+}
+
+/* tau_chi_i = u_i . sum over HB1..HB3 of residue i of (r_a - p_i) x F_a. */
+int or_torques_chi(int m, const double *r, const double *F, const double *u, const double *p, double *tau)
+{
+    for (int i = 0; i < m; ++i) {
+        double acc = 0.0;
+        for (int h = A_HB1; h <= A_HB3; ++h) {
+            const int a = APR * i + h;
+            double d[3], c[3];
+            v_sub(r + 3 * a, p + 3 * i, d);
+            v_cross(d, F + 3 * a, c);
+            acc += v_dot(u + 3 * i, c);
+        }
+        tau[i] = acc;
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
 /* Joint torques, eqs (KCM_01), (KCM_02), (KCM_04)-(KCM_06)             */
 /* ------------------------------------------------------------------ */
 /* Direct sum: tau_j = u_j . sum_{a in links > j} (r_a - p_j) x F_a. */

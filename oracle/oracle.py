@@ -68,6 +68,8 @@ def _load():
     lib.or_sasa_events.argtypes = [C.c_int, _dp, _dp, _dp, C.c_int, C.POINTER(_SasaP), _ip, vp]
     lib.or_sasa_atoms.argtypes = [C.c_int, _dp, _dp, _dp, _dp, C.c_int, C.POINTER(_SasaP), _dp, vp, vp]
     lib.or_torques.argtypes = [C.c_int, _dp, _dp, _dp, _dp, _dp]
+    lib.or_fk_chi.argtypes = [C.c_int, _dp, _dp, _dp, _dp]
+    lib.or_torques_chi.argtypes = [C.c_int, _dp, _dp, _dp, _dp, _dp]
     lib.or_step.argtypes = [C.c_int, _dp, vp, C.c_int, C.c_double, C.c_double, _dp, vp, vp]
     lib.or_threads.argtypes = []
     _lib = lib
@@ -147,13 +149,24 @@ class OracleChain:
 
 
 def fk(chain: OracleChain, theta):
-    """Eqs (kin_02)-(kin_04), (r1): positions r[n,3], joint axes u[J,3], joint points p[J,3]."""
+    """Eqs (kin_02)-(kin_04), (r1): positions r[n,3], joint axes u[J,3], joint points p[J,3].
+
+    theta holds the 2m backbone angles (phi_1, psi_1, ...), optionally
+    followed by the m side-chain angles chi_1..chi_m (Sec. 2.1); their axes
+    and points then follow the backbone joints' in u and p."""
     th = np.ascontiguousarray(theta, dtype=np.float64)
-    assert th.shape == (chain.J,)
+    J = th.size
+    assert J in (chain.J, chain.J + chain.m)
     r = np.zeros((chain.n, 3))
-    u = np.zeros((chain.J, 3))
-    p = np.zeros((chain.J, 3))
-    _load().or_fk(chain.m, chain.r0, th, r, _ptr(u), _ptr(p))
+    u = np.zeros((J, 3))
+    p = np.zeros((J, 3))
+    _load().or_fk(chain.m, chain.r0, np.ascontiguousarray(th[: chain.J]), r, _ptr(u), _ptr(p))
+    if J > chain.J:
+        uc = np.zeros((chain.m, 3))
+        pc = np.zeros((chain.m, 3))
+        _load().or_fk_chi(chain.m, np.ascontiguousarray(th[chain.J:]), r, uc, pc)
+        u[chain.J:] = uc
+        p[chain.J:] = pc
     return r, u, p
 
 
@@ -233,11 +246,23 @@ def sasa_definitional(r, R, sp: SasaParams = SasaParams(), Q=None):
 
 
 def torques(chain: OracleChain, r, F, u, p):
-    """Eqs (KCM_01)-(KCM_06): tau_j = u_j . sum_{a downstream of j} (r_a - p_j) x F_a."""
-    tau = np.zeros(chain.J)
-    _load().or_torques(chain.m, np.ascontiguousarray(r, dtype=np.float64),
-                       np.ascontiguousarray(F, dtype=np.float64), np.ascontiguousarray(u, dtype=np.float64),
-                       np.ascontiguousarray(p, dtype=np.float64), tau)
+    """Eqs (KCM_01)-(KCM_06): tau_j = u_j . sum_{a downstream of j} (r_a - p_j) x F_a.
+
+    With side-chain joints (u, p of 3m rows) the chi torques follow, each over
+    its residue's branch HB1..HB3."""
+    J = len(u)
+    tau = np.zeros(J)
+    r = np.ascontiguousarray(r, dtype=np.float64)
+    F = np.ascontiguousarray(F, dtype=np.float64)
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    p = np.ascontiguousarray(p, dtype=np.float64)
+    tb = np.zeros(chain.J)
+    _load().or_torques(chain.m, r, F, np.ascontiguousarray(u[: chain.J]), np.ascontiguousarray(p[: chain.J]), tb)
+    tau[: chain.J] = tb
+    if J > chain.J:
+        tc = np.zeros(chain.m)
+        _load().or_torques_chi(chain.m, r, F, np.ascontiguousarray(u[chain.J:]), np.ascontiguousarray(p[chain.J:]), tc)
+        tau[chain.J:] = tc
     return tau
 
 

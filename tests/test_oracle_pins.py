@@ -485,3 +485,85 @@ def test_fk_extend_grows_the_same_chain_as_fk():
         pos, M, p = oracle.fk_extend(ch, k, M, p, th[2 * k], th[2 * k + 1])
         grown[10 * k + 2: 10 * k + 2 + len(pos)] = pos
     assert np.array_equal(grown, r)
+
+
+# --------------------------------------------------------------------------
+# side-chain joints (Sec. 2.1): chi_i = dihedral N-CA-CB-HB1 turns HB1..HB3
+# --------------------------------------------------------------------------
+def _chi_thetas(m, seed):
+    rng = np.random.default_rng(500 + seed)
+    return np.concatenate([synth.random_dihedrals(m, 300 + seed), rng.uniform(-np.pi, np.pi, m)])
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_chi_kinematics_geometry_dihedrals_and_branch(seed):
+    m = 6
+    ch = chain(m, seed)
+    th = _chi_thetas(m, seed)
+    r, u, p = oracle.fk(ch, th)
+    rb, _, _ = oracle.fk(ch, th[: 2 * m])
+    assert u.shape == (3 * m, 3) and p.shape == (3 * m, 3)
+    # only the branch atoms HB1..HB3 differ from the backbone-only kinematics
+    branch = np.zeros(ch.n, bool)
+    for i in range(m):
+        branch[10 * i + 5: 10 * i + 8] = True
+    assert np.array_equal(r[~branch], rb[~branch])
+    # every bond length and bond angle of the zero position is kept
+    b = ch.bonds()
+    d0 = np.linalg.norm(ch.r0[b[:, 0]] - ch.r0[b[:, 1]], axis=1)
+    assert np.abs(np.linalg.norm(r[b[:, 0]] - r[b[:, 1]], axis=1) - d0).max() < 1e-12
+    for i in range(m):
+        CA, CB = 10 * i + 2, 10 * i + 4
+        for h in (5, 6, 7):
+            a0 = angle(ch.r0[CA], ch.r0[CB], ch.r0[10 * i + h])
+            assert abs(angle(r[CA], r[CB], r[10 * i + h]) - a0) < 1e-8
+        # chi is the dihedral N-CA-CB-HB1; HB2 and HB3 keep their 120 degree offsets
+        N = 10 * i
+        chi = dihedral(r[N], r[CA], r[CB], r[10 * i + 5])
+        assert abs(wrap(chi - th[2 * m + i])) < 1e-10
+        assert abs(wrap(dihedral(r[N], r[CA], r[CB], r[10 * i + 6]) - chi - 2 * np.pi / 3)) < 1e-10
+        assert abs(wrap(dihedral(r[N], r[CA], r[CB], r[10 * i + 7]) - chi + 2 * np.pi / 3)) < 1e-10
+        # axis along CA->CB through CA
+        assert np.allclose(u[2 * m + i], (r[CB] - r[CA]) / np.linalg.norm(r[CB] - r[CA]), atol=1e-12)
+        assert np.allclose(p[2 * m + i], r[CA], atol=1e-12)
+
+
+def test_chi_at_zero_position_leaves_the_template():
+    m = 3
+    ch = chain(m)
+    th = np.concatenate([np.full(2 * m, np.pi), np.full(m, np.radians(60.0))])
+    r, _, _ = oracle.fk(ch, th)
+    assert np.abs(r - ch.r0).max() < 1e-13
+
+
+@pytest.mark.parametrize("m,seed", [(4, 1), (7, 3)])
+def test_chi_torque_is_minus_energy_gradient(m, seed):
+    # all 3m torques against central differences of the pair energy
+    ch = chain(m, seed)
+    th = _chi_thetas(m, seed)
+    pp = oracle.PairParams(cutoff=1e6)
+
+    def E(t):
+        r, _, _ = oracle.fk(ch, t)
+        _, a, b = oracle.pair_forces(ch, r, pp)
+        return a + b
+
+    r, u, p = oracle.fk(ch, th)
+    F, _, _ = oracle.pair_forces(ch, r, pp)
+    tau = oracle.torques(ch, r, F, u, p)
+    h = 1e-6
+    fd = np.array([-(E(th + h * e) - E(th - h * e)) / (2 * h) for e in np.eye(3 * m)])
+    assert np.abs(tau - fd).max() < 1e-6 * max(1.0, np.abs(tau).max())
+    assert np.abs(tau[2 * m:]).max() > 0.0  # the branch feels the field
+
+
+def test_chi_step_moves_only_free_joints():
+    m = 5
+    ch = chain(m, 4)
+    th = _chi_thetas(m, 4)
+    mask = np.ones(3 * m, np.uint8)
+    mask[2 * m + 1] = 0
+    o = oracle.iterate(ch, th, terms="elec+vdw", mask=mask)
+    assert o["dtheta"].shape == (3 * m,)
+    assert o["dtheta"][2 * m + 1] == 0.0
+    assert np.abs(o["dtheta"][2 * m:]).max() > 0.0
