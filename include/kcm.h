@@ -66,8 +66,12 @@ typedef struct {
     const int32_t *res_type;        /* [m], values in 0 .. n_types-1 */
     const kcm_residue_type *types;  /* [n_types] */
     int32_t n_types;
-    const double *theta0;           /* [2m] initial phi_1, psi_1, ...; NULL = ZP */
-    const uint8_t *joint_mask;      /* [2m] 0 = joint held fixed (Sec. 4.1 options); NULL = all free */
+    const double *theta0;           /* [J] initial phi_1, psi_1, ..., phi_m, psi_m, then chi_1 .. chi_m
+                                       with side chains; NULL = ZP (phi = psi = 180, chi = 60 degrees) */
+    const uint8_t *joint_mask;      /* [J] 0 = joint held fixed (Sec. 4.1 options); NULL = all free */
+    int32_t side_chains;            /* 0: J = 2m backbone joints.  1: J = 3m, with one side-chain
+                                       joint per residue (Sec. 2.1): chi_i = dihedral N-CA-CB-HB1,
+                                       turning HB1..HB3 about the CA->CB bond */
 } kcm_chain_desc;
 
 /* Method parameters.  kcm_default_params() fills the defaults listed here. */
@@ -185,7 +189,8 @@ kcm_status kcm_get_cells(const kcm_chain *chain, void *hip_stream, int32_t *dims
                          double *origin, int32_t *n_cells, int32_t *order, int32_t *cell_start,
                          int32_t cell_start_capacity);
 
-/* Sizes of a built chain. */
+/* Sizes of a built chain: atoms, joints J (2m, or 3m with side chains),
+ * offset-sphere samples and the precision. */
 kcm_status kcm_chain_info(const kcm_chain *chain, int32_t *n_atoms, int32_t *n_joints,
                           int32_t *n_samples, int32_t *precision);
 

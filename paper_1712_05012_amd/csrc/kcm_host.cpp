@@ -159,17 +159,22 @@ struct Layout {
     size_t q64, q32;
     size_t total;
     int n, J, L, N, cap;
+    int n_chi, Jt, njb_bb, njb;  // side-chain joints, all joints, backbone and all joint blocks
 };
 
 static_assert((8LL * APR * (1 << 19) + SCAN_CHUNK - 1) / SCAN_CHUNK <= SCAN_MAX_CHUNKS,
               "the largest chain's grid capacity must fit the scan's chunk table");
 
-Layout make_layout(int m, int n_orb)
+Layout make_layout(int m, int n_orb, int side_chains)
 {
     Layout l{};
     l.n = APR * m;
     l.J = 2 * m;
     l.L = 2 * m + 1;
+    l.n_chi = side_chains ? m : 0;
+    l.Jt = l.J + l.n_chi;
+    l.njb_bb = (l.J + JOINT_BLOCK - 1) / JOINT_BLOCK;
+    l.njb = l.njb_bb + (l.n_chi + JOINT_BLOCK - 1) / JOINT_BLOCK;
     l.N = (int)sample_directions(n_orb).size();
     l.cap = std::max(8192, 8 * l.n);
     size_t off = 0;
@@ -183,18 +188,18 @@ Layout make_layout(int m, int n_orb)
     l.desc = take(sizeof(ChainDev));
     l.stats = take(sizeof(ChainStats));
     l.grid = take(sizeof(Grid));
-    l.theta = take(8 * J);
-    l.dtheta = take(8 * J);
-    l.tau = take(8 * J);
-    l.mask = take(J);
+    const size_t Jt = l.Jt;
+    l.theta = take(8 * Jt);
+    l.dtheta = take(8 * Jt);
+    l.tau = take(8 * Jt);
+    l.mask = take(Jt);
     l.joint0 = take(64 * J);
     l.jcur = take(64 * J);
     l.xform = take(96 * L);
-    const size_t njb = (J + JOINT_BLOCK - 1) / JOINT_BLOCK;
     l.xform_loc = take(96 * J);
-    l.blk_xf = take(96 * njb);
-    l.tmax_part = take(8 * njb);
-    l.bad_part = take(4 * njb);
+    l.blk_xf = take(96 * (size_t)l.njb_bb);
+    l.tmax_part = take(8 * (size_t)l.njb);
+    l.bad_part = take(4 * (size_t)l.njb);
     l.r0 = take(32 * n);
     l.r = take(32 * n);
     l.aparam = take(32 * n);
@@ -227,6 +232,7 @@ kcm_status check_inputs(const kcm_chain_desc *d, const kcm_params *p)
     if (!d || !p) return fail(KCM_E_INVAL, "null desc or params");
     // the grid capacity (8 cells per atom) must fit the scan's chunk table
     if (d->n_res < 1 || d->n_res > (1 << 19)) return fail(KCM_E_INVAL, "n_res out of range (1 .. 524288)");
+    if (d->side_chains != 0 && d->side_chains != 1) return fail(KCM_E_INVAL, "side_chains must be 0 or 1");
     if (!d->res_type || !d->types || d->n_types < 1) return fail(KCM_E_INVAL, "missing residue types");
     for (int i = 0; i < d->n_res; ++i)
         if (d->res_type[i] < 0 || d->res_type[i] >= d->n_types) return fail(KCM_E_INVAL, "res_type out of range");
@@ -373,7 +379,8 @@ struct kcm_chain {
     void *dev_mem;
     size_t bytes;
     int device;
-    int m, n, J, N;
+    int m, n, J, N;      // J: all joints (backbone, then side chains)
+    int njb;             // joint blocks (backbone blocks, then side-chain blocks)
     std::vector<unsigned char> staging;  // host source of the build copies
     bool boot = true;    // the conformation has no grid yet (built, or new angles)
 };
@@ -428,7 +435,7 @@ kcm_status ensure_table(kcm_chain *const *chains, int n_chains, hipStream_t stre
             sblk[i] = (int32_t)sblocks;
             total += chains[i]->n;
             blocks += (chains[i]->n + ATOM_BLOCK - 1) / ATOM_BLOCK;
-            jblocks += (chains[i]->J + JOINT_BLOCK - 1) / JOINT_BLOCK;
+            jblocks += chains[i]->njb;
             const int chunks = (chains[i]->h.cap_cells + SCAN_CHUNK - 1) / SCAN_CHUNK;
             sblocks += chunks;
             max_chunks = std::max(max_chunks, chunks);
@@ -528,7 +535,7 @@ kcm_status kcm_chain_bytes(const kcm_chain_desc *desc, const kcm_params *params,
     if (!bytes) return fail(KCM_E_INVAL, "null bytes");
     kcm_status s = check_inputs(desc, params);
     if (s != KCM_OK) return s;
-    *bytes = make_layout(desc->n_res, params->n_orbits).total;
+    *bytes = make_layout(desc->n_res, params->n_orbits, desc->side_chains).total;
     return KCM_OK;
 }
 
@@ -541,7 +548,7 @@ kcm_status kcm_build_chain(const kcm_chain_desc *desc, const kcm_params *params,
     if (s != KCM_OK) return s;
     if (!dev_mem || (reinterpret_cast<uintptr_t>(dev_mem) & 255)) return fail(KCM_E_INVAL, "dev_mem must be 256-byte aligned");
     const int m = desc->n_res;
-    const Layout l = make_layout(m, params->n_orbits);
+    const Layout l = make_layout(m, params->n_orbits, desc->side_chains);
     if (bytes < l.total) return fail(KCM_E_NOMEM, "device block smaller than kcm_chain_bytes");
     hipStream_t stream = static_cast<hipStream_t>(hip_stream);
 
@@ -550,7 +557,8 @@ kcm_status kcm_build_chain(const kcm_chain_desc *desc, const kcm_params *params,
     c->bytes = bytes;
     c->m = m;
     c->n = l.n;
-    c->J = l.J;
+    c->J = l.Jt;
+    c->njb = l.njb;
     c->N = l.N;
     if (hipGetDevice(&c->device) != hipSuccess) c->device = 0;
     unsigned char *base = static_cast<unsigned char *>(dev_mem);
@@ -559,6 +567,8 @@ kcm_status kcm_build_chain(const kcm_chain_desc *desc, const kcm_params *params,
     std::memset(&h, 0, sizeof h);
     h.n_atoms = l.n;
     h.n_joints = l.J;
+    h.n_chi = l.n_chi;
+    h.n_bb_blocks = l.njb_bb;
     h.n_links = l.L;
     h.n_samples = l.N;
     h.cap_cells = l.cap;
@@ -613,10 +623,11 @@ kcm_status kcm_build_chain(const kcm_chain_desc *desc, const kcm_params *params,
         joint0[2 * j] = make_double4(u.x, u.y, u.z, 0.0);
         joint0[2 * j + 1] = make_double4(a.x, a.y, a.z, 0.0);
     }
-    std::vector<double> theta(l.J);
-    std::vector<uint8_t> mask(l.J);
-    for (int j = 0; j < l.J; ++j) {
-        double t = desc->theta0 ? desc->theta0[j] : kPi;
+    std::vector<double> theta(l.Jt);
+    std::vector<uint8_t> mask(l.Jt);
+    for (int j = 0; j < l.Jt; ++j) {
+        // zero position: phi = psi = 180 degrees, chi (N-CA-CB-HB1) = 60 degrees
+        double t = desc->theta0 ? desc->theta0[j] : (j < l.J ? kPi : kPi / 3.0);
         if (!std::isfinite(t)) {
             delete c;
             return fail(KCM_E_INVAL, "theta0 not finite");
@@ -685,8 +696,8 @@ kcm_status kcm_build_chain(const kcm_chain_desc *desc, const kcm_params *params,
     auto put = [&](size_t off, const void *src, size_t nbytes) { std::memcpy(c->staging.data() + off, src, nbytes); };
     put(l.desc, &h, sizeof h);
     put(l.stats, &st, sizeof st);
-    put(l.theta, theta.data(), 8 * l.J);
-    put(l.mask, mask.data(), l.J);
+    put(l.theta, theta.data(), 8 * (size_t)l.Jt);
+    put(l.mask, mask.data(), (size_t)l.Jt);
     put(l.joint0, joint0.data(), 32 * joint0.size());
     put(l.r0, r0.data(), 32 * (size_t)l.n);
     put(l.aparam, apar.data(), 32 * (size_t)l.n);

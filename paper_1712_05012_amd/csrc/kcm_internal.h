@@ -56,7 +56,10 @@ struct Grid {
 // Everything one chain owns on the device.  The struct itself lives at the
 // start of the chain's device block; every pointer points into that block.
 struct ChainDev {
-    int32_t n_atoms, n_joints, n_links, n_samples;
+    int32_t n_atoms, n_joints, n_links, n_samples;  // n_joints: the 2m backbone joints
+    int32_t n_chi;       // side-chain joints (0 or m), stored after the backbone joints
+    int32_t n_bb_blocks; // joint blocks of the backbone; the side-chain joints' blocks follow
+    int32_t pad_chi[2];
     int32_t cap_cells, precision, terms, step_rule;
     double cutoff, kappa, max_step, diel_k, coulomb;  // coulomb = C / diel_k
     double w13, w14e, w14v, delta_r, r_probe, cell_min, roff_max;

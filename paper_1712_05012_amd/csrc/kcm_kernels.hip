@@ -361,6 +361,23 @@ __global__ __launch_bounds__(JOINT_BLOCK) void k_tau(Batch bt)
     __shared__ double s_S[8][6];
     const int jb = blockIdx.x - bt.jblk_off[c];
     const int tid = threadIdx.x;
+    if (jb >= cd->n_bb_blocks) {
+        // a block of side-chain joints: k_wrench left each chi torque whole
+        const int jc = (jb - cd->n_bb_blocks) * JOINT_BLOCK + tid, j = cd->n_joints + jc;
+        double tabs = 0.0, bad = 0.0;
+        if (jc < cd->n_chi) {
+            const double t = cd->tau[j];
+            if (!isfinite(t)) bad = 1.0;
+            if (cd->mask[j]) tabs = fabs(t);
+        }
+        const double tmax = block_max(tabs, s_red);
+        const double anybad = block_max(bad, s_red);
+        if (tid == 0) {
+            cd->tmax_part[jb] = tmax;
+            cd->bad_part[jb] = anybad > 0.0 ? 1 : 0;
+        }
+        return;
+    }
     const int J = cd->n_joints, n = cd->n_atoms;
     const int nblk = (n + ATOM_BLOCK - 1) / ATOM_BLOCK;
     const double *__restrict__ part = cd->wrench_part;
@@ -454,13 +471,17 @@ __global__ __launch_bounds__(JOINT_BLOCK) void k_stepfk(Batch bt, int mode)
     const int jb = blockIdx.x - bt.jblk_off[c];
     const int tid = threadIdx.x, lane = tid & (WAVE - 1), w = tid / WAVE;
     const int J = cd->n_joints;
-    const int j = jb * JOINT_BLOCK + tid;
-    const bool valid = j < J;
+    // backbone blocks first; the blocks after them hold the side-chain joints,
+    // which step with the others but are not part of the chain's scan
+    const bool chi_block = jb >= cd->n_bb_blocks;
+    if (chi_block && mode == MODE_BOOT) return;
+    const int j = chi_block ? J + (jb - cd->n_bb_blocks) * JOINT_BLOCK + tid : jb * JOINT_BLOCK + tid;
+    const bool valid = chi_block ? j < J + cd->n_chi : j < J;
     double th = valid ? cd->theta[j] : 0.0;
     const bool lead = jb == 0 && tid == 0;
 
     if (mode != MODE_BOOT && st->pending_post) {
-        const int nb = (J + JOINT_BLOCK - 1) / JOINT_BLOCK;
+        const int nb = cd->n_bb_blocks + (cd->n_chi + JOINT_BLOCK - 1) / JOINT_BLOCK;
         double tm = 0.0, bad = 0.0;
         for (int b = tid; b < nb; b += JOINT_BLOCK) {
             tm = fmax(tm, cd->tmax_part[b]);
@@ -507,7 +528,7 @@ __global__ __launch_bounds__(JOINT_BLOCK) void k_stepfk(Batch bt, int mode)
     } else if (lead && mode != MODE_BOOT) {
         st->run = 1;
     }
-    if (mode == MODE_FINAL) return;
+    if (mode == MODE_FINAL || chi_block) return;
 
     Xf x = xf_identity();
     if (valid) x = joint_xf_of(cd->joint0[2 * j], cd->joint0[2 * j + 1], th);
@@ -592,7 +613,25 @@ __global__ __launch_bounds__(ATOM_BLOCK) void k_place(Batch bt, int mode)
     bool fin = true;
     if (a <= a1) {
         const double *L = s_G[link_of_atom(a) - l_lo];
-        const double4 q = cd->r0[a];
+        double4 q = cd->r0[a];
+        const int res = a / APR, slot = a - res * APR;
+        if (cd->n_chi && slot >= 5 && slot <= 7) {
+            // side-chain joint chi of the residue (dihedral N-CA-CB-HB1, 60
+            // degrees in the zero position): HB1..HB3 turn about CA->CB, here
+            // in the zero-position frame before the link transform
+            const double4 ca = cd->r0[res * APR + 2], cb = cd->r0[res * APR + 4];
+            double ux = cb.x - ca.x, uy = cb.y - ca.y, uz = cb.z - ca.z;
+            const double inv = 1.0 / sqrt(ux * ux + uy * uy + uz * uz);
+            ux *= inv; uy *= inv; uz *= inv;
+            double sn, cs;
+            sincos(cd->theta[cd->n_joints + res] - PI_D / 3.0, &sn, &cs);
+            const double vx = q.x - cb.x, vy = q.y - cb.y, vz = q.z - cb.z;
+            const double dot = ux * vx + uy * vy + uz * vz;
+            const double wx = uy * vz - uz * vy, wy = uz * vx - ux * vz, wz = ux * vy - uy * vx;
+            q.x = cb.x + vx * cs + wx * sn + ux * dot * (1.0 - cs);
+            q.y = cb.y + vy * cs + wy * sn + uy * dot * (1.0 - cs);
+            q.z = cb.z + vz * cs + wz * sn + uz * dot * (1.0 - cs);
+        }
         double4 r;
         r.x = L[0] * q.x + L[1] * q.y + L[2] * q.z + L[9];
         r.y = L[3] * q.x + L[4] * q.y + L[5] * q.z + L[10];
@@ -1572,6 +1611,26 @@ __global__ __launch_bounds__(ATOM_BLOCK) void k_wrench(Batch bt)
     }
     if (a < cd->n_atoms) {
         const int res = a / APR, slot = a - res * APR;
+        if (slot == 4 && cd->n_chi) {
+            // side-chain joint of the residue: its whole torque, over HB1..HB3
+            // (atoms a+1 .. a+3), about the CA->CB axis through CA
+            const double inv_fix = 1.0 / FIX_SCALE;
+            const double4 ca = cd->r[a - 2];
+            double ux = r.x - ca.x, uy = r.y - ca.y, uz = r.z - ca.z;
+            const double inv = 1.0 / sqrt(ux * ux + uy * uy + uz * uz);
+            ux *= inv; uy *= inv; uz *= inv;
+            double t = 0.0;
+            for (int h = 1; h <= 3; ++h) {
+                const int b = a + h;
+                const double4 fp = cd->f_pair[b], rb = cd->r[b];
+                const double Fx = fp.x + (double)cd->f_cav[3 * b] * inv_fix;
+                const double Fy = fp.y + (double)cd->f_cav[3 * b + 1] * inv_fix;
+                const double Fz = fp.z + (double)cd->f_cav[3 * b + 2] * inv_fix;
+                const double dx = rb.x - ca.x, dy = rb.y - ca.y, dz = rb.z - ca.z;
+                t += ux * (dy * Fz - dz * Fy) + uy * (dz * Fx - dx * Fz) + uz * (dx * Fy - dy * Fx);
+            }
+            cd->tau[cd->n_joints + res] = t;
+        }
         if (slot == 2 || slot == 8) {
             const int j = 2 * res + (slot == 8 ? 1 : 0);
             const double4 u = cd->jcur[2 * j], p = cd->jcur[2 * j + 1];

@@ -41,7 +41,8 @@ class kcm_residue_type(C.Structure):
 class kcm_chain_desc(C.Structure):
     _fields_ = [("n_res", C.c_int32), ("res_type", C.POINTER(C.c_int32)),
                 ("types", C.POINTER(kcm_residue_type)), ("n_types", C.c_int32),
-                ("theta0", C.POINTER(C.c_double)), ("joint_mask", C.POINTER(C.c_uint8))]
+                ("theta0", C.POINTER(C.c_double)), ("joint_mask", C.POINTER(C.c_uint8)),
+                ("side_chains", C.c_int32)]
 
 
 class kcm_params(C.Structure):
@@ -143,8 +144,11 @@ class ChainInputs:
     desc: kcm_chain_desc = field(default=None)
 
 
-def make_desc(res_type, residue_types, theta0=None, joint_mask=None) -> ChainInputs:
-    """residue_types: object with q, sigma, eps (n_types, 10) and hydro (n_types,) arrays."""
+def make_desc(res_type, residue_types, theta0=None, joint_mask=None, side_chains: bool = False) -> ChainInputs:
+    """residue_types: object with q, sigma, eps (n_types, 10) and hydro (n_types,) arrays.
+
+    theta0 and joint_mask hold 2 n_res backbone entries, followed by n_res
+    side-chain angles chi when ``side_chains`` is set."""
     rt = np.ascontiguousarray(res_type, dtype=np.int32)
     nt = len(residue_types.hydro)
     types = (kcm_residue_type * nt)()
@@ -155,10 +159,11 @@ def make_desc(res_type, residue_types, theta0=None, joint_mask=None) -> ChainInp
         types[t].hydrophobicity = float(residue_types.hydro[t])
     th = None if theta0 is None else np.ascontiguousarray(theta0, dtype=np.float64)
     mk = None if joint_mask is None else np.ascontiguousarray(joint_mask, dtype=np.uint8)
-    if th is not None and th.shape != (2 * rt.size,):
-        raise ValueError("theta0 must have 2*n_res entries")
-    if mk is not None and mk.shape != (2 * rt.size,):
-        raise ValueError("joint_mask must have 2*n_res entries")
+    J = (3 if side_chains else 2) * rt.size
+    if th is not None and th.shape != (J,):
+        raise ValueError(f"theta0 must have {J} entries")
+    if mk is not None and mk.shape != (J,):
+        raise ValueError(f"joint_mask must have {J} entries")
     d = kcm_chain_desc()
     d.n_res = rt.size
     d.res_type = rt.ctypes.data_as(C.POINTER(C.c_int32))
@@ -166,6 +171,7 @@ def make_desc(res_type, residue_types, theta0=None, joint_mask=None) -> ChainInp
     d.n_types = nt
     d.theta0 = th.ctypes.data_as(C.POINTER(C.c_double)) if th is not None else None
     d.joint_mask = mk.ctypes.data_as(C.POINTER(C.c_uint8)) if mk is not None else None
+    d.side_chains = 1 if side_chains else 0
     return ChainInputs(rt, types, th, mk, d)
 
 
@@ -245,6 +251,9 @@ def kcm_set_limits(handle, tol: float, max_iterations: int, stream=None):
 
 def kcm_set_theta(handle, theta, stream=None):
     th = np.ascontiguousarray(theta, dtype=np.float64)
+    _, J, _, _ = kcm_chain_info(handle)
+    if th.shape != (J,):
+        raise ValueError(f"theta must have {J} entries")
     _check(load_library().kcm_set_theta(handle, _p(th), _stream_handle(stream)))
 
 
@@ -293,10 +302,10 @@ class Chain:
     """Builds one chain in a torch-allocated device block on the current device."""
 
     def __init__(self, res_type, residue_types, params: kcm_params | None = None, theta0=None,
-                 joint_mask=None, stream=None, device=None):
+                 joint_mask=None, stream=None, device=None, side_chains: bool = False):
         import torch
         self.params = params if params is not None else kcm_default_params()
-        self.inputs = make_desc(res_type, residue_types, theta0, joint_mask)
+        self.inputs = make_desc(res_type, residue_types, theta0, joint_mask, side_chains)
         self.nbytes = kcm_chain_bytes(self.inputs, self.params)
         dev = torch.device("cuda") if device is None else torch.device(device)
         self.block = torch.empty(self.nbytes + 256, dtype=torch.uint8, device=dev)

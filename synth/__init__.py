@@ -15,6 +15,7 @@ from .chains import (  # noqa: F401
     batch_lengths,
     config_seed,
     load_globule,
+    random_chi,
     random_dihedrals,
     residue_types,
     sequence,

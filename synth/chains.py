@@ -86,6 +86,12 @@ def random_dihedrals(m: int, seed: int) -> np.ndarray:
     return np.pi - u
 
 
+def random_chi(m: int, seed: int) -> np.ndarray:
+    """(chi_1, ..., chi_m), side-chain angles, each uniform in (-pi, pi]."""
+    u = _rng(seed * 2 + 3).uniform(0.0, 2.0 * np.pi, int(m))
+    return np.pi - u
+
+
 def batch_lengths(n_chains: int, seed: int, lo: int = 50, hi: int = 600) -> np.ndarray:
     return _rng(seed).integers(lo, hi + 1, int(n_chains)).astype(np.int32)
 

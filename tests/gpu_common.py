@@ -35,10 +35,15 @@ def terms_str(t):
     return "+".join(parts)
 
 
-def build_pair(m, seed, p, theta=None, mask=None):
+def build_pair(m, seed, p, theta=None, mask=None, side_chains=False):
     seq = synth.sequence(m, seed)
-    th = synth.random_dihedrals(m, seed) if theta is None else np.asarray(theta, dtype=np.float64)
-    gpu = kcm.Chain(seq, TYPES, p, theta0=th, joint_mask=mask)
+    if theta is not None:
+        th = np.asarray(theta, dtype=np.float64)
+    elif side_chains:
+        th = np.concatenate([synth.random_dihedrals(m, seed), synth.random_chi(m, seed)])
+    else:
+        th = synth.random_dihedrals(m, seed)
+    gpu = kcm.Chain(seq, TYPES, p, theta0=th, joint_mask=mask, side_chains=side_chains)
     ref = oracle.OracleChain(seq, TYPES, g_hydro=p.g_hydro)
     return gpu, ref, th
 

@@ -1,0 +1,156 @@
+"""Side-chain joints (Sec. 2.1): parity of the HIP path with the FP64 oracle
+when every residue also carries its chi angle (J = 3m), needs an MI355X."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle  # noqa: E402
+import synth  # noqa: E402
+from gpu_common import DTHETA_TOL, F_TOL, TYPES, build_pair, compare_step, oracle_step, params  # noqa: E402
+from paper_1712_05012_amd import kcm  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+PRECISIONS = [kcm.KCM_FP64, kcm.KCM_MIXED]
+HB_SLOTS = (5, 6, 7)
+
+
+def _log(**kw):
+    print(" ".join(f"{k}={v}" for k, v in kw.items()), flush=True)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    kcm.load_library()
+
+
+def _wrap(x):
+    return np.abs(np.angle(np.exp(1j * x)))
+
+
+@pytest.mark.parametrize("precision", PRECISIONS)
+@pytest.mark.parametrize("m,seed", [(1, 61), (16, 62), (64, synth.config_seed(1))])
+def test_one_iteration_with_side_chains(precision, m, seed):
+    p = params(precision)
+    gpu, ref, th = build_pair(m, seed, p, side_chains=True)
+    assert gpu.n_joints == 3 * m
+    _log(case="side_chain_iteration", m=m, seed=seed, precision=precision)
+    st, o, err = compare_step(gpu, ref, th, p)
+    tc = np.abs(o["tau"][2 * m:]).max()
+    err["tau_chi"] = float(np.abs(st["tau"][2 * m:] - o["tau"][2 * m:]).max() / max(tc, 1e-300))
+    _log(**err)
+    assert err["status"] == 0
+    assert err["margin"] > 1e-10, "a sample test sits on a tie; pick another seed"
+    assert err["xyz"] < 1e-9
+    assert err["F"] <= F_TOL and err["F_pair"] <= F_TOL and err["F_cav"] <= F_TOL
+    assert err["dtheta"] <= DTHETA_TOL[precision] and err["theta"] <= DTHETA_TOL[precision]
+    if precision == kcm.KCM_FP64:
+        assert err["tau_chi"] <= 1e-9
+    assert err["E_cav"] < 1e-12
+    gpu.free()
+
+
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_side_chain_joints_alone(precision):
+    # backbone fixed, chi free: the chi joints step, the backbone atoms and
+    # every atom off the HB branches keep their positions exactly
+    p = params(precision)
+    m = 20
+    mask = np.zeros(3 * m, np.uint8)
+    mask[2 * m:] = 1
+    gpu, ref, th = build_pair(m, 71, p, mask=mask, side_chains=True)
+    st, o, err = compare_step(gpu, ref, th, p, mask=mask)
+    _log(case="chi_alone", precision=precision, **err)
+    assert err["status"] == 0 and err["margin"] > 1e-10
+    assert np.all(st["dtheta"][:2 * m] == 0.0)
+    assert np.abs(st["dtheta"][2 * m:]).max() > 0.0
+    assert err["dtheta"] <= DTHETA_TOL[precision] and err["theta"] <= DTHETA_TOL[precision]
+    x0 = st["xyz"].copy()
+    gpu.step(1)
+    x1 = gpu.state()["xyz"]
+    slot = np.arange(x0.shape[0]) % synth.ATOMS_PER_RES
+    off = ~np.isin(slot, HB_SLOTS)
+    assert np.array_equal(x0[off], x1[off])
+    assert np.abs(x1[~off] - x0[~off]).max() > 0.0
+    gpu.free()
+
+
+def test_zero_position_chi_reproduces_backbone_only_chain():
+    # chi at its zero position (60 degrees) leaves the template: the same
+    # positions, forces and backbone torques as the chain without side chains
+    p = params(kcm.KCM_FP64)
+    m = 12
+    bb = synth.random_dihedrals(m, 81)
+    a, _, _ = build_pair(m, 81, p, theta=np.concatenate([bb, np.full(m, np.pi / 3)]), side_chains=True)
+    b, _, _ = build_pair(m, 81, p, theta=bb)
+    a.step(1)
+    b.step(1)
+    sa, sb = a.state(), b.state()
+    assert np.abs(sa["xyz"] - sb["xyz"]).max() < 1e-12
+    assert np.abs(sa["force"] - sb["force"]).max() <= 1e-9 * np.abs(sb["force"]).max()
+    assert np.abs(sa["tau"][:2 * m] - sb["tau"]).max() <= 1e-9 * np.abs(sb["tau"]).max()
+    a.free()
+    b.free()
+
+
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_side_chain_trajectory(precision):
+    # 20 iterations on the device in one call against 20 oracle iterations
+    p = params(precision)
+    m = 24
+    gpu, ref, th = build_pair(m, 91, p, side_chains=True)
+    rep = gpu.step(20)
+    assert rep.status == 0 and rep.iterations == 20
+    t = th.copy()
+    for _ in range(20):
+        t = oracle_step(ref, t, p)["theta"]
+    err = float(_wrap(gpu.state()["theta"] - t).max())
+    _log(case="chi_trajectory20", precision=precision, dtheta=err)
+    assert err <= 20 * DTHETA_TOL[precision]
+    gpu.free()
+
+
+def test_batch_mixes_side_chain_and_backbone_chains():
+    # one call over chains with and without side chains (and more than one
+    # workgroup of chi joints) equals separate calls bit for bit, and each
+    # chain follows its own oracle trajectory
+    p = params(kcm.KCM_FP64)
+    spec = [(20, 101, True), (33, 102, False), (5, 103, True), (300, 104, True)]
+    batch = [build_pair(m, s, p, side_chains=sc) for m, s, sc in spec]
+    alone = [build_pair(m, s, p, side_chains=sc)[0] for m, s, sc in spec]
+    _, reps = kcm.kcm_step([g for g, _, _ in batch], 3)
+    for g in alone:
+        g.step(3)
+    for (m, s, sc), (g, ref, th), a, r in zip(spec, batch, alone, reps):
+        assert r.status == 0 and r.iterations == 3
+        tb, ta = g.state()["theta"], a.state()["theta"]
+        assert tb.size == (3 if sc else 2) * m
+        assert np.array_equal(tb, ta), (m, sc)
+        t = th.copy()
+        for _ in range(3):
+            t = oracle_step(ref, t, p)["theta"]
+        err = float(_wrap(tb - t).max())
+        _log(case="mixed_batch", m=m, side_chains=sc, dtheta=err)
+        assert err <= 3 * DTHETA_TOL[kcm.KCM_FP64]
+    for g, _, _ in batch:
+        g.free()
+    for a in alone:
+        a.free()
+
+
+def test_side_chain_inputs_are_validated():
+    p = params(kcm.KCM_FP64)
+    seq = synth.sequence(4, 1)
+    with pytest.raises(ValueError):
+        kcm.Chain(seq, TYPES, p, theta0=np.zeros(8), side_chains=True)
+    c = kcm.Chain(seq, TYPES, p, side_chains=True)
+    assert c.n_joints == 12
+    th = c.state()["theta"]
+    assert np.allclose(th[:8], np.pi) and np.allclose(th[8:], np.pi / 3)
+    with pytest.raises(ValueError):
+        c.set_theta(np.zeros(8))
+    c.free()
+    assert oracle.OracleChain(seq, TYPES).J == 8
