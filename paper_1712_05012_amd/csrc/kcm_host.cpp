@@ -263,6 +263,9 @@ struct Table {
     int graph_prec = -1;
     hipGraphExec_t graph_n = nullptr;  // graph_n_depth iterations in one graph
     int graph_n_prec = -1, graph_n_depth = 0;
+    ChainStats *stats_dev = nullptr;   // [stats_cap] the batch's records, gathered on the device
+    ChainStats *stats_host = nullptr;  // [stats_cap] pinned host copy of them
+    int stats_cap = 0;
 };
 
 std::mutex g_mu;
@@ -474,17 +477,35 @@ kcm_status ensure_table(kcm_chain *const *chains, int n_chains, hipStream_t stre
     return KCM_OK;
 }
 
-kcm_status read_stats(const kcm_chain *c, hipStream_t s, ChainStats *st)
-{
-    HIP_TRY(hipMemcpyAsync(st, c->h.stats, sizeof(ChainStats), hipMemcpyDeviceToHost, s));
-    return KCM_OK;
-}
-
 template <typename T>
 kcm_status write_field(T *dev_field, T value, hipStream_t s)
 {
     HIP_TRY(hipMemcpyAsync(dev_field, &value, sizeof(T), hipMemcpyHostToDevice, s));
     HIP_TRY(hipStreamSynchronize(s));
+    return KCM_OK;
+}
+
+// The records of every chain of the table's batch, read back with one gather
+// kernel and one copy.  Synchronises the stream.
+kcm_status gather_stats(Table *t, hipStream_t stream, std::vector<ChainStats> &out)
+{
+    const int n = t->batch.n_chains;
+    if (n > t->stats_cap) {
+        HIP_TRY(hipStreamSynchronize(stream));
+        if (t->stats_dev) HIP_TRY(hipFree(t->stats_dev));
+        if (t->stats_host) HIP_TRY(hipHostFree(t->stats_host));
+        t->stats_dev = nullptr;
+        t->stats_host = nullptr;
+        t->stats_cap = 0;
+        const int cap = std::max(2 * n, 64);
+        HIP_TRY(hipMalloc(&t->stats_dev, sizeof(ChainStats) * cap));
+        HIP_TRY(hipHostMalloc(&t->stats_host, sizeof(ChainStats) * cap, hipHostMallocDefault));
+        t->stats_cap = cap;
+    }
+    HIP_TRY(launch_stats_gather(t->batch, t->stats_dev, stream));
+    HIP_TRY(hipMemcpyAsync(t->stats_host, t->stats_dev, sizeof(ChainStats) * n, hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+    out.assign(t->stats_host, t->stats_host + n);
     return KCM_OK;
 }
 
@@ -725,14 +746,14 @@ kcm_status kcm_chain_info(const kcm_chain *c, int32_t *n_atoms, int32_t *n_joint
     return KCM_OK;
 }
 
-kcm_status kcm_step(kcm_chain *const *chains, int n_chains, int n_iter, void *hip_stream, kcm_step_report *reports)
+namespace {
+
+// kcm_step with g_mu held and the chains checked; st, if given, receives every
+// chain's record after the call
+kcm_status step_locked(kcm_chain *const *chains, int n_chains, int n_iter, int prec, hipStream_t stream,
+                       std::vector<ChainStats> *st)
 {
-    if (n_iter < 0) return fail(KCM_E_INVAL, "n_iter < 0");
-    int prec = 0;
-    kcm_status s = check_chains(chains, n_chains, &prec);
-    if (s != KCM_OK) return s;
-    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
-    std::lock_guard<std::mutex> lock(g_mu);
+    kcm_status s;
     Table *t = nullptr;
     s = ensure_table(chains, n_chains, stream, &t);
     if (s != KCM_OK) return s;
@@ -792,13 +813,23 @@ kcm_status kcm_step(kcm_chain *const *chains, int n_chains, int n_iter, void *hi
         g_timed.push_back(ti);
     }
     if (n_iter > 0) HIP_TRY(launch_final(bt, stream));
-    if (!reports) return KCM_OK;
-    std::vector<ChainStats> st(n_chains);
-    for (int i = 0; i < n_chains; ++i) {
-        s = read_stats(chains[i], stream, &st[i]);
-        if (s != KCM_OK) return s;
-    }
-    HIP_TRY(hipStreamSynchronize(stream));
+    if (st) return gather_stats(t, stream, *st);
+    return KCM_OK;
+}
+
+}  // namespace
+
+kcm_status kcm_step(kcm_chain *const *chains, int n_chains, int n_iter, void *hip_stream, kcm_step_report *reports)
+{
+    if (n_iter < 0) return fail(KCM_E_INVAL, "n_iter < 0");
+    int prec = 0;
+    kcm_status s = check_chains(chains, n_chains, &prec);
+    if (s != KCM_OK) return s;
+    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    std::lock_guard<std::mutex> lock(g_mu);
+    std::vector<ChainStats> st;
+    s = step_locked(chains, n_chains, n_iter, prec, stream, reports ? &st : nullptr);
+    if (s != KCM_OK || !reports) return s;
     kcm_status worst = KCM_OK;
     for (int i = 0; i < n_chains; ++i) {
         kcm_step_report &r = reports[i];
@@ -824,47 +855,33 @@ kcm_status kcm_fold(kcm_chain *const *chains, int n_chains, double tol_dtheta, i
     if (s != KCM_OK) return s;
     if (max_iter < 0 || check_every < 1) return fail(KCM_E_INVAL, "max_iter < 0 or check_every < 1");
     hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    std::lock_guard<std::mutex> lock(g_mu);
     const auto t0 = std::chrono::steady_clock::now();
-    std::vector<ChainStats> st(n_chains);
+    Table *t = nullptr;
+    if ((s = ensure_table(chains, n_chains, stream, &t)) != KCM_OK) return s;
+    std::vector<ChainStats> st;
+    if ((s = gather_stats(t, stream, st)) != KCM_OK) return s;
     std::vector<int64_t> start(n_chains);
-    for (int i = 0; i < n_chains; ++i) {
-        s = read_stats(chains[i], stream, &st[i]);
-        if (s != KCM_OK) return s;
-    }
-    HIP_TRY(hipStreamSynchronize(stream));
-    for (int i = 0; i < n_chains; ++i) {
-        ChainStats *d = chains[i]->h.stats;
-        start[i] = st[i].iterations;
-        const int act = st[i].status == 0 ? 1 : 0;
-        if ((s = write_field(&d->tol, tol_dtheta, stream)) != KCM_OK) return s;
-        if ((s = write_field(&d->iter_limit, st[i].iterations + (int64_t)max_iter, stream)) != KCM_OK) return s;
-        if ((s = write_field(&d->converged, 0, stream)) != KCM_OK) return s;
-        if ((s = write_field(&d->active, max_iter > 0 ? act : 0, stream)) != KCM_OK) return s;
-        if ((s = write_field(&d->run, max_iter > 0 ? act : 0, stream)) != KCM_OK) return s;
-    }
+    for (int i = 0; i < n_chains; ++i) start[i] = st[i].iterations;
+    HIP_TRY(launch_fold_control(t->batch, FOLD_BEGIN, tol_dtheta, (int64_t)max_iter, stream));
     int done = 0;
     while (done < max_iter) {
         const int k = std::min(check_every, max_iter - done);
-        s = kcm_step(chains, n_chains, k, hip_stream, nullptr);
-        if (s != KCM_OK) return s;
+        if ((s = step_locked(chains, n_chains, k, prec, stream, &st)) != KCM_OK) return s;
         done += k;
         bool any = false;
-        for (int i = 0; i < n_chains; ++i)
-            if ((s = read_stats(chains[i], stream, &st[i])) != KCM_OK) return s;
-        HIP_TRY(hipStreamSynchronize(stream));
         for (int i = 0; i < n_chains; ++i) any = any || st[i].active;
         if (!any) break;
     }
     const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (done == 0 && (s = gather_stats(t, stream, st)) != KCM_OK) return s;
+    // leave the chains steppable again by kcm_step (ensure_table: the same
+    // batch, so the table is still current)
+    if ((s = ensure_table(chains, n_chains, stream, &t)) != KCM_OK) return s;
+    HIP_TRY(launch_fold_control(t->batch, FOLD_END, 0.0, 0, stream));
+    HIP_TRY(hipStreamSynchronize(stream));
     kcm_status worst = KCM_OK;
     for (int i = 0; i < n_chains; ++i) {
-        // leave the chain steppable again by kcm_step
-        ChainStats *d = chains[i]->h.stats;
-        if ((s = write_field(&d->tol, 0.0, stream)) != KCM_OK) return s;
-        if ((s = write_field(&d->iter_limit, std::numeric_limits<int64_t>::max(), stream)) != KCM_OK) return s;
-        const int again = st[i].status == 0 && !st[i].converged ? 1 : 0;
-        if ((s = write_field(&d->active, again, stream)) != KCM_OK) return s;
-        if ((s = write_field(&d->run, again, stream)) != KCM_OK) return s;
         if (results) {
             results[i].iterations = st[i].iterations - start[i];
             results[i].converged = st[i].converged;

@@ -139,5 +139,8 @@ hipError_t launch_scatter(const Batch &b, hipStream_t s);
 hipError_t launch_force(const Batch &b, int precision, hipStream_t s);
 hipError_t launch_rank(const Batch &b, hipStream_t s);
 hipError_t launch_wrench(const Batch &b, hipStream_t s);
+constexpr int FOLD_BEGIN = 0, FOLD_END = 1;
+hipError_t launch_stats_gather(const Batch &b, ChainStats *out, hipStream_t s);
+hipError_t launch_fold_control(const Batch &b, int mode, double tol, int64_t max_iter, hipStream_t s);
 
 }  // namespace kcm

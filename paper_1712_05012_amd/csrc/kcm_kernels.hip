@@ -703,6 +703,40 @@ __global__ void k_finish(Batch bt)
     st->active = running(st);
 }
 
+// k_stats_gather: the records of every chain of the batch into one array, so
+// that the host reads them back with a single copy.
+__global__ void k_stats_gather(Batch bt, ChainStats *__restrict__ out)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= bt.n_chains) return;
+    out[c] = *bt.table[c]->stats;
+}
+
+// k_fold_control: FOLD_BEGIN arms every chain for a fold of at most max_iter
+// iterations that stops below tol (a chain with a failure status stays
+// stopped); FOLD_END leaves every chain steppable again unless it converged
+// or failed.
+__global__ void k_fold_control(Batch bt, int mode, double tol, int64_t max_iter)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= bt.n_chains) return;
+    ChainStats *st = bt.table[c]->stats;
+    if (mode == FOLD_BEGIN) {
+        const int go = st->status == 0 && max_iter > 0 ? 1 : 0;
+        st->tol = tol;
+        st->iter_limit = st->iterations + max_iter;
+        st->converged = 0;
+        st->active = go;
+        st->run = go;
+    } else {
+        const int again = st->status == 0 && !st->converged ? 1 : 0;
+        st->tol = 0.0;
+        st->iter_limit = INT64_MAX;
+        st->active = again;
+        st->run = again;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // cell list: exclusive scan of the counts, counting-sort scatter, stable
 // order inside each cell, gather into cell order
@@ -1675,6 +1709,20 @@ hipError_t launch_finish(const Batch &b, hipStream_t s)
 {
     if (b.n_chains <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_finish, dim3((b.n_chains + 255) / 256), dim3(256), 0, s, b);
+    return hipGetLastError();
+}
+
+hipError_t launch_stats_gather(const Batch &b, ChainStats *out, hipStream_t s)
+{
+    if (b.n_chains <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_stats_gather, dim3((b.n_chains + 255) / 256), dim3(256), 0, s, b, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_fold_control(const Batch &b, int mode, double tol, int64_t max_iter, hipStream_t s)
+{
+    if (b.n_chains <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fold_control, dim3((b.n_chains + 255) / 256), dim3(256), 0, s, b, mode, tol, max_iter);
     return hipGetLastError();
 }
 

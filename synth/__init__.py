@@ -12,9 +12,11 @@ from .chains import (  # noqa: F401
     N_TYPES,
     TYPE_TABLE_SEED,
     ResidueTypes,
+    alanine_like_types,
     batch_lengths,
     config_seed,
     load_globule,
+    polyala_starts,
     random_chi,
     random_dihedrals,
     residue_types,

@@ -14,6 +14,9 @@ Recipe (every array is drawn from its own ``numpy.random.Generator(PCG64)``):
 * Batches: lengths uniform in [50, 600] residues, one seed per chain.
 * Serving: Poisson arrivals (exponential gaps) and lognormal lengths
   (median 200, sigma 0.6) clipped to [30, 2000].
+* Polyalanine: one fixed Ala-like residue type with element-typical constants
+  (listed in ``alanine_like_types``); batches of 10-20 residue chains with
+  phi, psi uniform in [-90, 90] degrees.
 """
 from __future__ import annotations
 
@@ -104,6 +107,33 @@ def serving_jobs(n_jobs: int, seed: int, rate: float = 50.0, median: float = 200
     arrivals = np.cumsum(gaps) - gaps[0]
     lengths = np.clip(np.rint(np.exp(rng.normal(np.log(median), sigma, int(n_jobs)))), lo, hi)
     return arrivals, lengths.astype(np.int32)
+
+
+def alanine_like_types() -> ResidueTypes:
+    """One residue type shaped like alanine, for the polyalanine experiments.
+
+    Slots N, H, CA, HA, CB, HB1-3, C, O.  Charges give the backbone amide its
+    dipole (N -0.40, H +0.25, C +0.50, O -0.50 e) and the CH3 group a small
+    polarity; the residue is neutral.  Lennard-Jones sigma and well depth are
+    element-typical round values (C 3.4 A / 0.09, N 3.25 A / 0.17,
+    O 3.0 A / 0.21 kcal/mol, H on carbon 2.5 A, H on nitrogen 1.1 A,
+    both 0.02 kcal/mol).  Hydrophobicity +1.8 (alanine on the Kyte-Doolittle
+    scale).  These are not the force-field tables of any published model.
+    """
+    q = np.array([[-0.40, 0.25, 0.05, 0.05, -0.10, 0.05, 0.05, 0.05, 0.50, -0.50]])
+    sigma = np.array([[3.25, 1.10, 3.40, 2.50, 3.40, 2.50, 2.50, 2.50, 3.40, 3.00]])
+    eps = np.array([[0.17, 0.02, 0.09, 0.02, 0.09, 0.02, 0.02, 0.02, 0.09, 0.21]])
+    return ResidueTypes(q=q, sigma=sigma, eps=eps, hydro=np.array([1.8]))
+
+
+def polyala_starts(n_chains: int, seed: int, lo: int = 10, hi: int = 20, max_deg: float = 90.0):
+    """Residue counts uniform in [lo, hi] and, per chain, (phi_1, psi_1, ...)
+    uniform in [-max_deg, +max_deg] degrees (radians)."""
+    rng = _rng(seed)
+    lengths = rng.integers(lo, hi + 1, int(n_chains)).astype(np.int32)
+    lim = np.radians(max_deg)
+    thetas = [rng.uniform(-lim, lim, 2 * int(m)) for m in lengths]
+    return lengths, thetas
 
 
 def load_globule(m: int) -> np.ndarray:

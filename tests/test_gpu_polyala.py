@@ -1,0 +1,149 @@
+"""Polyalanine experiments (Sec. 5) through the batched path, against the
+FP64 oracle (needs an MI355X)."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle  # noqa: E402
+import synth  # noqa: E402
+from paper_1712_05012_amd import kcm, polyala  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+def _log(**kw):
+    print(" ".join(f"{k}={v}" for k, v in kw.items()), flush=True)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    kcm.load_library()
+
+
+def _wrap(x):
+    return np.abs(np.angle(np.exp(1j * x)))
+
+
+def _oracle_run(m, theta, terms, n_iter, tol=0.0):
+    """The oracle's KCM run with the experiments' step (capped, s = 1e-2 rad);
+    stops after the first step whose max |dtheta| is below tol."""
+    ref = oracle.OracleChain(np.zeros(m, np.int32), synth.alanine_like_types())
+    th = np.array(theta, dtype=np.float64)
+    energies = []
+    it = 0
+    while it < n_iter:
+        o = oracle.iterate(ref, th, terms=terms, kappa=1e-3, s=1e-2)
+        th = o["theta"]
+        it += 1
+        energies.append((o["E_elec"], o["E_vdw"], o["E_cav"]))
+        if tol > 0.0 and np.abs(o["dtheta"]).max() < tol:
+            break
+    r, _, _ = oracle.fk(ref, th)
+    return th, r, np.array(energies), it
+
+
+def test_helix_runs_track_the_oracle_fp64():
+    # vacuum: the descent contracts perturbations (a 1e-12 rad offset of the
+    # start stays below 1e-11 over 1500 oracle iterations), so the device run
+    # must follow the oracle to 1e-8 rad all the way.  Water: the solvation
+    # forces are piecewise constant, and a rounding-level offset flips a sample
+    # test after ~100-200 iterations, so the runs agree to 1e-8 rad for 100
+    # iterations and in the hand and mean helical angles at the end.
+    short = polyala.helix_runs(n_iter=100, trace_every=10)
+    for run in short:
+        terms = "elec+vdw+cav" if run["solvation"] else "elec+vdw"
+        th, _, E, _ = _oracle_run(15, np.full(30, np.radians(run["start_deg"])), terms, 100)
+        err = float(_wrap(run["theta"] - th).max())
+        # the trace holds the energies of the last evaluation of each chunk
+        idx = run["iterations"] - 1
+        e_err = float(np.abs(run["energies"] - E[idx]).max() / np.abs(E).max())
+        _log(case="helix100", start=run["start_deg"], water=run["solvation"], dtheta=err, energy=e_err)
+        assert run["status"] == 0
+        assert err <= 1e-8 and e_err <= 1e-9
+    full = polyala.helix_runs(n_iter=1500, trace_every=50)
+    for run in full:
+        terms = "elec+vdw+cav" if run["solvation"] else "elec+vdw"
+        th, r, _, _ = _oracle_run(15, np.full(30, np.radians(run["start_deg"])), terms, 1500)
+        err = float(_wrap(run["theta"] - th).max())
+        deg = (np.degrees(th) + 180.0) % 360.0 - 180.0
+        mo = (deg[2::2].mean(), deg[3::2].mean())
+        _log(case="helix1500", start=run["start_deg"], water=run["solvation"], dtheta=err,
+             hand=run["handedness"], mean=run["mean_phi_psi"], oracle_mean=mo)
+        assert run["status"] == 0
+        assert run["handedness"] == polyala.handedness(r) == ("left" if run["start_deg"] > 0 else "right")
+        if not run["solvation"]:
+            assert err <= 1e-8
+        assert abs(run["mean_phi_psi"][0] - mo[0]) < 5.0 and abs(run["mean_phi_psi"][1] - mo[1]) < 5.0
+    vac = {r["start_deg"]: r["energy"] for r in full if not r["solvation"]}
+    assert vac[-10.0] < vac[10.0]
+
+
+def test_helix_runs_mixed_precision():
+    # mixed precision: per-step errors up to 1e-5 rad, contracted by the vacuum
+    # descent; the bound allows 100 per-step tolerances
+    runs = polyala.helix_runs(n_iter=1500, trace_every=100, precision=kcm.KCM_MIXED)
+    for run in runs:
+        if run["solvation"]:
+            assert run["handedness"] == ("left" if run["start_deg"] > 0 else "right")
+            continue
+        th, _, _, _ = _oracle_run(15, np.full(30, np.radians(run["start_deg"])), "elec+vdw", 1500)
+        err = float(_wrap(run["theta"] - th).max())
+        _log(case="helix_mixed", start=run["start_deg"], dtheta=err)
+        assert err <= 1e-3
+
+
+def test_statistics_sample_follows_the_oracle():
+    # chains folded together in one batch (vacuum, FP64).  From random starts
+    # the hard cutoff and the switching argmax of the capped step make the
+    # descent amplify rounding-level offsets (a 1e-12 rad offset of the start
+    # grows to 1e-7..1e-4 rad within 400 oracle iterations, to at most 4e-12
+    # within 100).  So: 100 iterations against oracle runs to 1e-8 rad; 400
+    # iterations split into two batches equal to one batch bit for bit; and at
+    # the folded angles of those 400 iterations, one more step of each side
+    # from the same angles agrees to the per-step tolerance.
+    import synth as S
+    from gpu_common import DTHETA_TOL
+
+    n, seed, tol = 48, 5, 1e-4
+    lengths, thetas = S.polyala_starts(n, seed)
+    off = np.concatenate([[0], np.cumsum(lengths - 1)])
+    short = polyala.ramachandran_statistics(n_chains=n, seed=seed, max_iter=100, tol=tol, check_every=5)
+    assert np.all(short["status"] == 0)
+    for k in (0, 7, 23, 47):
+        m = int(lengths[k])
+        th, _, _, it = _oracle_run(m, thetas[k], "elec+vdw", 100, tol)
+        deg = (np.degrees(th) + 180.0) % 360.0 - 180.0
+        err = max(float(_wrap(np.radians(short["phi"][off[k]:off[k + 1]] - deg[2::2])).max()),
+                  float(_wrap(np.radians(short["psi"][off[k]:off[k + 1]] - deg[3::2])).max()))
+        _log(case="stat_chain100", k=k, m=m, iterations=int(short["iterations"][k]), oracle_iterations=it,
+             dtheta=err)
+        assert short["iterations"][k] == it
+        assert err <= 1e-8
+    a = polyala.ramachandran_statistics(n_chains=n, seed=seed, max_iter=400, tol=tol, check_every=5)
+    b = polyala.ramachandran_statistics(n_chains=n, seed=seed, max_iter=400, tol=tol, check_every=5, batch=24)
+    assert np.array_equal(a["phi"], b["phi"]) and np.array_equal(a["psi"], b["psi"])
+    assert np.array_equal(a["iterations"], b["iterations"])
+    assert np.all(a["status"] == 0)
+    assert sum(a["region_counts"].values()) == int((lengths - 1).sum())
+    T = S.alanine_like_types()
+    p = polyala.experiment_params(False)
+    for k in (0, 7, 23, 47):
+        m = int(lengths[k])
+        # all folded angles (the statistics keep residues 2..m only) from a
+        # one-chain rerun of the same 400 iterations, equal to the batch's
+        c = kcm.Chain(np.zeros(m, np.int32), T, p, theta0=thetas[k])
+        kcm.kcm_fold([c], tol, 400, 5)
+        th = c.state()["theta"]
+        assert np.array_equal((np.degrees(th[2::2]) + 180.0) % 360.0 - 180.0, a["phi"][off[k]:off[k + 1]])
+        c.set_theta(th)
+        c.step(1)
+        st = c.state()
+        ref = oracle.OracleChain(np.zeros(m, np.int32), T)
+        o = oracle.iterate(ref, th, terms="elec+vdw", kappa=1e-3, s=1e-2)
+        err = float(np.abs(st["dtheta"] - o["dtheta"]).max())
+        _log(case="stat_chain_step_at_400", k=k, m=m, dtheta=err)
+        assert err <= DTHETA_TOL[kcm.KCM_FP64]
+        c.free()
