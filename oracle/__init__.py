@@ -25,3 +25,4 @@ from .oracle import (  # noqa: F401
     threads,
     torques,
 )
+from .mc import mc_minimize  # noqa: F401,E402
