@@ -112,13 +112,24 @@ typedef struct {
     double seconds;      /* wall time of the call */
 } kcm_fold_result;
 
+/* Per chain result of kcm_mc_minimize. */
+typedef struct {
+    double e_start;      /* energy (the chain's terms) of its angles at the start of the call */
+    double e_accepted;   /* energy of the accepted state at the end */
+    double e_best;       /* lowest energy of any state evaluated in the call */
+    int64_t trials;      /* completed trials */
+    int64_t accepted;    /* accepted trials */
+    int32_t status;
+    int32_t pad;
+} kcm_mc_result;
+
 typedef struct kcm_chain kcm_chain;
 
 /* Fill *p with the defaults above. */
 void kcm_default_params(kcm_params *p);
 
 /* Bytes of caller-owned device memory a chain needs (256-byte aligned block).
- * Depends on n_res and params->n_orbits only. */
+ * Depends on n_res, desc->side_chains and params->n_orbits only. */
 kcm_status kcm_chain_bytes(const kcm_chain_desc *desc, const kcm_params *params, size_t *bytes);
 
 /* Build a chain (Fig. 5 steps 1-3): zero-position geometry from the residue
@@ -150,6 +161,34 @@ kcm_status kcm_step(kcm_chain *const *chains, int n_chains, int n_iter, void *hi
  * Synchronises hip_stream.  results[n_chains] may be NULL. */
 kcm_status kcm_fold(kcm_chain *const *chains, int n_chains, double tol_dtheta, int max_iter,
                     int check_every, void *hip_stream, kcm_fold_result *results);
+
+/* Monte Carlo minimization: the hybrid of Monte Carlo sampling and steepest
+ * descent listed among the search improvements of Sec. 4, in the form of Li
+ * and Scheraga (Monte Carlo minimization) with the Metropolis rule.  The
+ * start is each chain's current angles and their energy E (the chain's terms:
+ * Coulomb + LJ, plus solvation when enabled).  Trial k of chain c:
+ *   theta' = wrap(accepted + delta) on the free joints (mask 1),
+ *   then n_descent KCM iterations from theta' (the chain's step rule),
+ *   E' = energy of the reached angles (one more evaluation),
+ *   accepted when E' <= E or u < exp(-(E' - E)/kT) (kT = 0: downhill only).
+ * delta: DEVICE array, the chains' blocks [n_trials][J_c] one after the other
+ * in call order (radians); u: DEVICE array [n_chains][n_trials], uniform in
+ * [0, 1).  Both are read during the call only.  All trials of all chains run
+ * on the device with no host round trip.  Afterwards each chain holds its
+ * accepted angles (kcm_mc_best_theta gives the lowest); its positions and
+ * forces are those of the last evaluated trial, and its next kcm_step starts
+ * with a fresh grid.  A chain that fails numerically keeps the accepted
+ * angles of before the failure.  The call clears the chains' convergence
+ * tolerance and iteration limit (kcm_set_limits), so every descent runs its
+ * n_descent iterations.  results[n_chains] may be NULL.
+ * Synchronises hip_stream. */
+kcm_status kcm_mc_minimize(kcm_chain *const *chains, int32_t n_chains, int32_t n_trials, int32_t n_descent,
+                           double kT, const double *delta, const double *u, void *hip_stream,
+                           kcm_mc_result *results);
+
+/* The lowest-energy angles (host array [J]) of the chain's last
+ * kcm_mc_minimize call; synchronises hip_stream. */
+kcm_status kcm_mc_best_theta(const kcm_chain *chain, void *hip_stream, double *theta);
 
 /* Copy a chain's state to host arrays (any pointer may be NULL); synchronises
  * hip_stream.  theta[J] and dtheta[J] (last applied step); xyz[n][3] and

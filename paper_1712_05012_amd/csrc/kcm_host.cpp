@@ -151,7 +151,7 @@ std::vector<V3> sample_directions(int n_orb)
 // device block layout
 // ---------------------------------------------------------------------------
 struct Layout {
-    size_t desc, stats, grid, theta, dtheta, tau, mask, joint0, jcur, xform, xform_loc, blk_xf, tmax_part, bad_part;
+    size_t desc, stats, grid, theta, dtheta, tau, mc_theta, mask, joint0, jcur, xform, xform_loc, blk_xf, tmax_part, bad_part;
     size_t r0, r, aparam, g0, qfix;
     size_t cell_key, cell_count, cell_start, cell_local, scan_part, bbox_part, wrench_part, s_r, s_p, s_tmp, s_idx, s_cell;
     size_t f_pair, f_cav;
@@ -192,6 +192,7 @@ Layout make_layout(int m, int n_orb, int side_chains)
     l.theta = take(8 * Jt);
     l.dtheta = take(8 * Jt);
     l.tau = take(8 * Jt);
+    l.mc_theta = take(16 * Jt);
     l.mask = take(Jt);
     l.joint0 = take(64 * J);
     l.jcur = take(64 * J);
@@ -266,6 +267,8 @@ struct Table {
     ChainStats *stats_dev = nullptr;   // [stats_cap] the batch's records, gathered on the device
     ChainStats *stats_host = nullptr;  // [stats_cap] pinned host copy of them
     int stats_cap = 0;
+    int64_t *mc_off_dev = nullptr;     // [mc_off_cap] per-chain offsets into a Monte Carlo call's perturbations
+    int mc_off_cap = 0;
 };
 
 std::mutex g_mu;
@@ -676,6 +679,7 @@ kcm_status kcm_build_chain(const kcm_chain_desc *desc, const kcm_params *params,
     PTR(theta, double *);
     PTR(dtheta, double *);
     PTR(tau, double *);
+    PTR(mc_theta, double *);
     PTR(mask, uint8_t *);
     PTR(joint0, double4 *);
     PTR(jcur, double4 *);
@@ -748,15 +752,12 @@ kcm_status kcm_chain_info(const kcm_chain *c, int32_t *n_atoms, int32_t *n_joint
 
 namespace {
 
-// kcm_step with g_mu held and the chains checked; st, if given, receives every
-// chain's record after the call
-kcm_status step_locked(kcm_chain *const *chains, int n_chains, int n_iter, int prec, hipStream_t stream,
-                       std::vector<ChainStats> *st)
+// n_iter iterations of the table's batch (HIP graphs where captured); boot
+// sequence first when a chain needs one or boot_all is set; the post phase of
+// the last forces only when final is set
+kcm_status iterate_locked(Table *t, kcm_chain *const *chains, int n_chains, int n_iter, int prec, hipStream_t stream,
+                          bool boot_all, bool final)
 {
-    kcm_status s;
-    Table *t = nullptr;
-    s = ensure_table(chains, n_chains, stream, &t);
-    if (s != KCM_OK) return s;
     const Batch &bt = t->batch;
     const int depth = g_graphs;
     if (depth > 0 && n_iter > 0 && (!t->graph || t->graph_prec != prec)) {
@@ -779,7 +780,7 @@ kcm_status step_locked(kcm_chain *const *chains, int n_chains, int n_iter, int p
         t->graph_n_depth = depth;
     }
     if (n_iter > 0) {
-        bool boot = false;
+        bool boot = boot_all;
         for (int i = 0; i < n_chains; ++i) boot = boot || chains[i]->boot;
         if (boot) {
             HIP_TRY(launch_boot(bt, stream));
@@ -812,7 +813,20 @@ kcm_status step_locked(kcm_chain *const *chains, int n_chains, int n_iter, int p
         HIP_TRY(launch_iteration(bt, prec, stream, &ti));
         g_timed.push_back(ti);
     }
-    if (n_iter > 0) HIP_TRY(launch_final(bt, stream));
+    if (n_iter > 0 && final) HIP_TRY(launch_final(bt, stream));
+    return KCM_OK;
+}
+
+// kcm_step with g_mu held and the chains checked; st, if given, receives every
+// chain's record after the call
+kcm_status step_locked(kcm_chain *const *chains, int n_chains, int n_iter, int prec, hipStream_t stream,
+                       std::vector<ChainStats> *st)
+{
+    kcm_status s;
+    Table *t = nullptr;
+    s = ensure_table(chains, n_chains, stream, &t);
+    if (s != KCM_OK) return s;
+    if ((s = iterate_locked(t, chains, n_chains, n_iter, prec, stream, false, true)) != KCM_OK) return s;
     if (st) return gather_stats(t, stream, *st);
     return KCM_OK;
 }
@@ -891,6 +905,80 @@ kcm_status kcm_fold(kcm_chain *const *chains, int n_chains, double tol_dtheta, i
         if (st[i].status != 0 && worst == KCM_OK) worst = (kcm_status)st[i].status;
     }
     return worst;
+}
+
+kcm_status kcm_mc_minimize(kcm_chain *const *chains, int32_t n_chains, int32_t n_trials, int32_t n_descent, double kT,
+                           const double *delta, const double *u, void *hip_stream, kcm_mc_result *results)
+{
+    int prec = 0;
+    kcm_status s = check_chains(chains, n_chains, &prec);
+    if (s != KCM_OK) return s;
+    if (n_trials < 0 || n_descent < 0) return fail(KCM_E_INVAL, "n_trials < 0 or n_descent < 0");
+    if (!(kT >= 0.0)) return fail(KCM_E_INVAL, "kT must be >= 0");
+    if (n_trials > 0 && (!delta || !u)) return fail(KCM_E_INVAL, "null delta or u");
+    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    std::lock_guard<std::mutex> lock(g_mu);
+    Table *t = nullptr;
+    if ((s = ensure_table(chains, n_chains, stream, &t)) != KCM_OK) return s;
+    // per-chain offsets of the perturbations: chain c's [n_trials][J_c] block
+    if (n_chains + 1 > t->mc_off_cap) {
+        HIP_TRY(hipStreamSynchronize(stream));
+        if (t->mc_off_dev) HIP_TRY(hipFree(t->mc_off_dev));
+        t->mc_off_dev = nullptr;
+        t->mc_off_cap = 0;
+        const int cap = std::max(2 * (n_chains + 1), 64);
+        HIP_TRY(hipMalloc(&t->mc_off_dev, sizeof(int64_t) * cap));
+        t->mc_off_cap = cap;
+    }
+    std::vector<int64_t> off(n_chains + 1, 0);
+    for (int i = 0; i < n_chains; ++i) off[i + 1] = off[i] + (int64_t)n_trials * chains[i]->J;
+    HIP_TRY(hipMemcpyAsync(t->mc_off_dev, off.data(), sizeof(int64_t) * (n_chains + 1), hipMemcpyHostToDevice,
+                           stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+    const Batch &bt = t->batch;
+    // the energy of the current angles: one evaluation, taken as the start
+    HIP_TRY(launch_mc_propose(bt, MC_RESET, nullptr, nullptr, 0, stream));
+    if ((s = iterate_locked(t, chains, n_chains, 1, prec, stream, true, false)) != KCM_OK) return s;
+    HIP_TRY(launch_tau(bt, stream));
+    HIP_TRY(launch_mc_decide(bt, MC_INIT, u, n_trials, 0, kT, stream));
+    HIP_TRY(launch_mc_apply(bt, stream));
+    for (int k = 0; k < n_trials; ++k) {
+        // perturb, n_descent steps, and the evaluation of the reached angles
+        HIP_TRY(launch_mc_propose(bt, MC_PROPOSE, delta, t->mc_off_dev, k, stream));
+        if ((s = iterate_locked(t, chains, n_chains, n_descent + 1, prec, stream, true, false)) != KCM_OK) return s;
+        HIP_TRY(launch_tau(bt, stream));
+        HIP_TRY(launch_mc_decide(bt, MC_TRIAL, u, n_trials, k, kT, stream));
+        HIP_TRY(launch_mc_apply(bt, stream));
+    }
+    std::vector<ChainStats> st;
+    if ((s = gather_stats(t, stream, st)) != KCM_OK) return s;
+    kcm_status worst = KCM_OK;
+    for (int i = 0; i < n_chains; ++i) {
+        // the angles are the accepted ones; positions and grid come anew
+        chains[i]->boot = true;
+        if (results) {
+            kcm_mc_result &r = results[i];
+            r.e_start = st[i].mc_e_start;
+            r.e_accepted = st[i].mc_e_acc;
+            r.e_best = st[i].mc_e_best;
+            r.trials = st[i].mc_trials;
+            r.accepted = st[i].mc_accepted;
+            r.status = st[i].status;
+            r.pad = 0;
+        }
+        if (st[i].status != 0 && worst == KCM_OK) worst = (kcm_status)st[i].status;
+    }
+    if (worst != KCM_OK) g_err = "a chain reported a failure status";
+    return worst;
+}
+
+kcm_status kcm_mc_best_theta(const kcm_chain *c, void *hip_stream, double *theta)
+{
+    if (!c || !theta) return fail(KCM_E_INVAL, "null chain or theta");
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    HIP_TRY(hipMemcpyAsync(theta, c->h.mc_theta + c->J, 8 * (size_t)c->J, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return KCM_OK;
 }
 
 kcm_status kcm_get_state(const kcm_chain *c, void *hip_stream, double *theta, double *xyz, double *force, double *tau,

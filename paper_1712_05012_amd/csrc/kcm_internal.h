@@ -35,6 +35,11 @@ struct ChainStats {
     int32_t run;                   // 0: the kernels after the step skip this chain in this iteration
     int32_t grid_bad;              // this iteration's grid could not be sized: the chain stops
     int32_t pad;
+    // Monte Carlo minimization: energies of the starting, accepted and lowest
+    // states, completed and accepted trials, this trial's decisions
+    double mc_e_start, mc_e_acc, mc_e_best;
+    int64_t mc_trials, mc_accepted;
+    int32_t mc_acc, mc_best;
 };
 // active is read by the torque and step kernels and written only at the end of
 // an iteration (or call); run (set by the step) and grid_bad (set by the grid
@@ -67,6 +72,7 @@ struct ChainDev {
     uint32_t pad_masks[2];
 
     double *theta, *dtheta, *tau;
+    double *mc_theta;    // [2][J]: accepted, then lowest angles of Monte Carlo minimization
     uint8_t *mask;
     double4 *joint0;     // [J][2]: (u0, 0), (p0, 0) zero-position axis and point
     double4 *jcur;       // [J][2]: current (u, 0), (p, 0)
@@ -140,6 +146,13 @@ hipError_t launch_force(const Batch &b, int precision, hipStream_t s);
 hipError_t launch_rank(const Batch &b, hipStream_t s);
 hipError_t launch_wrench(const Batch &b, hipStream_t s);
 constexpr int FOLD_BEGIN = 0, FOLD_END = 1;
+constexpr int MC_RESET = 0, MC_PROPOSE = 1;  // k_mc_propose: flags only, or flags and new angles
+constexpr int MC_INIT = 0, MC_TRIAL = 1;     // k_mc_decide: take the state, or the Metropolis test
+hipError_t launch_mc_propose(const Batch &b, int mode, const double *delta, const int64_t *delta_off, int trial,
+                             hipStream_t s);
+hipError_t launch_mc_decide(const Batch &b, int mode, const double *u, int n_trials, int trial, double kT,
+                            hipStream_t s);
+hipError_t launch_mc_apply(const Batch &b, hipStream_t s);
 hipError_t launch_stats_gather(const Batch &b, ChainStats *out, hipStream_t s);
 hipError_t launch_fold_control(const Batch &b, int mode, double tol, int64_t max_iter, hipStream_t s);
 

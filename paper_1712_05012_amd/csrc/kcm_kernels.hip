@@ -738,6 +738,119 @@ __global__ void k_fold_control(Batch bt, int mode, double tol, int64_t max_iter)
 }
 
 // ---------------------------------------------------------------------------
+// Monte Carlo minimization over the descent (the hybrid of Monte Carlo
+// sampling and steepest descent among the search improvements of Sec. 4, in
+// the form of Li and Scheraga): perturb the accepted angles, descend, keep the
+// descended state by the Metropolis rule on its energy.  Three small kernels
+// around the ordinary iterations; the random numbers are inputs.
+// ---------------------------------------------------------------------------
+// joint j of workgroup jb of a chain's joint blocks (backbone blocks, then
+// side-chain blocks); false past the end
+__device__ __forceinline__ bool joint_of_block(const ChainDev *cd, int jb, int tid, int *j)
+{
+    if (jb >= cd->n_bb_blocks) {
+        const int jc = (jb - cd->n_bb_blocks) * JOINT_BLOCK + tid;
+        *j = cd->n_joints + jc;
+        return jc < cd->n_chi;
+    }
+    *j = jb * JOINT_BLOCK + tid;
+    return *j < cd->n_joints;
+}
+
+// angle into (-pi, pi]; an angle already inside comes back unchanged
+__device__ __forceinline__ double wrap_angle(double t)
+{
+    t -= 2.0 * PI_D * floor((t + PI_D) / (2.0 * PI_D));
+    return t <= -PI_D ? t + 2.0 * PI_D : t;
+}
+
+// MC_RESET: the chain re-boots from its current angles (positions, grid),
+// with no convergence test or iteration limit, so that every descent runs its
+// full length.  MC_PROPOSE: angles = wrap(accepted + delta of this trial) on
+// the free joints, then the same re-boot.  A chain with a failure status is
+// left alone.
+__global__ __launch_bounds__(JOINT_BLOCK) void k_mc_propose(Batch bt, int mode, const double *__restrict__ delta,
+                                                             const int64_t *__restrict__ delta_off, int trial)
+{
+    const int c = find_block_owner(bt.jblk_off, bt.n_chains, blockIdx.x);
+    ChainDev *cd = bt.table[c];
+    ChainStats *st = cd->stats;
+    if (st->status != 0) return;
+    const int jb = blockIdx.x - bt.jblk_off[c];
+    if (jb == 0 && threadIdx.x == 0) {
+        st->need_grid = 1;
+        st->pending_post = 0;
+        st->post_bad = 0;
+        st->converged = 0;
+        st->tol = 0.0;
+        st->iter_limit = INT64_MAX;
+        st->run = 1;
+        st->active = 1;
+    }
+    int j;
+    if (mode != MC_PROPOSE || !joint_of_block(cd, jb, threadIdx.x, &j)) return;
+    const int Jt = cd->n_joints + cd->n_chi;
+    const double a = cd->mc_theta[j];
+    cd->theta[j] = cd->mask[j] ? wrap_angle(a + delta[delta_off[c] + (int64_t)trial * Jt + j]) : a;
+}
+
+// One thread per chain, after the torque kernel has reduced the energies of
+// the last evaluation.  MC_INIT takes the state as the accepted and lowest
+// one; MC_TRIAL accepts it when E <= E_acc or u < exp(-(E - E_acc)/kT).  The
+// pending step of the last evaluation is discarded either way.
+__global__ void k_mc_decide(Batch bt, int mode, const double *__restrict__ u, int n_trials, int trial, double kT)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= bt.n_chains) return;
+    const ChainDev *cd = bt.table[c];
+    ChainStats *st = cd->stats;
+    // the energy of the chain's terms (bits 1 Coulomb, 2 Lennard-Jones, 4 solvation)
+    double e = 0.0;
+    if (cd->terms & 1) e += st->e_elec;
+    if (cd->terms & 2) e += st->e_vdw;
+    if (cd->terms & 4) e += st->e_cav;
+    if (st->status == 0 && (st->post_bad || !isfinite(e))) st->status = -4;
+    const int ok = st->status == 0;
+    int acc = 0, best = 0;
+    if (mode == MC_INIT) {
+        // taken even after a failure, so that the accepted angles are defined
+        acc = best = 1;
+        st->mc_e_start = st->mc_e_acc = st->mc_e_best = e;
+        st->mc_trials = st->mc_accepted = 0;
+    } else if (ok) {
+        const double de = e - st->mc_e_acc;
+        acc = de <= 0.0 || (kT > 0.0 && u[(int64_t)c * n_trials + trial] < exp(-de / kT));
+        best = e < st->mc_e_best;
+        if (acc) st->mc_e_acc = e;
+        if (best) st->mc_e_best = e;
+        st->mc_trials += 1;
+        st->mc_accepted += acc;
+    }
+    st->mc_acc = acc;
+    st->mc_best = best;
+    st->pending_post = 0;
+    st->need_grid = 1;
+    st->active = ok;
+    st->run = ok;
+}
+
+// Joint blocks: the lowest and accepted angles take the trial's angles as
+// decided; a rejected trial returns the chain to the accepted angles.
+__global__ __launch_bounds__(JOINT_BLOCK) void k_mc_apply(Batch bt)
+{
+    const int c = find_block_owner(bt.jblk_off, bt.n_chains, blockIdx.x);
+    ChainDev *cd = bt.table[c];
+    const ChainStats *st = cd->stats;
+    int j;
+    if (!joint_of_block(cd, blockIdx.x - bt.jblk_off[c], threadIdx.x, &j)) return;
+    const int Jt = cd->n_joints + cd->n_chi;
+    const double p = cd->theta[j];
+    if (st->mc_best) cd->mc_theta[Jt + j] = p;
+    if (st->mc_acc) cd->mc_theta[j] = p;
+    else cd->theta[j] = cd->mc_theta[j];
+}
+
+// ---------------------------------------------------------------------------
 // cell list: exclusive scan of the counts, counting-sort scatter, stable
 // order inside each cell, gather into cell order
 // ---------------------------------------------------------------------------
@@ -1723,6 +1836,31 @@ hipError_t launch_fold_control(const Batch &b, int mode, double tol, int64_t max
 {
     if (b.n_chains <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_fold_control, dim3((b.n_chains + 255) / 256), dim3(256), 0, s, b, mode, tol, max_iter);
+    return hipGetLastError();
+}
+
+hipError_t launch_mc_propose(const Batch &b, int mode, const double *delta, const int64_t *delta_off, int trial,
+                             hipStream_t s)
+{
+    if (b.total_jblocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_mc_propose, dim3(b.total_jblocks), dim3(JOINT_BLOCK), 0, s, b, mode, delta, delta_off,
+                       trial);
+    return hipGetLastError();
+}
+
+hipError_t launch_mc_decide(const Batch &b, int mode, const double *u, int n_trials, int trial, double kT,
+                            hipStream_t s)
+{
+    if (b.n_chains <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_mc_decide, dim3((b.n_chains + 255) / 256), dim3(256), 0, s, b, mode, u, n_trials, trial,
+                       kT);
+    return hipGetLastError();
+}
+
+hipError_t launch_mc_apply(const Batch &b, hipStream_t s)
+{
+    if (b.total_jblocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_mc_apply, dim3(b.total_jblocks), dim3(JOINT_BLOCK), 0, s, b);
     return hipGetLastError();
 }
 

@@ -24,7 +24,7 @@ KCM_TERM_ELEC, KCM_TERM_VDW, KCM_TERM_CAV, KCM_TERM_ALL = 1, 2, 4, 7
 EXPORTED = ("kcm_default_params", "kcm_chain_bytes", "kcm_build_chain", "kcm_step", "kcm_fold",
             "kcm_get_state", "kcm_get_forces", "kcm_set_theta", "kcm_get_cells", "kcm_chain_info",
             "kcm_set_timing", "kcm_get_timing", "kcm_chain_free", "kcm_last_error", "kcm_get_atom_terms",
-            "kcm_set_limits", "kcm_set_graphs")
+            "kcm_set_limits", "kcm_set_graphs", "kcm_mc_minimize", "kcm_mc_best_theta")
 
 
 class KcmError(RuntimeError):
@@ -64,6 +64,11 @@ class kcm_fold_result(C.Structure):
                 ("seconds", C.c_double)]
 
 
+class kcm_mc_result(C.Structure):
+    _fields_ = [("e_start", C.c_double), ("e_accepted", C.c_double), ("e_best", C.c_double),
+                ("trials", C.c_int64), ("accepted", C.c_int64), ("status", C.c_int32), ("pad", C.c_int32)]
+
+
 def load_library(path: str = LIB_PATH):
     """Load libkcm.so; raises if it has not been built (there is no fallback)."""
     global _lib
@@ -92,6 +97,9 @@ def load_library(path: str = LIB_PATH):
     lib.kcm_set_timing.argtypes = [C.c_int]
     lib.kcm_get_timing.argtypes = [vp, vp, vp, vp, C.c_int]
     lib.kcm_chain_free.argtypes = [vp]
+    lib.kcm_mc_minimize.argtypes = [C.POINTER(vp), C.c_int32, C.c_int32, C.c_int32, C.c_double, vp, vp, vp,
+                                    C.POINTER(kcm_mc_result)]
+    lib.kcm_mc_best_theta.argtypes = [vp, vp, vp]
     lib.kcm_last_error.argtypes = []
     lib.kcm_last_error.restype = C.c_char_p
     for name in EXPORTED:
@@ -215,6 +223,47 @@ def kcm_fold(chains, tol: float, max_iter: int, check_every: int = 10, stream=No
     return st, list(res)
 
 
+def kcm_mc_minimize(chains, delta, u, n_descent: int, kT: float, stream=None, check: bool = True):
+    """Monte Carlo minimization of every chain on the device.
+
+    delta: one host array [n_trials, J_c] per chain (radians); u: host array
+    [n_chains, n_trials] uniform in [0, 1).  Both are copied to the device
+    here.  Returns (status, [kcm_mc_result])."""
+    import torch
+
+    n = len(chains)
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    if u.ndim != 2 or u.shape[0] != n:
+        raise ValueError("u must have shape [n_chains, n_trials]")
+    n_trials = u.shape[1]
+    if len(delta) != n:
+        raise ValueError("one delta array per chain")
+    parts = []
+    for c, d in zip(chains, delta):
+        d = np.ascontiguousarray(d, dtype=np.float64)
+        J = kcm_chain_info(c.handle if isinstance(c, Chain) else c)[1]
+        if d.shape != (n_trials, J):
+            raise ValueError(f"delta of a chain must have shape [{n_trials}, {J}]")
+        parts.append(d.reshape(-1))
+    dev = torch.device("cuda")
+    d_dev = torch.from_numpy(np.concatenate(parts) if parts else np.zeros(0)).to(dev)
+    u_dev = torch.from_numpy(u.reshape(-1)).to(dev)
+    res = (kcm_mc_result * n)()
+    st = load_library().kcm_mc_minimize(_handles(chains), n, n_trials, int(n_descent), float(kT),
+                                        C.c_void_p(d_dev.data_ptr()), C.c_void_p(u_dev.data_ptr()),
+                                        _stream_handle(stream), res)
+    if check:
+        _check(st)
+    return st, list(res)
+
+
+def kcm_mc_best_theta(handle, stream=None):
+    _, J, _, _ = kcm_chain_info(handle)
+    th = np.zeros(J)
+    _check(load_library().kcm_mc_best_theta(handle, _stream_handle(stream), _p(th)))
+    return th
+
+
 def kcm_chain_info(handle):
     v = [C.c_int32() for _ in range(4)]
     _check(load_library().kcm_chain_info(handle, *[C.byref(x) for x in v]))
@@ -328,6 +377,9 @@ class Chain:
 
     def set_theta(self, theta, stream=None):
         kcm_set_theta(self.handle, theta, stream)
+
+    def mc_best_theta(self, stream=None):
+        return kcm_mc_best_theta(self.handle, stream)
 
     def cells(self, stream=None):
         return kcm_get_cells(self.handle, stream)

@@ -192,3 +192,53 @@ def ramachandran_statistics(n_chains: int = 2000, seed: int = 1712, lo: int = 10
         "iterations": np.array(iters), "converged": np.array(conv), "status": np.array(status),
         "lengths": lengths, "atom_steps": atom_steps, "fold_seconds": fold_s,
     }
+
+
+def mc_versus_descent(n_chains: int = 2000, seed: int = 1712, lo: int = 10, hi: int = 20, n_trials: int = 20,
+                      n_descent: int = 50, kT: float = 1.0, n_moved: int = 2, max_rad: float = 0.5,
+                      solvation: bool = False, precision=None, max_step: float = 1e-2, stream=None):
+    """Monte Carlo minimization (``kcm_mc_minimize``) against plain KCM descent
+    with the same number of force evaluations, on the statistics' chains.
+
+    Both start from the same random conformations.  The descent runs
+    1 + n_trials (n_descent + 1) iterations; the search makes n_trials trials
+    of n_moved joints perturbed by up to max_rad, each descended n_descent
+    iterations.  Returns per-chain final descent energies, lowest search
+    energies, acceptance counts and the two calls' seconds."""
+    import time
+
+    import synth
+
+    from . import kcm
+
+    T = synth.alanine_like_types()
+    lengths, thetas = synth.polyala_starts(n_chains, seed, lo, hi)
+    p = experiment_params(solvation, precision, max_step)
+    evals = 1 + n_trials * (n_descent + 1)
+    out = {"n_chains": n_chains, "evaluations": evals, "n_trials": n_trials, "n_descent": n_descent, "kT": kT}
+    chains = [kcm.Chain(np.zeros(m, np.int32), T, p, theta0=th, stream=stream) for m, th in zip(lengths, thetas)]
+    try:
+        kcm.kcm_step(chains, 1, stream)  # first launches and graph capture outside the timing
+        for c, th in zip(chains, thetas):
+            c.set_theta(th, stream)
+        t0 = time.perf_counter()
+        _, reps = kcm.kcm_step(chains, evals, stream, report=True, check=False)
+        out["descent_seconds"] = time.perf_counter() - t0
+        e_desc = np.array([r.e_elec + r.e_vdw + (r.e_cav if solvation else 0.0) for r in reps])
+        for c, th in zip(chains, thetas):
+            c.set_theta(th, stream)
+        moves = [synth.mc_moves(n_trials, 2 * int(m), seed * 7919 + k, n_moved, max_rad)
+                 for k, m in enumerate(lengths)]
+        t0 = time.perf_counter()
+        _, res = kcm.kcm_mc_minimize(chains, [mv[0] for mv in moves], np.stack([mv[1] for mv in moves]),
+                                     n_descent, kT, stream, check=False)
+        out["search_seconds"] = time.perf_counter() - t0
+    finally:
+        for c in chains:
+            c.free()
+    out["atoms"] = int(10 * lengths.sum())
+    out["e_descent"] = e_desc
+    out["e_search_best"] = np.array([r.e_best for r in res])
+    out["accepted"] = np.array([r.accepted for r in res])
+    out["status"] = np.array([r.status for r in res])
+    return out

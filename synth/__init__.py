@@ -16,6 +16,7 @@ from .chains import (  # noqa: F401
     batch_lengths,
     config_seed,
     load_globule,
+    mc_moves,
     polyala_starts,
     random_chi,
     random_dihedrals,

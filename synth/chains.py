@@ -17,6 +17,8 @@ Recipe (every array is drawn from its own ``numpy.random.Generator(PCG64)``):
 * Polyalanine: one fixed Ala-like residue type with element-typical constants
   (listed in ``alanine_like_types``); batches of 10-20 residue chains with
   phi, psi uniform in [-90, 90] degrees.
+* Monte Carlo moves: per trial a few random joints with uniform offsets, and
+  one uniform number for the Metropolis test.
 """
 from __future__ import annotations
 
@@ -134,6 +136,21 @@ def polyala_starts(n_chains: int, seed: int, lo: int = 10, hi: int = 20, max_deg
     lim = np.radians(max_deg)
     thetas = [rng.uniform(-lim, lim, 2 * int(m)) for m in lengths]
     return lengths, thetas
+
+
+def mc_moves(n_trials: int, n_joints: int, seed: int, n_moved: int = 2, max_rad: float = 0.5):
+    """Monte Carlo perturbations [n_trials, n_joints]: per trial, n_moved
+    distinct joints drawn uniformly get an offset uniform in [-max_rad,
+    max_rad]; the others stay 0.  Also the trials' Metropolis uniforms
+    [n_trials] in [0, 1).  Returns (delta, u)."""
+    rng = _rng(seed)
+    d = np.zeros((int(n_trials), int(n_joints)))
+    k = min(int(n_moved), int(n_joints))
+    for t in range(int(n_trials)):
+        js = rng.choice(int(n_joints), size=k, replace=False)
+        d[t, js] = rng.uniform(-max_rad, max_rad, k)
+    u = rng.uniform(0.0, 1.0, int(n_trials))
+    return d, u
 
 
 def load_globule(m: int) -> np.ndarray:

@@ -1,0 +1,135 @@
+"""Monte Carlo minimization on the device (kcm_mc_minimize) against the
+oracle's mc_minimize (needs an MI355X)."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle  # noqa: E402
+import synth  # noqa: E402
+from gpu_common import DTHETA_TOL  # noqa: E402
+from paper_1712_05012_amd import kcm, polyala  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+T = synth.alanine_like_types()
+N_TRIALS, N_DESCENT, KT = 8, 10, 2.0
+
+
+def _log(**kw):
+    print(" ".join(f"{k}={v}" for k, v in kw.items()), flush=True)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    kcm.load_library()
+
+
+def _wrap(x):
+    return np.abs(np.angle(np.exp(1j * x)))
+
+
+def _cases():
+    # polyalanine chains of 8-14 residues from random starts, with and without
+    # side-chain joints; perturbations of two joints per trial
+    lengths, thetas = synth.polyala_starts(4, 77, lo=8, hi=14)
+    out = []
+    for k in range(4):
+        m = int(lengths[k])
+        for sc in (False, True):
+            th = np.concatenate([thetas[k], synth.random_chi(m, 5 + k)]) if sc else thetas[k]
+            d, u = synth.mc_moves(N_TRIALS, th.size, 100 + k)
+            out.append((m, sc, th, d, u))
+    return out
+
+
+def _build(cases, precision=kcm.KCM_FP64):
+    p = polyala.experiment_params(False, precision)
+    return [kcm.Chain(np.zeros(m, np.int32), T, p, theta0=th, side_chains=sc) for m, sc, th, _, _ in cases]
+
+
+def test_mc_matches_oracle_fp64():
+    cases = _cases()
+    chains = _build(cases)
+    _, res = kcm.kcm_mc_minimize(chains, [c[3] for c in cases], np.stack([c[4] for c in cases]), N_DESCENT, KT)
+    for (m, sc, th, d, u), c, r in zip(cases, chains, res):
+        ref = oracle.OracleChain(np.zeros(m, np.int32), T)
+        o = oracle.mc_minimize(ref, th, d, u, N_DESCENT, KT, terms="elec+vdw", s=1e-2)
+        assert o["margins"].min() > 1e-6, "a Metropolis decision sits on its threshold; pick another seed"
+        got = c.state()["theta"]
+        best = c.mc_best_theta()
+        e = [abs(r.e_start - o["E_start"]), abs(r.e_accepted - o["E"]), abs(r.e_best - o["E_best"])]
+        scale = max(abs(o["E_start"]), 1.0)
+        _log(case="mc", m=m, side_chains=sc, accepted=r.accepted, oracle_accepted=o["accepted"],
+             dtheta=float(_wrap(got - o["theta"]).max()), dbest=float(_wrap(best - o["theta_best"]).max()),
+             de=max(e) / scale)
+        assert r.status == 0 and r.trials == N_TRIALS
+        assert r.accepted == o["accepted"]
+        assert max(e) <= 1e-9 * scale
+        assert _wrap(got - o["theta"]).max() <= 1e-8
+        assert _wrap(best - o["theta_best"]).max() <= 1e-8
+        assert r.e_best <= r.e_accepted and r.e_best <= r.e_start
+    for c in chains:
+        c.free()
+
+
+def test_mc_batch_equals_separate_calls_and_continues_with_steps():
+    cases = _cases()[:4]
+    a = _build(cases)
+    b = _build(cases)
+    _, ra = kcm.kcm_mc_minimize(a, [c[3] for c in cases], np.stack([c[4] for c in cases]), N_DESCENT, KT)
+    rb = [kcm.kcm_mc_minimize([ch], [c[3]], c[4][None], N_DESCENT, KT)[1][0] for ch, c in zip(b, cases)]
+    for ca, cb, x, y in zip(a, b, ra, rb):
+        assert np.array_equal(ca.state()["theta"], cb.state()["theta"])
+        assert (x.e_start, x.e_accepted, x.e_best, x.accepted) == (y.e_start, y.e_accepted, y.e_best, y.accepted)
+    # after the call a chain steps on from its accepted angles like a fresh one
+    p = polyala.experiment_params(False)
+    for (m, sc, th, d, u), ca in zip(cases, a):
+        th_acc = ca.state()["theta"]
+        rep = ca.step(1)
+        assert rep.status == 0
+        o = oracle.iterate(oracle.OracleChain(np.zeros(m, np.int32), T), th_acc, terms="elec+vdw",
+                           kappa=p.kappa, s=p.max_step)
+        err = float(np.abs(ca.state()["dtheta"] - o["dtheta"]).max())
+        _log(case="mc_then_step", m=m, side_chains=sc, dtheta=err)
+        assert err <= DTHETA_TOL[kcm.KCM_FP64]
+    for c in a + b:
+        c.free()
+
+
+def test_mc_zero_temperature_and_no_trials():
+    cases = _cases()[:3]
+    chains = _build(cases)
+    _, res = kcm.kcm_mc_minimize(chains, [c[3] for c in cases], np.stack([c[4] for c in cases]), N_DESCENT, 0.0)
+    for r in res:
+        assert r.status == 0 and r.e_accepted == r.e_best and r.e_best <= r.e_start
+    th = [c.state()["theta"] for c in chains]
+    _, res0 = kcm.kcm_mc_minimize(chains, [np.zeros((0, c[2].size)) for c in cases], np.zeros((3, 0)),
+                                  N_DESCENT, 1.0)
+    for c, t, r, r1 in zip(chains, th, res0, res):
+        # no trials: the start is the accepted state, its energy evaluated anew
+        assert r.trials == 0 and r.accepted == 0
+        assert np.array_equal(c.state()["theta"], t)
+        assert abs(r.e_start - r1.e_accepted) <= 1e-9 * max(abs(r1.e_accepted), 1.0)
+        assert r.e_start == r.e_accepted == r.e_best
+    for c in chains:
+        c.free()
+
+
+def test_mc_mixed_precision():
+    # mixed precision: energies within the form's tolerance of the oracle's at
+    # the start; the search itself may take other decisions
+    cases = _cases()
+    chains = _build(cases, kcm.KCM_MIXED)
+    _, res = kcm.kcm_mc_minimize(chains, [c[3] for c in cases], np.stack([c[4] for c in cases]), N_DESCENT, KT)
+    for (m, sc, th, d, u), r in zip(cases, res):
+        ref = oracle.OracleChain(np.zeros(m, np.int32), T)
+        o = oracle.iterate(ref, th, terms="elec+vdw")
+        e0 = o["E_elec"] + o["E_vdw"]
+        assert r.status == 0 and r.trials == N_TRIALS
+        assert abs(r.e_start - e0) <= 1e-5 * max(abs(e0), 1.0)
+        assert r.e_best <= r.e_start
+    for c in chains:
+        c.free()
