@@ -21,7 +21,8 @@ import numpy as np
 class EnergyScanner:
     """A pool of ``batch`` copies of one chain with every joint fixed."""
 
-    def __init__(self, res_type, residue_types, params=None, batch: int = 256, stream=None):
+    def __init__(self, res_type, residue_types, params=None, batch: int = 256, stream=None,
+                 side_chains: bool = False):
         from . import kcm
 
         if batch < 1:
@@ -30,13 +31,15 @@ class EnergyScanner:
         self.params = params if params is not None else kcm.kcm_default_params()
         self.stream = stream
         self.res_type = np.ascontiguousarray(res_type, dtype=np.int32)
-        self.n_joints = 2 * self.res_type.size
+        self.n_joints = (3 if side_chains else 2) * self.res_type.size
         mask = np.zeros(self.n_joints, np.uint8)
-        self.pool = [kcm.Chain(self.res_type, residue_types, self.params, joint_mask=mask, stream=stream)
+        self.pool = [kcm.Chain(self.res_type, residue_types, self.params, joint_mask=mask, stream=stream,
+                               side_chains=side_chains)
                      for _ in range(batch)]
 
     def energies(self, thetas) -> np.ndarray:
-        """thetas: [G, 2 n_res] dihedrals; returns [G, 3] (elec, vdw, cav) energies."""
+        """thetas: [G, J] dihedrals (J = 2 n_res, or 3 n_res with side chains);
+        returns [G, 3] (elec, vdw, cav) energies."""
         th = np.asarray(thetas, dtype=np.float64)
         if th.ndim != 2 or th.shape[1] != self.n_joints:
             raise ValueError(f"thetas must have shape [G, {self.n_joints}]")
@@ -62,7 +65,7 @@ class EnergyScanner:
 
 def grid_thetas(theta0, joints, values) -> np.ndarray:
     """Every combination of ``values`` (one sequence per joint) at ``joints``, the
-    other dihedrals at ``theta0``: [prod(len(v)), 2 n_res], the last joint fastest."""
+    other dihedrals at ``theta0``: [prod(len(v)), len(theta0)], the last joint fastest."""
     base = np.asarray(theta0, dtype=np.float64)
     joints = list(joints)
     if len(joints) != len(values):

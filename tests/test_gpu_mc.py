@@ -133,3 +133,26 @@ def test_mc_mixed_precision():
         assert r.e_best <= r.e_start
     for c in chains:
         c.free()
+
+
+def test_mc_with_fixed_joints_matches_oracle():
+    # a joint mask: fixed joints are neither perturbed nor stepped
+    m = 10
+    lengths, thetas = synth.polyala_starts(1, 31, lo=m, hi=m)
+    th = thetas[0]
+    mask = np.ones(2 * m, np.uint8)
+    mask[::3] = 0
+    d, u = synth.mc_moves(N_TRIALS, 2 * m, 303, n_moved=4)
+    p = polyala.experiment_params(False)
+    c = kcm.Chain(np.zeros(m, np.int32), T, p, theta0=th, joint_mask=mask)
+    _, (r,) = kcm.kcm_mc_minimize([c], [d], u[None], N_DESCENT, KT)
+    ref = oracle.OracleChain(np.zeros(m, np.int32), T)
+    o = oracle.mc_minimize(ref, th, d, u, N_DESCENT, KT, terms="elec+vdw", mask=mask, s=1e-2)
+    assert o["margins"].min() > 1e-6
+    got = c.state()["theta"]
+    _log(case="mc_mask", accepted=r.accepted, oracle_accepted=o["accepted"],
+         dtheta=float(_wrap(got - o["theta"]).max()))
+    assert r.status == 0 and r.accepted == o["accepted"]
+    assert _wrap(got - o["theta"]).max() <= 1e-8
+    assert np.array_equal(got[mask == 0], th[mask == 0])
+    c.free()

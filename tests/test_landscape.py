@@ -92,3 +92,39 @@ def test_hinge_scan_matches_oracle():
             assert abs(E[g, 2] - o["E_cav"]) <= 1e-12 * max(abs(o["E_cav"]), 1.0)
     print(f"case=hinge_scan points={len(grid)} worst_pair_energy={worst}", flush=True)
     assert worst < 1e-5
+
+
+@pytest.mark.gpu
+def test_side_chain_rotamer_scan_matches_oracle():
+    # chi of one residue of a 12-residue chain with side chains, 10-degree steps
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import oracle
+    import synth
+    from gpu_common import TYPES, oracle_step, params
+    from paper_1712_05012_amd import kcm
+    from paper_1712_05012_amd.landscape import EnergyScanner
+
+    kcm.load_library()
+    p = params(kcm.KCM_FP64)
+    m, seed = 12, 91
+    seq = synth.sequence(m, seed)
+    th0 = np.concatenate([synth.random_dihedrals(m, seed), synth.random_chi(m, seed)])
+    vals = np.radians(np.arange(-180.0, 180.0, 10.0))
+    grid = grid_thetas(th0, [2 * m + 5], [vals])
+    sc = EnergyScanner(seq, TYPES, p, batch=16, side_chains=True)
+    E = sc.energies(grid)
+    sc.free()
+    ref = oracle.OracleChain(seq, TYPES, g_hydro=p.g_hydro)
+    mask = np.zeros(3 * m, np.uint8)
+    worst = 0.0
+    for g, th in enumerate(grid):
+        o = oracle_step(ref, th, p, mask)
+        worst = max(worst, max(abs(E[g, k] - o[n]) / max(abs(o[n]), 1.0) for k, n in enumerate(("E_elec", "E_vdw"))))
+        if o["margin"] > 1e-10:
+            assert abs(E[g, 2] - o["E_cav"]) <= 1e-12 * max(abs(o["E_cav"]), 1.0)
+    print(f"case=chi_scan points={len(grid)} worst_pair_energy={worst}", flush=True)
+    assert worst < 1e-9
+    # the scan moves only the three HB atoms of residue 6: energies vary
+    assert np.ptp(E[:, 0] + E[:, 1]) > 0.0
