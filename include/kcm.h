@@ -13,7 +13,9 @@
  *    links.  Atom 10 i + s is slot s of residue i, slots in the order
  *    N, H, CA, HA, CB, HB1, HB2, HB3, C, O.  Joint 2 i is phi_i (axis N_i->CA_i),
  *    joint 2 i + 1 is psi_i (axis CA_i->C_i); joint j turns every atom of the
- *    links after it (Sec. 2.1, Table 2).  omega is fixed at 180 degrees.
+ *    links after it (Sec. 2.1, Table 2).  omega is fixed at 180 degrees.  A
+ *    chain built with side chains has J = 3 m: joint 2 m + i is chi_i, which
+ *    turns HB1..HB3 of residue i about CA_i->CB_i.
  *  * Angles theta are the dihedrals phi/psi themselves, in (-pi, pi]; the zero
  *    position (ZP) of the paper's ZRPD convention is phi = psi = 180 degrees.
  *  * Host pointers are read during the call and not kept.  Device memory is
@@ -23,6 +25,9 @@
  *    work is queued asynchronously unless a function says it synchronises.
  *  * Every function returns a kcm_status; no exception crosses the ABI.  The
  *    calling thread's last error message is available from kcm_last_error().
+ *  * The entry points that launch work (kcm_step, kcm_fold, kcm_mc_minimize)
+ *    may be called from several threads; the library serialises them, each
+ *    for the whole of its call.
  *  * A numeric failure (NaN/Inf in forces or torques) marks only the chain it
  *    occurs in: its theta is left unchanged, its report carries
  *    KCM_E_NUMERIC, and the other chains of a batched call continue.
