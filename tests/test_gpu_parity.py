@@ -505,3 +505,49 @@ def test_large_globule_sampled_parity():
     assert net <= 1e-6
     assert np.abs(fc.sum(axis=0)).max() < 1e-6
     gpu.free()
+
+
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_benchmark_workload_in_its_launch_configuration(precision):
+    # the benchmarked workload itself: the 1000-residue compact globule
+    # (10,000 atoms), replayed as HIP graphs of 8 iterations like bench.py.
+    # The capped descent of this start is chaotic (the oracle turns a 1e-13
+    # rad offset into 3e-3 rad within 16 iterations: its first steps create
+    # clashes with torques near 1e23), so parity is per step from shared
+    # angles: one iteration at the start, and one at the angles the device
+    # reached after 16 graph-replayed iterations, which must equal 16 directly
+    # launched ones bit for bit.
+    m = 1000
+    seq = synth.sequence(m, synth.config_seed(2))
+    th = synth.load_globule(m)
+    p = params(precision)
+    ref = oracle.OracleChain(seq, TYPES, g_hydro=p.g_hydro)
+    try:
+        kcm.kcm_set_graphs(8)
+        gpu = kcm.Chain(seq, TYPES, p, theta0=th)
+        for label, start in (("start", None), ("after16", "run")):
+            if start == "run":
+                gpu.set_theta(th)
+                rep = gpu.step(16)
+                assert rep.status == 0
+                th16 = gpu.state()["theta"]
+                kcm.kcm_set_graphs(0)
+                direct = kcm.Chain(seq, TYPES, p, theta0=th)
+                assert direct.step(16).status == 0
+                assert np.array_equal(direct.state()["theta"], th16)
+                direct.free()
+                kcm.kcm_set_graphs(8)
+                at = th16
+            else:
+                at = th
+            st, o, err = compare_step(gpu, ref, at, p)
+            _log(case="benchmark_workload", at=label, precision=precision, **err)
+            assert err["status"] == 0
+            assert err["xyz"] < 1e-9
+            assert err["F"] <= F_TOL and err["F_pair"] <= F_TOL and err["F_cav"] <= F_TOL
+            assert err["dtheta"] <= DTHETA_TOL[precision]
+            if err["margin"] > 1e-10:
+                assert err["E_cav"] < 1e-12
+        gpu.free()
+    finally:
+        kcm.kcm_set_graphs(1)
