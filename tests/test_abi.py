@@ -92,3 +92,19 @@ def test_launch_mode_settings_are_validated():
         assert lib.kcm_set_graphs(depth) == kcm.KCM_OK
     assert lib.kcm_set_timing(-1) == kcm.KCM_E_INVAL
     assert lib.kcm_set_timing(0) == kcm.KCM_OK
+
+
+def test_side_chain_layout_and_validation():
+    T = synth.residue_types()
+    p = kcm.kcm_default_params()
+    seq = synth.sequence(100, 1)
+    b = kcm.kcm_chain_bytes(kcm.make_desc(seq, T), p)
+    bs = kcm.kcm_chain_bytes(kcm.make_desc(seq, T, side_chains=True), p)
+    assert bs > b and bs % 256 == 0
+    with pytest.raises(ValueError):
+        kcm.make_desc(seq, T, theta0=np.zeros(200), side_chains=True)
+    bad = kcm.make_desc(seq, T)
+    bad.desc.side_chains = 2
+    with pytest.raises(kcm.KcmError) as e:
+        kcm.kcm_chain_bytes(bad, p)
+    assert e.value.status == kcm.KCM_E_INVAL

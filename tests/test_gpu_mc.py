@@ -156,3 +156,20 @@ def test_mc_with_fixed_joints_matches_oracle():
     assert _wrap(got - o["theta"]).max() <= 1e-8
     assert np.array_equal(got[mask == 0], th[mask == 0])
     c.free()
+
+
+def test_mc_rejects_bad_arguments():
+    cases = _cases()[:1]
+    chains = _build(cases)
+    d, u = cases[0][3], cases[0][4][None]
+    for kw in ({"kT": -1.0}, {"n_descent": -1}):
+        args = {"n_descent": N_DESCENT, "kT": KT, **kw}
+        with pytest.raises(kcm.KcmError) as e:
+            kcm.kcm_mc_minimize(chains, [d], u, args["n_descent"], args["kT"])
+        assert e.value.status == kcm.KCM_E_INVAL
+    with pytest.raises(ValueError):
+        kcm.kcm_mc_minimize(chains, [d[:, :-1]], u, N_DESCENT, KT)
+    with pytest.raises(ValueError):
+        kcm.kcm_mc_minimize(chains, [d], u[:, :-1], N_DESCENT, KT)
+    for c in chains:
+        c.free()
