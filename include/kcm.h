@@ -225,6 +225,16 @@ kcm_status kcm_set_limits(kcm_chain *chain, double tol_dtheta, int64_t max_itera
  * or to re-synchronise with a reference; clears its converged flag. */
 kcm_status kcm_set_theta(kcm_chain *chain, const double *theta, void *hip_stream);
 
+/* kcm_set_theta for many chains from one DEVICE array: chain c's J_c angles
+ * follow the earlier chains' in call order.  Angles are wrapped into
+ * (-pi, pi] on the device; they must be finite (a non-finite angle makes the
+ * chain fail with KCM_E_NUMERIC at its next iteration).  Each chain's flags
+ * are cleared as by kcm_set_theta.  The array is read by work queued on
+ * hip_stream, so it must stay valid until that work has run (the next
+ * kcm_step on the stream suffices). */
+kcm_status kcm_set_theta_batch(kcm_chain *const *chains, int32_t n_chains, const double *theta,
+                               void *hip_stream);
+
 /* The cell list of the last evaluation (Sec. 3.2): dims[3] cells per axis,
  * *cell_size (A), origin[3] (grid corner), order[n] (atom index of each
  * sorted slot), cell_start[dims0*dims1*dims2 + 1].  Any pointer may be NULL;

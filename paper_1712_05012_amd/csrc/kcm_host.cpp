@@ -512,6 +512,28 @@ kcm_status gather_stats(Table *t, hipStream_t stream, std::vector<ChainStats> &o
     return KCM_OK;
 }
 
+// Device offsets of per-chain blocks of `per_joint` x J_c doubles laid one
+// after the other in call order, in the table's offset buffer.  Synchronises.
+kcm_status upload_joint_offsets(Table *t, kcm_chain *const *chains, int n_chains, int64_t per_joint,
+                                hipStream_t stream)
+{
+    if (n_chains + 1 > t->mc_off_cap) {
+        HIP_TRY(hipStreamSynchronize(stream));
+        if (t->mc_off_dev) HIP_TRY(hipFree(t->mc_off_dev));
+        t->mc_off_dev = nullptr;
+        t->mc_off_cap = 0;
+        const int cap = std::max(2 * (n_chains + 1), 64);
+        HIP_TRY(hipMalloc(&t->mc_off_dev, sizeof(int64_t) * cap));
+        t->mc_off_cap = cap;
+    }
+    std::vector<int64_t> off(n_chains + 1, 0);
+    for (int i = 0; i < n_chains; ++i) off[i + 1] = off[i] + per_joint * chains[i]->J;
+    HIP_TRY(hipMemcpyAsync(t->mc_off_dev, off.data(), sizeof(int64_t) * (n_chains + 1), hipMemcpyHostToDevice,
+                           stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+    return KCM_OK;
+}
+
 kcm_status check_chains(kcm_chain *const *chains, int n_chains, int *precision)
 {
     if (!chains || n_chains < 1) return fail(KCM_E_INVAL, "no chains");
@@ -921,20 +943,7 @@ kcm_status kcm_mc_minimize(kcm_chain *const *chains, int32_t n_chains, int32_t n
     Table *t = nullptr;
     if ((s = ensure_table(chains, n_chains, stream, &t)) != KCM_OK) return s;
     // per-chain offsets of the perturbations: chain c's [n_trials][J_c] block
-    if (n_chains + 1 > t->mc_off_cap) {
-        HIP_TRY(hipStreamSynchronize(stream));
-        if (t->mc_off_dev) HIP_TRY(hipFree(t->mc_off_dev));
-        t->mc_off_dev = nullptr;
-        t->mc_off_cap = 0;
-        const int cap = std::max(2 * (n_chains + 1), 64);
-        HIP_TRY(hipMalloc(&t->mc_off_dev, sizeof(int64_t) * cap));
-        t->mc_off_cap = cap;
-    }
-    std::vector<int64_t> off(n_chains + 1, 0);
-    for (int i = 0; i < n_chains; ++i) off[i + 1] = off[i] + (int64_t)n_trials * chains[i]->J;
-    HIP_TRY(hipMemcpyAsync(t->mc_off_dev, off.data(), sizeof(int64_t) * (n_chains + 1), hipMemcpyHostToDevice,
-                           stream));
-    HIP_TRY(hipStreamSynchronize(stream));
+    if ((s = upload_joint_offsets(t, chains, n_chains, n_trials, stream)) != KCM_OK) return s;
     const Batch &bt = t->batch;
     // the energy of the current angles: one evaluation, taken as the start
     HIP_TRY(launch_mc_propose(bt, MC_RESET, nullptr, nullptr, 0, stream));
@@ -1073,6 +1082,22 @@ kcm_status kcm_set_theta(kcm_chain *c, const double *theta, void *hip_stream)
     if ((st = write_field(&c->h.stats->grid_bad, 0, s)) != KCM_OK) return st;
     c->boot = true;
     return write_field(&c->h.stats->active, 1, s);
+}
+
+kcm_status kcm_set_theta_batch(kcm_chain *const *chains, int32_t n_chains, const double *theta, void *hip_stream)
+{
+    int prec = 0;
+    kcm_status s = check_chains(chains, n_chains, &prec);
+    if (s != KCM_OK) return s;
+    if (!theta) return fail(KCM_E_INVAL, "null theta");
+    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    std::lock_guard<std::mutex> lock(g_mu);
+    Table *t = nullptr;
+    if ((s = ensure_table(chains, n_chains, stream, &t)) != KCM_OK) return s;
+    if ((s = upload_joint_offsets(t, chains, n_chains, 1, stream)) != KCM_OK) return s;
+    HIP_TRY(launch_set_theta(t->batch, theta, t->mc_off_dev, stream));
+    for (int i = 0; i < n_chains; ++i) chains[i]->boot = true;
+    return KCM_OK;
 }
 
 kcm_status kcm_set_limits(kcm_chain *c, double tol_dtheta, int64_t max_iterations, void *hip_stream)

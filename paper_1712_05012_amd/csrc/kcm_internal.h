@@ -153,6 +153,7 @@ hipError_t launch_mc_propose(const Batch &b, int mode, const double *delta, cons
 hipError_t launch_mc_decide(const Batch &b, int mode, const double *u, int n_trials, int trial, double kT,
                             hipStream_t s);
 hipError_t launch_mc_apply(const Batch &b, hipStream_t s);
+hipError_t launch_set_theta(const Batch &b, const double *theta, const int64_t *theta_off, hipStream_t s);
 hipError_t launch_stats_gather(const Batch &b, ChainStats *out, hipStream_t s);
 hipError_t launch_fold_control(const Batch &b, int mode, double tol, int64_t max_iter, hipStream_t s);
 

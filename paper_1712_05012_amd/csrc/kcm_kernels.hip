@@ -850,6 +850,32 @@ __global__ __launch_bounds__(JOINT_BLOCK) void k_mc_apply(Batch bt)
     else cd->theta[j] = cd->mc_theta[j];
 }
 
+// New angles for every chain of the batch from one device array (chain c's
+// J_c angles at theta_off[c]), wrapped into (-pi, pi]; each chain restarts
+// like a freshly built one (flags cleared, positions and grid anew).
+__global__ __launch_bounds__(JOINT_BLOCK) void k_set_theta(Batch bt, const double *__restrict__ theta,
+                                                            const int64_t *__restrict__ theta_off)
+{
+    const int c = find_block_owner(bt.jblk_off, bt.n_chains, blockIdx.x);
+    ChainDev *cd = bt.table[c];
+    const int jb = blockIdx.x - bt.jblk_off[c];
+    if (jb == 0 && threadIdx.x == 0) {
+        ChainStats *st = cd->stats;
+        st->converged = 0;
+        st->status = 0;
+        st->nbr_overflow = 0;
+        st->need_grid = 1;
+        st->pending_post = 0;
+        st->post_bad = 0;
+        st->grid_bad = 0;
+        st->run = 1;
+        st->active = 1;
+    }
+    int j;
+    if (!joint_of_block(cd, jb, threadIdx.x, &j)) return;
+    cd->theta[j] = wrap_angle(theta[theta_off[c] + j]);
+}
+
 // ---------------------------------------------------------------------------
 // cell list: exclusive scan of the counts, counting-sort scatter, stable
 // order inside each cell, gather into cell order
@@ -1861,6 +1887,13 @@ hipError_t launch_mc_apply(const Batch &b, hipStream_t s)
 {
     if (b.total_jblocks <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_mc_apply, dim3(b.total_jblocks), dim3(JOINT_BLOCK), 0, s, b);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_theta(const Batch &b, const double *theta, const int64_t *theta_off, hipStream_t s)
+{
+    if (b.total_jblocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_set_theta, dim3(b.total_jblocks), dim3(JOINT_BLOCK), 0, s, b, theta, theta_off);
     return hipGetLastError();
 }
 

@@ -24,7 +24,7 @@ KCM_TERM_ELEC, KCM_TERM_VDW, KCM_TERM_CAV, KCM_TERM_ALL = 1, 2, 4, 7
 EXPORTED = ("kcm_default_params", "kcm_chain_bytes", "kcm_build_chain", "kcm_step", "kcm_fold",
             "kcm_get_state", "kcm_get_forces", "kcm_set_theta", "kcm_get_cells", "kcm_chain_info",
             "kcm_set_timing", "kcm_get_timing", "kcm_chain_free", "kcm_last_error", "kcm_get_atom_terms",
-            "kcm_set_limits", "kcm_set_graphs", "kcm_mc_minimize", "kcm_mc_best_theta")
+            "kcm_set_limits", "kcm_set_graphs", "kcm_mc_minimize", "kcm_mc_best_theta", "kcm_set_theta_batch")
 
 
 class KcmError(RuntimeError):
@@ -100,6 +100,7 @@ def load_library(path: str = LIB_PATH):
     lib.kcm_mc_minimize.argtypes = [C.POINTER(vp), C.c_int32, C.c_int32, C.c_int32, C.c_double, vp, vp, vp,
                                     C.POINTER(kcm_mc_result)]
     lib.kcm_mc_best_theta.argtypes = [vp, vp, vp]
+    lib.kcm_set_theta_batch.argtypes = [C.POINTER(vp), C.c_int32, vp, vp]
     lib.kcm_last_error.argtypes = []
     lib.kcm_last_error.restype = C.c_char_p
     for name in EXPORTED:
@@ -255,6 +256,30 @@ def kcm_mc_minimize(chains, delta, u, n_descent: int, kT: float, stream=None, ch
     if check:
         _check(st)
     return st, list(res)
+
+
+def kcm_set_theta_batch(chains, thetas, stream=None):
+    """New angles for every chain in one device copy and one kernel.
+
+    thetas: one host array [J_c] per chain (a 2-D array works when all chains
+    have the same J).  Returns the device tensor holding them, which the
+    caller keeps until work queued after this call on the stream has run."""
+    import torch
+
+    if len(thetas) != len(chains):
+        raise ValueError("one theta array per chain")
+    parts = []
+    for c, t in zip(chains, thetas):
+        t = np.ascontiguousarray(t, dtype=np.float64)
+        J = kcm_chain_info(c.handle if isinstance(c, Chain) else c)[1]
+        if t.shape != (J,):
+            raise ValueError(f"theta of a chain must have {J} entries")
+        parts.append(t)
+    dev = torch.from_numpy(np.concatenate(parts)).to(torch.device("cuda"))
+    torch.cuda.current_stream().synchronize()
+    _check(load_library().kcm_set_theta_batch(_handles(chains), len(chains), C.c_void_p(dev.data_ptr()),
+                                              _stream_handle(stream)))
+    return dev
 
 
 def kcm_mc_best_theta(handle, stream=None):

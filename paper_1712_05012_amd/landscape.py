@@ -43,14 +43,16 @@ class EnergyScanner:
         th = np.asarray(thetas, dtype=np.float64)
         if th.ndim != 2 or th.shape[1] != self.n_joints:
             raise ValueError(f"thetas must have shape [G, {self.n_joints}]")
+        if not np.all(np.isfinite(th)):
+            raise ValueError("thetas must be finite")
         out = np.zeros((th.shape[0], 3))
         B = len(self.pool)
         for g0 in range(0, th.shape[0], B):
             part = th[g0:g0 + B]
             chains = self.pool[:part.shape[0]]
-            for c, t in zip(chains, part):
-                c.set_theta(t, self.stream)
+            held = self.kcm.kcm_set_theta_batch(chains, part, self.stream)
             _, reps = self.kcm.kcm_step(chains, 1, self.stream, report=True, check=False)
+            del held  # kcm_step with reports has synchronised the stream
             for k, r in enumerate(reps):
                 if r.status != 0:
                     raise self.kcm.KcmError(r.status, f"grid point {g0 + k}: numeric status {r.status}")

@@ -219,20 +219,19 @@ def mc_versus_descent(n_chains: int = 2000, seed: int = 1712, lo: int = 10, hi: 
     chains = [kcm.Chain(np.zeros(m, np.int32), T, p, theta0=th, stream=stream) for m, th in zip(lengths, thetas)]
     try:
         kcm.kcm_step(chains, 1, stream)  # first launches and graph capture outside the timing
-        for c, th in zip(chains, thetas):
-            c.set_theta(th, stream)
+        held = kcm.kcm_set_theta_batch(chains, thetas, stream)
         t0 = time.perf_counter()
         _, reps = kcm.kcm_step(chains, evals, stream, report=True, check=False)
         out["descent_seconds"] = time.perf_counter() - t0
         e_desc = np.array([r.e_elec + r.e_vdw + (r.e_cav if solvation else 0.0) for r in reps])
-        for c, th in zip(chains, thetas):
-            c.set_theta(th, stream)
+        held = kcm.kcm_set_theta_batch(chains, thetas, stream)
         moves = [synth.mc_moves(n_trials, 2 * int(m), seed * 7919 + k, n_moved, max_rad)
                  for k, m in enumerate(lengths)]
         t0 = time.perf_counter()
         _, res = kcm.kcm_mc_minimize(chains, [mv[0] for mv in moves], np.stack([mv[1] for mv in moves]),
                                      n_descent, kT, stream, check=False)
         out["search_seconds"] = time.perf_counter() - t0
+        del held
     finally:
         for c in chains:
             c.free()

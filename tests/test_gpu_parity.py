@@ -551,3 +551,42 @@ def test_benchmark_workload_in_its_launch_configuration(precision):
         gpu.free()
     finally:
         kcm.kcm_set_graphs(1)
+
+
+def test_batched_angle_setter_equals_per_chain_setter():
+    # kcm_set_theta_batch (one device array, one kernel) against kcm_set_theta
+    # per chain, on chains of different lengths with and without side chains:
+    # the next iterations are bit for bit the same
+    p = params(kcm.KCM_MIXED)
+    spec = [(7, 301, False), (40, 302, True), (300, 303, False), (129, 304, True)]
+    a = [build_pair(m, s, p, side_chains=sc)[0] for m, s, sc in spec]
+    b = [build_pair(m, s, p, side_chains=sc)[0] for m, s, sc in spec]
+    kcm.kcm_step(a, 3)
+    kcm.kcm_step(b, 3)
+    rng = np.random.default_rng(5)
+    new = [rng.uniform(-np.pi, np.pi, c.n_joints) for c in a]
+    held = kcm.kcm_set_theta_batch(a, new)
+    for c, t in zip(b, new):
+        c.set_theta(t)
+    _, ra = kcm.kcm_step(a, 4)
+    _, rb = kcm.kcm_step(b, 4)
+    del held
+    for ca, cb, x, y in zip(a, b, ra, rb):
+        assert x.status == 0 and y.status == 0
+        assert np.array_equal(ca.state()["theta"], cb.state()["theta"])
+        assert (x.e_elec, x.e_vdw, x.e_cav) == (y.e_elec, y.e_vdw, y.e_cav)
+    # angles outside (-pi, pi] are wrapped (the two setters by different
+    # formulas, equal up to rounding)
+    far = [rng.uniform(-20.0, 20.0, c.n_joints) for c in a]
+    held = kcm.kcm_set_theta_batch(a, far)
+    for c, t in zip(b, far):
+        c.set_theta(t)
+    torch.cuda.synchronize()
+    del held
+    for ca, cb, t in zip(a, b, far):
+        ta, tb = ca.state()["theta"], cb.state()["theta"]
+        assert np.all(ta > -np.pi) and np.all(ta <= np.pi)
+        assert np.abs(ta - tb).max() <= 1e-14
+        assert np.abs(np.angle(np.exp(1j * (ta - t)))).max() <= 1e-13
+    for c in a + b:
+        c.free()
