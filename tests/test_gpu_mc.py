@@ -173,3 +173,28 @@ def test_mc_rejects_bad_arguments():
         kcm.kcm_mc_minimize(chains, [d], u[:, :-1], N_DESCENT, KT)
     for c in chains:
         c.free()
+
+
+def test_mc_with_solvation_matches_oracle():
+    # in water: the solvation energy enters the Metropolis test
+    lengths, thetas = synth.polyala_starts(3, 41, lo=8, hi=12)
+    p = polyala.experiment_params(True)
+    chains, moves = [], []
+    for k in range(3):
+        m = int(lengths[k])
+        chains.append(kcm.Chain(np.zeros(m, np.int32), T, p, theta0=thetas[k]))
+        moves.append(synth.mc_moves(6, 2 * m, 500 + k))
+    _, res = kcm.kcm_mc_minimize(chains, [d for d, _ in moves], np.stack([u for _, u in moves]), N_DESCENT, KT)
+    for k, (c, r) in enumerate(zip(chains, res)):
+        m = int(lengths[k])
+        d, u = moves[k]
+        o = oracle.mc_minimize(oracle.OracleChain(np.zeros(m, np.int32), T), thetas[k], d, u, N_DESCENT, KT,
+                               terms="elec+vdw+cav", s=1e-2)
+        assert o["margins"].min() > 1e-6
+        err = float(_wrap(c.state()["theta"] - o["theta"]).max())
+        _log(case="mc_water", m=m, accepted=r.accepted, oracle_accepted=o["accepted"], dtheta=err,
+             de=abs(r.e_best - o["E_best"]) / max(abs(o["E_best"]), 1.0))
+        assert r.status == 0 and r.accepted == o["accepted"]
+        assert err <= 1e-8
+        assert abs(r.e_best - o["E_best"]) <= 1e-9 * max(abs(o["E_best"]), 1.0)
+        c.free()
