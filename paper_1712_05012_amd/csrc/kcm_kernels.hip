@@ -1083,6 +1083,21 @@ __device__ __forceinline__ bool test_cover(Real v, const ChainDev *cd, const dou
     return hit;
 }
 
+// The three displaced tests of one (sample, neighbour) pair are decided in
+// the form's precision first; the mixed form then takes every test inside the
+// band again in FP64, the three behind one branch.  band3: is any of them in
+// the band; redo: the FP32 decision minus the FP64 one for a test in the band
+// (0 outside it), the correction to a count of covered tests.
+__device__ __forceinline__ bool band3(float v0, float v1, float v2)
+{
+    return fminf(fabsf(v0), fminf(fabsf(v1), fabsf(v2))) <= MIXED_BAND;
+}
+__device__ __forceinline__ int redo(float v, const ChainDev *cd, const double4 &ri, double roff_i, int k, int aj, int s)
+{
+    if (fabsf(v) > MIXED_BAND) return 0;
+    return (v >= 0.0f ? 1 : 0) - (cover_exact(cd, ri, roff_i, k, aj, s) ? 1 : 0);
+}
+
 template <typename Real>
 __device__ __forceinline__ void load_q(const ChainDev *cd, int k, Real &x, Real &y, Real &z)
 {
@@ -1651,11 +1666,19 @@ __global__ __launch_bounds__(WAVE, sizeof(Real) == 4 ? 4 : 3) void k_force(Batch
                         const Real base = Qx[i] * e.ax + Qy[i] * e.ay + Qz[i] * e.az - e.c0 - kq;
                         const Real span = drr + k1 * fmax(fabs(e.ax), fmax(fabs(e.ay), fabs(e.az)));
                         if (base - span <= guard) {
-                            unsigned inc01 = 0;
-                            if (!test_cover<Real, MIXED>(base + drr * Qx[i] - k1 * e.ax, cd, ri, roff_i, k, aj, 0)) inc01 += 1u;
-                            if (!test_cover<Real, MIXED>(base + drr * Qy[i] - k1 * e.ay, cd, ri, roff_i, k, aj, 1)) inc01 += 1u << 16;
+                            // events: the shifted copies that no longer cover the sample
+                            const Real v0 = base + drr * Qx[i] - k1 * e.ax;
+                            const Real v1 = base + drr * Qy[i] - k1 * e.ay;
+                            const Real v2 = base + drr * Qz[i] - k1 * e.az;
+                            int n0 = v0 < (Real)0, n1 = v1 < (Real)0, n2 = v2 < (Real)0;
+                            if (MIXED && band3((float)v0, (float)v1, (float)v2)) {
+                                n0 += redo((float)v0, cd, ri, roff_i, k, aj, 0);
+                                n1 += redo((float)v1, cd, ri, roff_i, k, aj, 1);
+                                n2 += redo((float)v2, cd, ri, roff_i, k, aj, 2);
+                            }
+                            const unsigned inc01 = (unsigned)n0 + ((unsigned)n1 << 16);
                             if (inc01) atomicAdd(&s_ev01[u], inc01);
-                            if (!test_cover<Real, MIXED>(base + drr * Qz[i] - k1 * e.az, cd, ri, roff_i, k, aj, 2)) atomicAdd(&s_ev2[u], 1);
+                            if (n2) atomicAdd(&s_ev2[u], 1);
                         }
                     }
                     if (valid && C >= 1) ++ncov;
@@ -1679,10 +1702,19 @@ __global__ __launch_bounds__(WAVE, sizeof(Real) == 4 ? 4 : 3) void k_force(Batch
                                 const Real qx = bcast(Qx[i], l), qy = bcast(Qy[i], l), qz = bcast(Qz[i], l);
                                 const Real base = qx * e.ax + qy * e.ay + qz * e.az - e.c0 - kq;
                                 if (own && base >= lim) {
-                                    const int kx = kb + l + WAVE * i;
-                                    if (test_cover<Real, MIXED>(base + drr * qx - k1 * e.ax, cd, ri, roff_i, kx, aj, 0)) --d0;
-                                    if (test_cover<Real, MIXED>(base + drr * qy - k1 * e.ay, cd, ri, roff_i, kx, aj, 1)) --d1;
-                                    if (test_cover<Real, MIXED>(base + drr * qz - k1 * e.az, cd, ri, roff_i, kx, aj, 2)) --d2;
+                                    // events: the shifted copies that now cover the sample
+                                    const Real v0 = base + drr * qx - k1 * e.ax;
+                                    const Real v1 = base + drr * qy - k1 * e.ay;
+                                    const Real v2 = base + drr * qz - k1 * e.az;
+                                    d0 -= v0 >= (Real)0;
+                                    d1 -= v1 >= (Real)0;
+                                    d2 -= v2 >= (Real)0;
+                                    if (MIXED && band3((float)v0, (float)v1, (float)v2)) {
+                                        const int kx = kb + l + WAVE * i;
+                                        d0 += redo((float)v0, cd, ri, roff_i, kx, aj, 0);
+                                        d1 += redo((float)v1, cd, ri, roff_i, kx, aj, 1);
+                                        d2 += redo((float)v2, cd, ri, roff_i, kx, aj, 2);
+                                    }
                                 }
                             }
                             // the lane owns neighbour u here, but critical samples of
