@@ -154,3 +154,31 @@ def test_side_chain_inputs_are_validated():
         c.set_theta(np.zeros(8))
     c.free()
     assert oracle.OracleChain(seq, TYPES).J == 8
+
+
+def test_fold_with_side_chains_follows_the_oracle():
+    # kcm_fold with a tolerance on a perturbed 8-residue alanine-like helix with
+    # side chains, in vacuum: the device stops where the oracle's loop stops
+    # (116 iterations), with the same angles
+    T = synth.alanine_like_types()
+    m, cap, tol = 8, 300, 1e-3
+    p = params(kcm.KCM_FP64, max_step=1e-2, terms=kcm.KCM_TERM_ELEC | kcm.KCM_TERM_VDW)
+    th = np.concatenate([np.radians(np.tile([-68.0, -39.0], m)), np.full(m, np.pi / 3)])
+    th = th + 0.05 * np.random.default_rng(1).standard_normal(3 * m)
+    gpu = kcm.Chain(np.zeros(m, np.int32), T, p, theta0=th, side_chains=True)
+    _, (res,) = kcm.kcm_fold([gpu], tol, cap, 7)
+    ref = oracle.OracleChain(np.zeros(m, np.int32), T)
+    t = th.copy()
+    it = 0
+    while it < cap:
+        o = oracle.iterate(ref, t, terms="elec+vdw", kappa=p.kappa, s=p.max_step)
+        t = o["theta"]
+        it += 1
+        if np.abs(o["dtheta"]).max() < tol:
+            break
+    err = float(_wrap(gpu.state()["theta"] - t).max())
+    _log(case="chi_fold", iterations=res.iterations, oracle_iterations=it, converged=res.converged, dtheta=err)
+    assert it < cap, "the oracle run must converge for this test"
+    assert res.status == 0 and res.converged == 1 and res.iterations == it
+    assert err <= 1e-9
+    gpu.free()
