@@ -104,11 +104,10 @@ def test_statistics_sample_follows_the_oracle():
     # iterations split into two batches equal to one batch bit for bit; and at
     # the folded angles of those 400 iterations, one more step of each side
     # from the same angles agrees to the per-step tolerance.
-    import synth as S
     from gpu_common import DTHETA_TOL
 
     n, seed, tol = 48, 5, 1e-4
-    lengths, thetas = S.polyala_starts(n, seed)
+    lengths, thetas = synth.polyala_starts(n, seed)
     off = np.concatenate([[0], np.cumsum(lengths - 1)])
     short = polyala.ramachandran_statistics(n_chains=n, seed=seed, max_iter=100, tol=tol, check_every=5)
     assert np.all(short["status"] == 0)
@@ -128,7 +127,7 @@ def test_statistics_sample_follows_the_oracle():
     assert np.array_equal(a["iterations"], b["iterations"])
     assert np.all(a["status"] == 0)
     assert sum(a["region_counts"].values()) == int((lengths - 1).sum())
-    T = S.alanine_like_types()
+    T = synth.alanine_like_types()
     p = polyala.experiment_params(False)
     for k in (0, 7, 23, 47):
         m = int(lengths[k])
