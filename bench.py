@@ -73,15 +73,19 @@ def algorithmic_units(xyz, T, seq, p, n_exposed, n_samples):
             "exposed_fraction": float(np.mean(n_exposed) / n_samples), "flops": flops}
 
 
-def run_gpu(precision: str, steps: int, warmup: int, m: int):
+def run_gpu(precision: str, steps: int, warmup: int, m: int, side_chains: bool = False):
+    import numpy as np
     import torch
 
     from paper_1712_05012_amd import kcm
 
     T, seq, th = workload(m)
+    if side_chains:
+        # chi at its zero position: the same conformation, with m more joints
+        th = np.concatenate([th, np.full(m, np.pi / 3)])
     prec = kcm.KCM_MIXED if precision == "mixed" else kcm.KCM_FP64
     p = kcm.kcm_default_params(precision=prec)
-    chain = kcm.Chain(seq, T, p, theta0=th)
+    chain = kcm.Chain(seq, T, p, theta0=th, side_chains=side_chains)
     stream = torch.cuda.current_stream()
     kcm.kcm_step([chain], warmup, stream, report=False)
     torch.cuda.synchronize()
@@ -361,9 +365,9 @@ def main():
     ap.add_argument("--serve-warmup", type=int, default=100,
                     help="earliest jobs left out of the serving latency percentiles")
     ap.add_argument("--serve-max-iter", type=int, default=2000)
-    ap.add_argument("--legs", default="main,companion,batch,serving,landscape,polyala,cpu",
-                    help="comma-separated legs to run (main, companion, batch, serving, landscape, polyala, "
-                         "cpu); "
+    ap.add_argument("--legs", default="main,companion,chi,batch,serving,landscape,polyala,cpu",
+                    help="comma-separated legs to run (main, companion, chi, batch, serving, landscape, "
+                         "polyala, cpu); "
                          "profiling runs use a subset, the benchmark line needs main")
     ap.add_argument("--graph-depth", type=int, default=8,
                     help="iterations per replayed HIP graph in the single-chain legs")
@@ -470,6 +474,12 @@ def main():
                        "force_ms": companion["force_ms_mean"],
                        "frac": companion["units"]["flops"] / (companion["force_ms_mean"] * 1e-3) / 1e12
                        / PEAK_TFLOPS[other]}
+    if "chi" in legs:
+        # the same workload with one side-chain joint per residue
+        ch = run_gpu(args.precision, args.steps, args.warmup, residues, side_chains=True)
+        line["side_chains"] = {"value": ch["value"], "ms_per_step": ch["ms_per_step"],
+                               "force_ms": ch["force_ms_mean"], "joints": 3 * residues,
+                               "relative_to_main": ch["value"] / main_run["value"]}
     if "batch" in legs:
         b = run_batch(args.batch_steps, 5, direct=args.no_graphs)
         fp64 = run_per_chain_fp64(max(5, args.batch_steps // 10))
