@@ -198,3 +198,25 @@ def test_mc_with_solvation_matches_oracle():
         assert err <= 1e-8
         assert abs(r.e_best - o["E_best"]) <= 1e-9 * max(abs(o["E_best"]), 1.0)
         c.free()
+
+
+def test_pure_metropolis_without_descent_matches_oracle():
+    # n_descent = 0: every trial is evaluated where it was proposed
+    m = 9
+    lengths, thetas = synth.polyala_starts(1, 55, lo=m, hi=m)
+    d, u = synth.mc_moves(12, 2 * m, 77, n_moved=2, max_rad=0.3)
+    p = polyala.experiment_params(False)
+    c = kcm.Chain(np.zeros(m, np.int32), T, p, theta0=thetas[0])
+    _, (r,) = kcm.kcm_mc_minimize([c], [d], u[None], 0, 5.0)
+    o = oracle.mc_minimize(oracle.OracleChain(np.zeros(m, np.int32), T), thetas[0], d, u, 0, 5.0,
+                           terms="elec+vdw", s=1e-2)
+    assert o["margins"].min() > 1e-6
+    err = float(_wrap(c.state()["theta"] - o["theta"]).max())
+    _log(case="mc_no_descent", accepted=r.accepted, oracle_accepted=o["accepted"], dtheta=err)
+    assert r.status == 0 and r.trials == 12 and r.accepted == o["accepted"]
+    assert err <= 1e-12
+    assert abs(r.e_accepted - o["E"]) <= 1e-9 * max(abs(o["E"]), 1.0)
+    # a fold after the search runs under its own limits again
+    _, (f,) = kcm.kcm_fold([c], 1e-12, 25, 5)
+    assert f.status == 0 and f.iterations == 25 and not f.converged
+    c.free()
