@@ -345,8 +345,40 @@ def cpu_baseline(seconds: float, m: int):
         if time.perf_counter() - t0 >= seconds:
             break
     dt = time.perf_counter() - t0
-    return {"value": ch.n * iters / dt, "unit": "atom-steps/s", "cores": oracle.threads(), "kind": "oracle",
-            "sample": f"{iters} FP64 KCM iterations of the {m}-residue globule ({ch.n} atoms), {dt:.1f} s"}
+    out = {"value": ch.n * iters / dt, "unit": "atom-steps/s", "cores": oracle.threads(), "kind": "oracle",
+           "sample": f"{iters} FP64 KCM iterations of the {m}-residue globule ({ch.n} atoms), {dt:.1f} s"}
+    single = cpu_single_core(max(2.0, seconds / 3), m)
+    if single is not None:
+        out["single_core_value"] = single
+    return out
+
+
+def cpu_single_core(seconds: float, m: int):
+    """The same oracle sample on one host core (a child process with one
+    OpenMP thread); atom-steps/s, or None if the child fails."""
+    import subprocess
+
+    code = (
+        "import json, sys, time\n"
+        f"sys.path.insert(0, {os.path.dirname(os.path.abspath(__file__))!r})\n"
+        "import bench, oracle\n"
+        f"T, seq, th = bench.workload({int(m)})\n"
+        "ch = oracle.OracleChain(seq, T)\n"
+        "it = 0\n"
+        "t0 = time.perf_counter()\n"
+        f"while it == 0 or time.perf_counter() - t0 < {float(seconds)}:\n"
+        "    th = oracle.iterate(ch, th)['theta']\n"
+        "    it += 1\n"
+        "print(json.dumps({'v': ch.n * it / (time.perf_counter() - t0), 't': oracle.threads()}))\n"
+    )
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    try:
+        r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True,
+                           timeout=seconds * 10 + 120)
+        d = json.loads(r.stdout.strip().splitlines()[-1])
+        return d["v"] if d["t"] == 1 else None
+    except Exception:
+        return None
 
 
 def main():
