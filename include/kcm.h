@@ -178,7 +178,8 @@ kcm_status kcm_fold(kcm_chain *const *chains, int n_chains, double tol_dtheta, i
  *   accepted when E' <= E or u < exp(-(E' - E)/kT) (kT = 0: downhill only).
  * delta: DEVICE array, the chains' blocks [n_trials][J_c] one after the other
  * in call order (radians); u: DEVICE array [n_chains][n_trials], uniform in
- * [0, 1).  Both are read during the call only.  All trials of all chains run
+ * [0, 1).  Both are read during the call only; pageable host memory is
+ * rejected with KCM_E_INVAL.  All trials of all chains run
  * on the device with no host round trip.  Afterwards each chain holds its
  * accepted angles (kcm_mc_best_theta gives the lowest); its positions and
  * forces are those of the last evaluated trial, and its next kcm_step starts
@@ -228,7 +229,8 @@ kcm_status kcm_set_theta(kcm_chain *chain, const double *theta, void *hip_stream
 /* kcm_set_theta for many chains from one DEVICE array: chain c's J_c angles
  * follow the earlier chains' in call order.  Angles are wrapped into
  * (-pi, pi] on the device; they must be finite (a non-finite angle makes the
- * chain fail with KCM_E_NUMERIC at its next iteration).  Each chain's flags
+ * chain fail with KCM_E_NUMERIC at its next iteration); pageable host memory
+ * is rejected with KCM_E_INVAL.  Each chain's flags
  * are cleared as by kcm_set_theta.  The array is read by work queued on
  * hip_stream, so it must stay valid until that work has run (the next
  * kcm_step on the stream suffices). */

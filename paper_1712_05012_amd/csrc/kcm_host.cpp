@@ -512,6 +512,18 @@ kcm_status gather_stats(Table *t, hipStream_t stream, std::vector<ChainStats> &o
     return KCM_OK;
 }
 
+// Whether kernels may read p: device, managed or pinned host memory known to
+// HIP.  Pageable host memory (or an unknown address) is not.
+bool device_readable(const void *p)
+{
+    hipPointerAttribute_t a;
+    if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged || a.type == hipMemoryTypeHost;
+}
+
 // Device offsets of per-chain blocks of `per_joint` x J_c doubles laid one
 // after the other in call order, in the table's offset buffer.  Synchronises.
 kcm_status upload_joint_offsets(Table *t, kcm_chain *const *chains, int n_chains, int64_t per_joint,
@@ -938,6 +950,8 @@ kcm_status kcm_mc_minimize(kcm_chain *const *chains, int32_t n_chains, int32_t n
     if (n_trials < 0 || n_descent < 0) return fail(KCM_E_INVAL, "n_trials < 0 or n_descent < 0");
     if (!(kT >= 0.0)) return fail(KCM_E_INVAL, "kT must be >= 0");
     if (n_trials > 0 && (!delta || !u)) return fail(KCM_E_INVAL, "null delta or u");
+    if (n_trials > 0 && (!device_readable(delta) || !device_readable(u)))
+        return fail(KCM_E_INVAL, "delta and u must be device memory");
     hipStream_t stream = static_cast<hipStream_t>(hip_stream);
     std::lock_guard<std::mutex> lock(g_mu);
     Table *t = nullptr;
@@ -1090,6 +1104,7 @@ kcm_status kcm_set_theta_batch(kcm_chain *const *chains, int32_t n_chains, const
     kcm_status s = check_chains(chains, n_chains, &prec);
     if (s != KCM_OK) return s;
     if (!theta) return fail(KCM_E_INVAL, "null theta");
+    if (!device_readable(theta)) return fail(KCM_E_INVAL, "theta must be device memory");
     hipStream_t stream = static_cast<hipStream_t>(hip_stream);
     std::lock_guard<std::mutex> lock(g_mu);
     Table *t = nullptr;
