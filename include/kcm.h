@@ -142,8 +142,8 @@ kcm_status kcm_chain_bytes(const kcm_chain_desc *desc, const kcm_params *params,
  * offset-sphere sample set, and theta0.  Lays everything out in dev_mem (at
  * least kcm_chain_bytes bytes, device memory of the current device) with
  * asynchronous copies on hip_stream and returns a host handle in *out.
- * Errors: KCM_E_INVAL (bad desc/params), KCM_E_NOMEM (bytes too small),
- * KCM_E_DEVICE. */
+ * Errors: KCM_E_INVAL (bad desc/params, dev_mem not 256-byte aligned or not
+ * device memory), KCM_E_NOMEM (bytes too small), KCM_E_DEVICE. */
 kcm_status kcm_build_chain(const kcm_chain_desc *desc, const kcm_params *params, void *dev_mem,
                            size_t bytes, void *hip_stream, kcm_chain **out);
 

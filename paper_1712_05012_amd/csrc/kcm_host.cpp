@@ -608,6 +608,7 @@ kcm_status kcm_build_chain(const kcm_chain_desc *desc, const kcm_params *params,
     const int m = desc->n_res;
     const Layout l = make_layout(m, params->n_orbits, desc->side_chains);
     if (bytes < l.total) return fail(KCM_E_NOMEM, "device block smaller than kcm_chain_bytes");
+    if (!device_readable(dev_mem)) return fail(KCM_E_INVAL, "dev_mem must be device memory");
     hipStream_t stream = static_cast<hipStream_t>(hip_stream);
 
     kcm_chain *c = new kcm_chain();
