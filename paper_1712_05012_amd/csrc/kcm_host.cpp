@@ -555,9 +555,11 @@ kcm_status check_chains(kcm_chain *const *chains, int n_chains, int *precision)
         if (!chains[i]) return fail(KCM_E_INVAL, "null chain handle");
         if (chains[i]->device != dev) return fail(KCM_E_INVAL, "chain lives on another device");
         if (chains[i]->h.precision != chains[0]->h.precision) return fail(KCM_E_INVAL, "chains of one call must share precision");
-        for (int k = 0; k < i; ++k)
-            if (chains[k] == chains[i]) return fail(KCM_E_INVAL, "a chain appears twice in one call");
     }
+    std::vector<const kcm_chain *> sorted(chains, chains + n_chains);
+    std::sort(sorted.begin(), sorted.end());
+    if (std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end())
+        return fail(KCM_E_INVAL, "a chain appears twice in one call");
     *precision = chains[0]->h.precision;
     return KCM_OK;
 }

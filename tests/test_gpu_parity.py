@@ -590,3 +590,17 @@ def test_batched_angle_setter_equals_per_chain_setter():
         assert np.abs(np.angle(np.exp(1j * (ta - t)))).max() <= 1e-13
     for c in a + b:
         c.free()
+
+
+def test_a_chain_twice_in_one_call_is_rejected():
+    p = params(kcm.KCM_MIXED)
+    a = build_pair(5, 401, p)[0]
+    b = build_pair(6, 402, p)[0]
+    for call in (lambda: kcm.kcm_step([a, b, a], 1), lambda: kcm.kcm_fold([b, a, b], 1e-3, 2),
+                 lambda: kcm.kcm_set_theta_batch([a, a], [np.zeros(10), np.zeros(10)])):
+        with pytest.raises(kcm.KcmError) as e:
+            call()
+        assert e.value.status == kcm.KCM_E_INVAL
+    assert kcm.kcm_step([a, b], 1)[0] == kcm.KCM_OK
+    a.free()
+    b.free()
