@@ -204,14 +204,20 @@ def _handles(chains):
     return arr
 
 
-def kcm_step(chains, n_iter: int = 1, stream=None, report: bool = True, check: bool = True):
+def kcm_step(chains, n_iter: int = 1, stream=None, report=True, check: bool = True):
+    """report: True for a list of kcm_step_report, "array" for one numpy
+    structured array with the same fields, False for none."""
     arr = _handles(chains)
     reps = (kcm_step_report * len(chains))() if report else None
     st = load_library().kcm_step(arr, len(chains), int(n_iter), _stream_handle(stream),
                                  reps if report else None)
     if check:
         _check(st)
-    return (st, list(reps)) if report else (st, None)
+    if not report:
+        return st, None
+    if isinstance(report, str) and report == "array":
+        return st, np.ctypeslib.as_array(reps)
+    return st, list(reps)
 
 
 def kcm_fold(chains, tol: float, max_iter: int, check_every: int = 10, stream=None, check: bool = True):
@@ -268,14 +274,18 @@ def kcm_set_theta_batch(chains, thetas, stream=None):
 
     if len(thetas) != len(chains):
         raise ValueError("one theta array per chain")
-    parts = []
-    for c, t in zip(chains, thetas):
-        t = np.ascontiguousarray(t, dtype=np.float64)
-        J = kcm_chain_info(c.handle if isinstance(c, Chain) else c)[1]
-        if t.shape != (J,):
-            raise ValueError(f"theta of a chain must have {J} entries")
-        parts.append(t)
-    dev = torch.from_numpy(np.concatenate(parts)).to(torch.device("cuda"))
+    Js = [c.n_joints if isinstance(c, Chain) else kcm_chain_info(c)[1] for c in chains]
+    if isinstance(thetas, np.ndarray) and thetas.ndim == 2 and all(J == thetas.shape[1] for J in Js):
+        flat = np.ascontiguousarray(thetas, dtype=np.float64).reshape(-1)
+    else:
+        parts = []
+        for J, t in zip(Js, thetas):
+            t = np.ascontiguousarray(t, dtype=np.float64)
+            if t.shape != (J,):
+                raise ValueError(f"theta of a chain must have {J} entries")
+            parts.append(t)
+        flat = np.concatenate(parts)
+    dev = torch.from_numpy(flat).to(torch.device("cuda"))
     torch.cuda.current_stream().synchronize()
     _check(load_library().kcm_set_theta_batch(_handles(chains), len(chains), C.c_void_p(dev.data_ptr()),
                                               _stream_handle(stream)))

@@ -51,12 +51,13 @@ class EnergyScanner:
             part = th[g0:g0 + B]
             chains = self.pool[:part.shape[0]]
             held = self.kcm.kcm_set_theta_batch(chains, part, self.stream)
-            _, reps = self.kcm.kcm_step(chains, 1, self.stream, report=True, check=False)
+            _, reps = self.kcm.kcm_step(chains, 1, self.stream, report="array", check=False)
             del held  # kcm_step with reports has synchronised the stream
-            for k, r in enumerate(reps):
-                if r.status != 0:
-                    raise self.kcm.KcmError(r.status, f"grid point {g0 + k}: numeric status {r.status}")
-                out[g0 + k] = (r.e_elec, r.e_vdw, r.e_cav)
+            bad = np.nonzero(reps["status"] != 0)[0]
+            if bad.size:
+                k = int(bad[0])
+                raise self.kcm.KcmError(int(reps["status"][k]), f"grid point {g0 + k}: numeric status {reps['status'][k]}")
+            out[g0:g0 + len(chains)] = np.stack([reps["e_elec"], reps["e_vdw"], reps["e_cav"]], axis=1)
         return out
 
     def free(self):
