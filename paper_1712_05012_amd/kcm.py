@@ -314,6 +314,14 @@ def kcm_get_state(handle, stream=None):
     return {"theta": theta, "xyz": xyz, "force": F, "tau": tau, "dtheta": dth}
 
 
+def kcm_get_theta(handle, stream=None):
+    """The angles alone (one copy instead of the whole state)."""
+    _, J, _, _ = kcm_chain_info(handle)
+    theta = np.zeros(J)
+    _check(load_library().kcm_get_state(handle, _stream_handle(stream), _p(theta), None, None, None, None))
+    return theta
+
+
 def kcm_get_forces(handle, stream=None):
     n, _, _, _ = kcm_chain_info(handle)
     fp, fc = np.zeros((n, 3)), np.zeros((n, 3))
@@ -403,6 +411,9 @@ class Chain:
 
     def state(self, stream=None):
         return kcm_get_state(self.handle, stream)
+
+    def theta(self, stream=None):
+        return kcm_get_theta(self.handle, stream)
 
     def forces(self, stream=None):
         return kcm_get_forces(self.handle, stream)

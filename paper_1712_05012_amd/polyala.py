@@ -173,7 +173,7 @@ def ramachandran_statistics(n_chains: int = 2000, seed: int = 1712, lo: int = 10
             _, res = kcm.kcm_fold(chains, tol, max_iter, check_every, stream, check=False)
             fold_s += max(r.seconds for r in res)
             for c, r in zip(chains, res):
-                th = c.state(stream)["theta"]
+                th = c.theta(stream)
                 phis.append(_wrap_deg(np.degrees(th[2::2])))
                 psis.append(_wrap_deg(np.degrees(th[3::2])))
                 iters.append(int(r.iterations))

@@ -73,7 +73,7 @@ class KcmEngine:
         return [(int(r.iterations), bool(r.converged), int(r.status)) for r in reps]
 
     def theta(self, chain):
-        return chain.state(self.stream)["theta"]
+        return chain.theta(self.stream)
 
     def close(self, chain):
         chain.free()
