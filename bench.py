@@ -13,7 +13,7 @@ Roofline of the dominant kernel (the force kernel): algorithmic FP work per
 launch = 40 flops per unordered pair within the cutoff + 9 flops per
 (sample, solvation neighbour) coverage test + 9 flops per (exposed sample,
 neighbour) pair for the three displaced tests, divided by the kernel's mean
-launch time from HIP events recorded on its launch stream (on every tenth
+launch time from HIP events recorded on its launch stream (on every 50th
 timed iteration, so that the events barely perturb the timeline).
 """
 from __future__ import annotations
@@ -29,7 +29,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_TFLOPS = {"mixed": 157.3, "fp64": 78.6}  # MI355X vector FP32 / FP64
-TIMING_EVERY = 10  # HIP events bracket the force kernel on every 10th timed iteration
+TIMING_EVERY = 50  # HIP events bracket the force kernel on every 50th timed iteration
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "force_kernel_traffic.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_1712_05012_amd", "csrc", "kcm_kernels.hip")
 
