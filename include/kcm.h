@@ -187,7 +187,10 @@ kcm_status kcm_fold(kcm_chain *const *chains, int n_chains, double tol_dtheta, i
  * angles of before the failure.  The call clears the chains' convergence
  * tolerance and iteration limit (kcm_set_limits), so every descent runs its
  * n_descent iterations.  results[n_chains] may be NULL.
- * Synchronises hip_stream. */
+ * Synchronises hip_stream.  Errors: KCM_E_INVAL (negative n_trials or
+ * n_descent, kT < 0 or NaN, a missing or non-device delta/u, or the chain-set
+ * errors of kcm_step), KCM_E_DEVICE; otherwise the first failing chain's
+ * status, as kcm_step. */
 kcm_status kcm_mc_minimize(kcm_chain *const *chains, int32_t n_chains, int32_t n_trials, int32_t n_descent,
                            double kT, const double *delta, const double *u, void *hip_stream,
                            kcm_mc_result *results);
