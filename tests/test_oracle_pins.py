@@ -471,6 +471,79 @@ def test_coulomb_constant_from_si_units():
     assert abs(Ee - C * ch.q[i] * ch.q[j] / (4.0 * d * d)) < 1e-5 * abs(Ee)
 
 
+def _coulomb_constant():
+    e, eps0, NA = 1.602176634e-19, 8.8541878128e-12, 6.02214076e23
+    return e * e / (4 * np.pi * eps0 * 1e-10) * NA / 4184.0
+
+
+# (slot of an atom of residue 0, slot of an atom of residue 3): every pair is
+# three residues apart, so its weight is 1 (Sec. 3.3)
+_TABLE_PAIRS = [(4, 4), (0, 9), (2, 7), (9, 1), (5, 8)]
+
+
+@pytest.mark.parametrize("seed", [1, 6])
+def test_atom_parameters_follow_the_type_table(seed):
+    # The per-atom inputs are read from the residue-type table, never from the
+    # oracle's own per-atom arrays.  Sec. 2.2 gives the LJ well distance as
+    # D_ij = R_i + R_j (eq 03, 03_1) with eps_ij = sqrt(eps_i eps_j); with the
+    # reading R = 2^(1/6) sigma / 2 the LJ energy of a pair placed at
+    # D = 2^(1/6) (sigma_i + sigma_j) / 2 is exactly -sqrt(eps_i eps_j) and its
+    # force is zero, so what is left of the force is the Coulomb closed form
+    # with the table's charges of (residue type, slot).
+    m = 4
+    seq = synth.sequence(m, synth.config_seed(seed))
+    assert len({int(seq[0]), int(seq[3])}) == 2, "the two residues must have different types"
+    ch = oracle.OracleChain(seq, TYPES)
+    C = _coulomb_constant()
+    k6 = 2.0 ** (1.0 / 6.0)
+    for si, sj in _TABLE_PAIRS:
+        i, j = si, 30 + sj
+        ti, tj = int(seq[0]), int(seq[3])
+        D = k6 * (TYPES.sigma[ti, si] + TYPES.sigma[tj, sj]) / 2.0
+        r = spread_positions(ch.n)
+        e = np.array([0.36, -0.48, 0.8])
+        r[j] = r[i] + D * e
+        F, Ee, Ev = oracle.pair_forces(ch, r, oracle.PairParams(cutoff=10.0))
+        depth = np.sqrt(TYPES.eps[ti, si] * TYPES.eps[tj, sj])
+        assert abs(Ev + depth) < 1e-12 * max(1.0, depth), (si, sj)
+        qi, qj = TYPES.q[ti, si], TYPES.q[tj, sj]
+        E_want = C * qi * qj / (4.0 * D * D)
+        assert abs(Ee - E_want) < 2e-6 * abs(E_want) + 1e-15, (si, sj)
+        # -dE/dd of C q q / (4 d^2) is 2E/d, repulsive for like charges; F_j
+        # points along +e (from i to j) when E > 0
+        Fj_want = (2.0 * E_want / D) * e
+        assert np.abs(F[j] - Fj_want).max() < 2e-6 * np.abs(Fj_want).max() + 1e-15, (si, sj)
+        assert np.allclose(F[i], -F[j], rtol=0, atol=1e-12 * max(1.0, np.abs(F[j]).max()))
+
+
+@pytest.mark.parametrize("g_hydro", [0.025, 0.05])
+def test_isolated_atoms_solvation_energy_from_the_type_table(g_hydro):
+    # Every atom of a chain spread 100 A apart is isolated: all its samples are
+    # exposed (f = 1), and its solvation energy is 4 pi gamma R_off^2 (eq
+    # G_cav_patch) with gamma = g_h * hydrophobicity of its residue type
+    # (reading of Table 3) and R_off = 2^(1/6) sigma / 2 + r_probe.
+    m = 3
+    seq = synth.sequence(m, synth.config_seed(2))
+    ch = oracle.OracleChain(seq, TYPES, g_hydro=g_hydro)
+    r = spread_positions(ch.n)
+    sp = oracle.SasaParams(r_probe=1.4)
+    F, f, E = oracle.sasa_forces(ch, r, sp)[:3]
+    assert np.all(f == 1.0) and not F.any()
+    want = 0.0
+    for a in range(ch.n):
+        t, s = int(seq[a // 10]), a % 10
+        R_off = 2.0 ** (1.0 / 6.0) * TYPES.sigma[t, s] / 2.0 + 1.4
+        want += 4.0 * np.pi * g_hydro * TYPES.hydro[t] * R_off ** 2
+    assert abs(E - want) < 1e-12 * max(1.0, abs(want))
+    # one atom at a time: the free-atom form gives the same per-atom value
+    a = 17
+    t, s = int(seq[a // 10]), a % 10
+    R = 2.0 ** (1.0 / 6.0) * TYPES.sigma[t, s] / 2.0
+    _, fa, Ea = oracle.sasa_atoms(r[[a]], np.array([R]), np.array([g_hydro * TYPES.hydro[t]]), sp)
+    assert fa[0] == 1.0
+    assert abs(Ea - 4.0 * np.pi * g_hydro * TYPES.hydro[t] * (R + 1.4) ** 2) < 1e-12
+
+
 def test_fk_extend_grows_the_same_chain_as_fk():
     # the residue-by-residue kinematics used to grow start conformations is the
     # same sequence of operations as the whole-chain kinematics: equal bit for bit
