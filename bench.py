@@ -1,20 +1,28 @@
 #!/usr/bin/env python3
 """Throughput of KCM iterations (atom-steps/s) on one MI355X.
 
-One step is one full KCM iteration of the chain (forward kinematics, cell
-list, Coulomb + LJ + SASA solvation forces, torques, compliance step) on the
-single 1000-residue chain (10,000 atoms) in a compact-globule start, 10 A
-cutoff, 250 samples per offset sphere (--workload globule10000: the
-10,000-residue chain, 100,000 atoms, 200 steps).  Inputs are built once and stay in
-HBM; the timed region covers exactly --steps iterations between two device
-synchronisations.  Prints one JSON line.
+Headline workload: the ragged batch of 256 chains with lengths uniform in
+[50, 600] residues (818,020 atoms), random-coil starts from per-chain seeds,
+10 A cutoff, 250 samples per offset sphere, mixed precision (FP32 pair forces
+and sample tests, FP64 kinematics, torques and step), the cell edge and the
+iterations per replayed HIP graph picked by the autotuner on the same batch
+before timing.  One step is one KCM iteration of every chain of the batch
+(forward kinematics, cell list, Coulomb + LJ + SASA solvation forces,
+torques, compliance step).  Inputs are built and every graph is captured
+before the timed region, which covers exactly --steps iterations between two
+device synchronisations.  Prints one JSON line.
+
+Sub-legs (each with its own roofline): the 1000-residue compact globule
+(10,000 atoms, 1,000 iterations) in mixed precision and in FP64, the
+10,000-residue globule (100,000 atoms, 200 iterations), the batch run for its
+500 iterations, the serving loop, energy scans and the polyalanine runs.
 
 Roofline of the dominant kernel (the force kernel): algorithmic FP work per
 launch = 40 flops per unordered pair within the cutoff + 9 flops per
 (sample, solvation neighbour) coverage test + 9 flops per (exposed sample,
-neighbour) pair for the three displaced tests, divided by the kernel's mean
-launch time from HIP events recorded on its launch stream (on every 50th
-timed iteration, so that the events barely perturb the timeline).
+neighbour) pair for the three displaced tests, summed over the chains of the
+launch, divided by the kernel's mean launch time from HIP events recorded on
+its launch stream on sampled iterations of the timed region (at least five).
 """
 from __future__ import annotations
 
@@ -29,7 +37,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_TFLOPS = {"mixed": 157.3, "fp64": 78.6}  # MI355X vector FP32 / FP64
-TIMING_EVERY = 50  # HIP events bracket the force kernel on every 50th timed iteration
+MIN_SAMPLES = 5    # HIP-event samples of the force kernel in a timed region, at least
+MAX_EVERY = 50     # and at least one every 50 timed iterations
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "force_kernel_traffic.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_1712_05012_amd", "csrc", "kcm_kernels.hip")
 
@@ -73,7 +82,35 @@ def algorithmic_units(xyz, T, seq, p, n_exposed, n_samples):
             "exposed_fraction": float(np.mean(n_exposed) / n_samples), "flops": flops}
 
 
-def run_gpu(precision: str, steps: int, warmup: int, m: int, side_chains: bool = False):
+def timing_every(steps: int) -> int:
+    """Sample interval of the HIP events over a timed region of `steps`
+    iterations: at least MIN_SAMPLES samples, and one per MAX_EVERY."""
+    return max(1, min(MAX_EVERY, steps // MIN_SAMPLES))
+
+
+def timed_steps(kcm, chains, steps, stream):
+    """Exactly `steps` iterations of `chains` between two device
+    synchronisations, with the force kernel bracketed by HIP events on sampled
+    iterations; returns (seconds, force-kernel ms per launch, iteration ms,
+    number of samples)."""
+    import torch
+
+    kcm.kcm_get_timing(reset=True)
+    kcm.kcm_set_timing(timing_every(steps))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    kcm.kcm_step(chains, steps, stream, report=False)
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t0
+    kcm.kcm_set_timing(0)
+    tm = kcm.kcm_get_timing(reset=True)
+    n = max(tm["force_launches"], 1)
+    return secs, tm["force_ms"] / n, tm["iter_ms"] / max(tm["iterations"], 1), int(tm["force_launches"])
+
+
+def run_gpu(precision: str, steps: int, warmup: int, m: int, side_chains: bool = False, depth: int = 8):
+    """A single globule chain; warm-up of at least one graph depth so that
+    every graph is captured before the timed region."""
     import numpy as np
     import torch
 
@@ -87,29 +124,22 @@ def run_gpu(precision: str, steps: int, warmup: int, m: int, side_chains: bool =
     p = kcm.kcm_default_params(precision=prec)
     chain = kcm.Chain(seq, T, p, theta0=th, side_chains=side_chains)
     stream = torch.cuda.current_stream()
-    kcm.kcm_step([chain], warmup, stream, report=False)
+    kcm.kcm_step([chain], max(warmup, 1) + depth, stream, report=False)
     torch.cuda.synchronize()
-    kcm.kcm_get_timing(reset=True)
-    kcm.kcm_set_timing(TIMING_EVERY)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    kcm.kcm_step([chain], steps, stream, report=False)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    kcm.kcm_set_timing(0)
-    tm = kcm.kcm_get_timing(reset=True)
+    secs, force_ms, iter_ms, samples = timed_steps(kcm, [chain], steps, stream)
     _, reps = kcm.kcm_step([chain], 0, stream, report=True, check=False)
     st = chain.state()
     terms = chain.atom_terms()
     units = algorithmic_units(st["xyz"], T, seq, p, terms["n_exposed"], chain.n_samples)
-    secs = t1 - t0
     out = {
         "n_atoms": chain.n_atoms,
+        "steps": steps,
         "seconds": secs,
         "ms_per_step": 1e3 * secs / steps,
         "value": chain.n_atoms * steps / secs,
-        "force_ms_mean": tm["force_ms"] / max(tm["force_launches"], 1),
-        "iter_ms_mean": tm["iter_ms"] / max(tm["iterations"], 1),
+        "force_ms_mean": force_ms,
+        "iter_ms_mean": iter_ms,
+        "force_samples": samples,
         "units": units,
         "status": reps[0].status,
         "energies": [reps[0].e_elec, reps[0].e_vdw, reps[0].e_cav],
@@ -117,6 +147,27 @@ def run_gpu(precision: str, steps: int, warmup: int, m: int, side_chains: bool =
     }
     chain.free()
     return out
+
+
+def roofline(units, force_ms, precision, traffic=None):
+    achieved = units["flops"] / (force_ms * 1e-3) / 1e12
+    peak = PEAK_TFLOPS[precision]
+    return {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+            "traffic": traffic}
+
+
+def sum_units(per_chain):
+    tot = {"pairs_within_cutoff": 0, "coverage_tests": 0, "exposed_sample_neighbour_pairs": 0, "flops": 0.0}
+    nbr = atoms = exp = 0.0
+    for u, n, ns in per_chain:
+        for k in tot:
+            tot[k] += u[k]
+        nbr += u["sasa_neighbours_mean"] * n
+        exp += u["exposed_fraction"] * n
+        atoms += n
+    tot["sasa_neighbours_mean"] = nbr / atoms
+    tot["exposed_fraction"] = exp / atoms
+    return tot
 
 
 def batch_workload(n_chains: int = 256):
@@ -132,10 +183,13 @@ def batch_workload(n_chains: int = 256):
     return T, chains
 
 
-def run_batch(steps: int, warmup: int, n_chains: int = 256, tune: bool = True, direct: bool = False):
+def run_batch(steps: int, warmup: int, n_chains: int = 256, tune: bool = True, direct: bool = False,
+              full_steps: int = 500):
     """Ragged batch in mixed precision: all chains advanced together by replayed
     HIP graphs, with the cell edge and the iterations per graph picked by the
-    autotuner on the same batch first."""
+    autotuner on the same batch first.  Times `steps` iterations (events on
+    sampled ones), then, on fresh chains, the workload's full `full_steps`
+    iterations without event samples."""
     import torch
 
     from paper_1712_05012_amd import autotune, kcm
@@ -147,22 +201,50 @@ def run_batch(steps: int, warmup: int, n_chains: int = 256, tune: bool = True, d
     depth = 0 if direct else (tuned.graph_depth if tuned else 1)
     chains = [kcm.Chain(seq, T, p, theta0=th) for seq, th in items]
     atoms = sum(c.n_atoms for c in chains)
+    n_samples = chains[0].n_samples
     kcm.kcm_set_graphs(depth)
+    full = None
     try:
-        kcm.kcm_step(chains, warmup + depth, stream, report=False)
+        # warm-up: captures the one-iteration and the depth-iteration graphs
+        kcm.kcm_step(chains, max(warmup, 1) + depth, stream, report=False)
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        kcm.kcm_step(chains, steps, stream, report=False)
-        torch.cuda.synchronize()
-        secs = time.perf_counter() - t0
+        secs, force_ms, iter_ms, samples = timed_steps(kcm, chains, steps, stream)
+        _, reps = kcm.kcm_step(chains, 0, stream, report=True, check=False)
+        bad = sum(r.status != 0 for r in reps)
+        per_chain = []
+        for c, (seq, _) in zip(chains, items):
+            st = c.state()
+            terms = c.atom_terms()
+            per_chain.append((algorithmic_units(st["xyz"], T, seq, p, terms["n_exposed"], c.n_samples),
+                              c.n_atoms, c.n_samples))
+        units = sum_units(per_chain)
+        if full_steps > 0:
+            fresh = [kcm.Chain(seq, T, p, theta0=th) for seq, th in items]
+            try:
+                kcm.kcm_step(fresh, depth + 1, stream, report=False)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                kcm.kcm_step(fresh, full_steps, stream, report=False)
+                torch.cuda.synchronize()
+                fs = time.perf_counter() - t0
+                _, freps = kcm.kcm_step(fresh, 0, stream, report=True, check=False)
+                full = {"steps": full_steps, "seconds": fs, "ms_per_step": 1e3 * fs / full_steps,
+                        "value": atoms * full_steps / fs,
+                        "failed_chains": int(sum(r.status != 0 for r in freps)),
+                        "note": "fresh chains from the same starts, depth+1 warm-up iterations, no event samples"}
+            finally:
+                for c in fresh:
+                    c.free()
     finally:
         kcm.kcm_set_graphs(0 if direct else 1)
-    _, reps = kcm.kcm_step(chains, 0, stream, report=True, check=False)
-    bad = sum(r.status != 0 for r in reps)
-    for c in chains:
-        c.free()
-    out = {"chains": len(items), "atoms": atoms, "steps": steps, "ms_per_step": 1e3 * secs / steps,
-           "value": atoms * steps / secs, "failed_chains": int(bad), "cell_size": p.cell_size, "graph_depth": depth}
+        for c in chains:
+            c.free()
+    out = {"chains": len(items), "atoms": atoms, "steps": steps, "seconds": secs, "ms_per_step": 1e3 * secs / steps,
+           "value": atoms * steps / secs, "failed_chains": int(bad), "cell_size": p.cell_size, "graph_depth": depth,
+           "force_ms_mean": force_ms, "iter_ms_mean": iter_ms, "force_samples": samples, "units": units,
+           "n_samples": n_samples}
+    if full:
+        out["full_run"] = full
     if tuned:
         out["autotune"] = tuned.as_dict()
     return out
@@ -313,47 +395,58 @@ def run_polyala(n_chains: int = 2000):
     return out
 
 
-def traffic_for(precision: str, workload_name: str = "globule1000"):
-    """HBM bytes per force launch from committed rocprofv3 counters, if still current."""
+def traffic_for(precision: str, workload_name: str):
+    """HBM bytes per force launch from committed rocprofv3 counters of this
+    workload, while the kernel source is the one they were taken on."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     try:
         rec = json.load(open(TRAFFIC_FILE))
         sha = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
-        if rec.get("workload", "globule1000") != workload_name:
+        if rec.get("kernel_sha256") != sha:
             return None
-        entry = rec.get(precision)
-        if not entry or rec.get("kernel_sha256") != sha:
-            return None
-        return float(entry["bytes_per_launch"])
+        entry = rec.get("workloads", {}).get(workload_name, {}).get(precision)
+        return float(entry["bytes_per_launch"]) if entry else None
     except Exception:
         return None
 
 
-def cpu_baseline(seconds: float, m: int):
-    """The FP64 oracle as it stands, on the host cores, over a bounded sample."""
+CPU_SUBSAMPLE = 16  # chains of the batch the oracle is timed on
+
+
+def cpu_baseline(seconds: float):
+    """The FP64 oracle as it stands, on the host cores, over a bounded sample
+    of the headline workload: whole KCM iterations of the batch's first
+    CPU_SUBSAMPLE chains, repeated (each chain from its own last angles) until
+    `seconds` have passed; the rate is the sample's atom-steps per second,
+    taken as the batch's."""
     import oracle
 
-    T, seq, th = workload(m)
-    ch = oracle.OracleChain(seq, T)
-    iters = 0
+    T, items = batch_workload(256)
+    pick = items[:CPU_SUBSAMPLE]
+    refs = [oracle.OracleChain(seq, T) for seq, _ in pick]
+    ths = [th.copy() for _, th in pick]
+    atom_steps = passes = 0
     t0 = time.perf_counter()
     while True:
-        o = oracle.iterate(ch, th)
-        th = o["theta"]
-        iters += 1
+        for k, ch in enumerate(refs):
+            ths[k] = oracle.iterate(ch, ths[k])["theta"]
+            atom_steps += ch.n
+        passes += 1
         if time.perf_counter() - t0 >= seconds:
             break
     dt = time.perf_counter() - t0
-    out = {"value": ch.n * iters / dt, "unit": "atom-steps/s", "cores": oracle.threads(), "kind": "oracle",
-           "sample": f"{iters} FP64 KCM iterations of the {m}-residue globule ({ch.n} atoms), {dt:.1f} s"}
-    single = cpu_single_core(max(2.0, seconds / 3), m)
+    n_atoms = sum(ch.n for ch in refs)
+    out = {"value": atom_steps / dt, "unit": "atom-steps/s", "cores": oracle.threads(), "kind": "oracle",
+           "sample": f"{passes} FP64 KCM iterations of each of the first {CPU_SUBSAMPLE} of the 256 batch chains "
+                     f"({n_atoms} atoms), {dt:.1f} s; the subsample's rate stands for the batch's"}
+    single = cpu_single_core(max(2.0, seconds / 3))
     if single is not None:
         out["single_core_value"] = single
     return out
 
 
-def cpu_single_core(seconds: float, m: int):
+def cpu_single_core(seconds: float):
     """The same oracle sample on one host core (a child process with one
     OpenMP thread); atom-steps/s, or None if the child fails."""
     import subprocess
@@ -362,14 +455,17 @@ def cpu_single_core(seconds: float, m: int):
         "import json, sys, time\n"
         f"sys.path.insert(0, {os.path.dirname(os.path.abspath(__file__))!r})\n"
         "import bench, oracle\n"
-        f"T, seq, th = bench.workload({int(m)})\n"
-        "ch = oracle.OracleChain(seq, T)\n"
-        "it = 0\n"
+        "T, items = bench.batch_workload(256)\n"
+        f"pick = items[:{CPU_SUBSAMPLE}]\n"
+        "refs = [oracle.OracleChain(seq, T) for seq, _ in pick]\n"
+        "ths = [th.copy() for _, th in pick]\n"
+        "n = 0\n"
         "t0 = time.perf_counter()\n"
-        f"while it == 0 or time.perf_counter() - t0 < {float(seconds)}:\n"
-        "    th = oracle.iterate(ch, th)['theta']\n"
-        "    it += 1\n"
-        "print(json.dumps({'v': ch.n * it / (time.perf_counter() - t0), 't': oracle.threads()}))\n"
+        f"while n == 0 or time.perf_counter() - t0 < {float(seconds)}:\n"
+        "    for k, ch in enumerate(refs):\n"
+        "        ths[k] = oracle.iterate(ch, ths[k])['theta']\n"
+        "        n += ch.n\n"
+        "print(json.dumps({'v': n / (time.perf_counter() - t0), 't': oracle.threads()}))\n"
     )
     env = dict(os.environ, OMP_NUM_THREADS="1")
     try:
@@ -381,42 +477,51 @@ def cpu_single_core(seconds: float, m: int):
         return None
 
 
+def globule_leg(name: str, precision: str, warmup: int, steps: int | None = None):
+    residues, _, default_steps = WORKLOADS[name]
+    r = run_gpu(precision, steps or default_steps, warmup, residues)
+    return {"workload": f"single chain, {residues} residues ({10 * residues:,} atoms), compact random globule, "
+                        f"{precision} precision", "value": r["value"], "steps": r["steps"],
+            "ms_per_step": r["ms_per_step"], "status": r["status"],
+            "kernel_ms": {"force": r["force_ms_mean"], "iteration": r["iter_ms_mean"],
+                          "chain_kernels": r["iter_ms_mean"] - r["force_ms_mean"]},
+            "force_samples": r["force_samples"], "units_per_step": r["units"],
+            "roofline": roofline(r["units"], r["force_ms_mean"], precision, traffic_for(precision, name))}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=None, help="timed iterations (default: the workload's)")
-    ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed")
-    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="globule1000",
-                    help="single-chain workload: 1,000 residues (10,000 atoms) or 10,000 residues (100,000 atoms)")
+    ap.add_argument("--steps", type=int, default=500, help="timed iterations of the batch (the workload's 500)")
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-companion", action="store_true", help="skip the other precision's measurement")
-    ap.add_argument("--batch-steps", type=int, default=100, help="iterations of the 256-chain batch (0: skip)")
+    ap.add_argument("--full-steps", type=int, default=500,
+                    help="iterations of the batch's full run on fresh chains (0: skip)")
     ap.add_argument("--serve-jobs", type=int, default=2000, help="jobs of the serving run (0: skip)")
     ap.add_argument("--serve-warmup", type=int, default=100,
                     help="earliest jobs left out of the serving latency percentiles")
     ap.add_argument("--serve-max-iter", type=int, default=2000)
-    ap.add_argument("--legs", default="main,companion,chi,batch,serving,landscape,polyala,cpu",
-                    help="comma-separated legs to run (main, companion, chi, batch, serving, landscape, "
-                         "polyala, cpu); "
-                         "profiling runs use a subset, the benchmark line needs main")
+    ap.add_argument("--legs", default="batch,globule1000,globule1000_fp64,globule10000,chi,serving,landscape,"
+                                      "polyala,cpu",
+                    help="comma-separated legs (batch is the headline; globule1000, globule1000_fp64, "
+                         "globule10000, chi, serving, landscape, polyala, cpu); profiling runs use a subset")
+    ap.add_argument("--globule-steps", type=int, default=None,
+                    help="timed iterations of the globule legs (default: the workload's, 1,000 and 200)")
     ap.add_argument("--graph-depth", type=int, default=8,
                     help="iterations per replayed HIP graph in the single-chain legs")
     ap.add_argument("--no-graphs", action="store_true",
                     help="launch each iteration's kernels directly instead of replaying a HIP graph")
+    ap.add_argument("--no-tune", action="store_true", help="batch leg with the default cell edge, one-deep graphs")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="first run a plain device copy of MIB MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build runs a chain on a single MI355X "
+        print("bench.py measures one GPU only: this build runs its chains on a single MI355X "
               "(how chains would shard over several GPUs is described in the design notes); "
               "run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
-    residues, _, default_steps = WORKLOADS[args.workload]
-    if args.steps is None:
-        args.steps = default_steps
 
     import torch
 
@@ -426,7 +531,8 @@ def main():
     torch.cuda.set_device(0)
     from paper_1712_05012_amd import kcm
 
-    kcm.kcm_set_graphs(0 if args.no_graphs else args.graph_depth)
+    depth = 0 if args.no_graphs else args.graph_depth
+    kcm.kcm_set_graphs(depth)
     if args.copy_probe > 0:
         src = torch.empty(args.copy_probe << 18, dtype=torch.float32, device="cuda").fill_(1.0)
         dst = torch.empty_like(src)
@@ -436,96 +542,80 @@ def main():
         del src, dst
 
     legs = set(args.legs.split(","))
-    if args.no_companion:
-        legs.discard("companion")
-    if args.batch_steps <= 0:
-        legs.discard("batch")
     if args.serve_jobs <= 0:
         legs.discard("serving")
     if args.no_cpu_baseline:
         legs.discard("cpu")
-    if "main" not in legs:
-        # a profiling run of the other legs only
-        line = {"legs": sorted(legs)}
-        if "batch" in legs:
-            line["batched"] = run_batch(args.batch_steps, 5, direct=args.no_graphs)
-        if "serving" in legs:
-            line["serving"] = run_serving(args.serve_jobs, args.serve_max_iter, 64.0, args.serve_warmup)
-        if "landscape" in legs:
-            line["landscape"] = run_landscape()
-        if "polyala" in legs:
-            line["polyala"] = run_polyala()
-        print(json.dumps(line), flush=True)
-        return
 
-    main_run = run_gpu(args.precision, args.steps, args.warmup, residues)
-    other = "fp64" if args.precision == "mixed" else "mixed"
-    companion = run_gpu(other, args.steps, args.warmup, residues) if "companion" in legs else None
+    def progress(msg):
+        print(f"bench: {msg}", file=sys.stderr, flush=True)
 
-    u = main_run["units"]
-    achieved = u["flops"] / (main_run["force_ms_mean"] * 1e-3) / 1e12
-    peak = PEAK_TFLOPS[args.precision]
-    line = {
-        "metric": "atom-steps/s per KCM iteration",
-        "value": main_run["value"],
-        "unit": "atom-steps/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": main_run["ms_per_step"],
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32+f64" if args.precision == "mixed" else "f64",
-        "data": "synthetic",
-        "config": {
-            "workload": f"single chain, {residues} residues ({10 * residues:,} atoms), compact random globule, "
-                        "10 A cutoff, 250 samples per offset sphere, 1 KCM iteration per step",
-            "name": args.workload,
-            "precision": args.precision,
-            "n_atoms": main_run["n_atoms"],
-            "n_samples": main_run["n_samples"],
-        },
-        "roofline": {
-            "bound": "alu",
-            "achieved": achieved,
-            "peak": peak,
-            "unit": "TFLOP/s",
-            "frac": achieved / peak,
-            "traffic": traffic_for(args.precision, args.workload),
-        },
-        "graph_depth": 0 if args.no_graphs else args.graph_depth,
-        "kernel_ms": {"force": main_run["force_ms_mean"],
-                      "iteration": main_run["iter_ms_mean"],
-                      "chain_kernels": main_run["iter_ms_mean"] - main_run["force_ms_mean"]},
-        "units_per_step": u,
-        "status": main_run["status"],
-    }
-    if companion is not None:
-        line[other] = {"value": companion["value"], "ms_per_step": companion["ms_per_step"],
-                       "force_ms": companion["force_ms_mean"],
-                       "frac": companion["units"]["flops"] / (companion["force_ms_mean"] * 1e-3) / 1e12
-                       / PEAK_TFLOPS[other]}
-    if "chi" in legs:
-        # the same workload with one side-chain joint per residue
-        ch = run_gpu(args.precision, args.steps, args.warmup, residues, side_chains=True)
-        line["side_chains"] = {"value": ch["value"], "ms_per_step": ch["ms_per_step"],
-                               "force_ms": ch["force_ms_mean"], "joints": 3 * residues,
-                               "relative_to_main": ch["value"] / main_run["value"]}
+    line = {}
     if "batch" in legs:
-        b = run_batch(args.batch_steps, 5, direct=args.no_graphs)
-        fp64 = run_per_chain_fp64(max(5, args.batch_steps // 10))
-        b["plain_fp64_per_chain"] = fp64
-        b["speedup_vs_plain_fp64_per_chain"] = b["value"] / fp64["value"]
-        line["batched"] = b
+        b = run_batch(args.steps, args.warmup, tune=not args.no_tune, direct=args.no_graphs,
+                      full_steps=args.full_steps)
+        progress(f"batch done: {b['value']:.4g} atom-steps/s")
+        u = b.pop("units")
+        line = {
+            "metric": "atom-steps/s per KCM iteration",
+            "value": b["value"],
+            "unit": "atom-steps/s",
+            "n_gpus": 1,
+            "steps": args.steps,
+            "warmup": args.warmup,
+            "ms_per_step": b["ms_per_step"],
+            "higher_is_better": True,
+            "scaling": "weak",
+            "vs_baseline": None,
+            "dtype": "f32+f64",
+            "data": "synthetic",
+            "config": {
+                "workload": f"ragged batch of {b['chains']} chains, lengths uniform in [50, 600] residues "
+                            f"({b['atoms']:,} atoms), random-coil starts, 10 A cutoff, 250 samples per offset "
+                            "sphere, mixed precision, one KCM iteration of every chain per step",
+                "name": "batch256",
+                "precision": "mixed",
+                "n_atoms": b["atoms"],
+                "n_chains": b["chains"],
+                "cell_size": b["cell_size"],
+                "graph_depth": b["graph_depth"],
+            },
+            "roofline": roofline(u, b["force_ms_mean"], "mixed", traffic_for("mixed", "batch256")),
+            "kernel_ms": {"force": b["force_ms_mean"], "iteration": b["iter_ms_mean"],
+                          "chain_kernels": b["iter_ms_mean"] - b["force_ms_mean"]},
+            "force_samples": b["force_samples"],
+            "units_per_step": u,
+            "failed_chains": b["failed_chains"],
+        }
+        if "full_run" in b:
+            line["full_run"] = b["full_run"]
+        if "autotune" in b:
+            line["autotune"] = b["autotune"]
+        fp64 = run_per_chain_fp64(10)
+        line["plain_fp64_per_chain"] = fp64
+        line["speedup_vs_plain_fp64_per_chain"] = b["value"] / fp64["value"]
+    sub = {}
+    for name, prec in (("globule1000", "mixed"), ("globule1000_fp64", "fp64"), ("globule10000", "mixed")):
+        if name in legs:
+            sub[name] = globule_leg(name.replace("_fp64", ""), prec, args.warmup, args.globule_steps)
+            progress(f"{name} done: {sub[name]['value']:.4g} atom-steps/s")
+    if "chi" in legs:
+        # the 1000-residue globule with one side-chain joint per residue
+        residues, _, st = WORKLOADS["globule1000"]
+        ch = run_gpu("mixed", args.globule_steps or st, args.warmup, residues, side_chains=True)
+        sub["globule1000_side_chains"] = {"value": ch["value"], "ms_per_step": ch["ms_per_step"],
+                                          "force_ms": ch["force_ms_mean"], "joints": 3 * residues}
+    if sub:
+        line["legs"] = sub
     if "serving" in legs:
         line["serving"] = run_serving(args.serve_jobs, args.serve_max_iter, 64.0, args.serve_warmup)
+        progress("serving done")
     if "landscape" in legs:
         line["landscape"] = run_landscape()
     if "polyala" in legs:
         line["polyala"] = run_polyala()
     if "cpu" in legs:
-        line["cpu_baseline"] = cpu_baseline(args.cpu_seconds, residues)
+        line["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
     print(json.dumps(line), flush=True)
 
 

@@ -163,7 +163,12 @@ kcm_status kcm_step(kcm_chain *const *chains, int n_chains, int n_iter, void *hi
 
 /* Iterate every chain until max|dtheta| < tol_dtheta or max_iter iterations
  * (Fig. 5 step 9); convergence is polled every check_every iterations (>= 1).
- * Synchronises hip_stream.  results[n_chains] may be NULL. */
+ * For the call, tol_dtheta and max_iter replace each chain's own stopping
+ * rule (kcm_set_limits); the call puts that rule back at its end, so a chain
+ * that has reached its own iteration cap stays stopped afterwards.
+ * Synchronises hip_stream.  results[n_chains] may be NULL.  Errors:
+ * KCM_E_INVAL (max_iter < 0, check_every < 1, or the chain-set errors of
+ * kcm_step), KCM_E_DEVICE; otherwise the first failing chain's status. */
 kcm_status kcm_fold(kcm_chain *const *chains, int n_chains, double tol_dtheta, int max_iter,
                     int check_every, void *hip_stream, kcm_fold_result *results);
 
@@ -222,7 +227,10 @@ kcm_status kcm_get_atom_terms(const kcm_chain *chain, void *hip_stream, double *
  * max_iterations iterations since it was built (<= 0: no cap), the chain is
  * marked converged / finished and later launches skip it.  Its reports then
  * carry converged = 1 or iterations == max_iterations.  Used by serving loops
- * that advance many chains with one call (Fig. 5 step 9, per chain). */
+ * that advance many chains with one call (Fig. 5 step 9, per chain).  A
+ * kcm_fold call suspends the rule for its duration and restores it;
+ * kcm_mc_minimize clears it.  Synchronises hip_stream.  Errors: KCM_E_INVAL
+ * (null chain, tol_dtheta not finite), KCM_E_DEVICE. */
 kcm_status kcm_set_limits(kcm_chain *chain, double tol_dtheta, int64_t max_iterations, void *hip_stream);
 
 /* Replace a chain's theta (host array [J]), e.g. to resume from a checkpoint

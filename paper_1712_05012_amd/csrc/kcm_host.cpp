@@ -19,13 +19,16 @@ using namespace kcm;
 
 namespace {
 
-thread_local std::string g_err;
+// the calling thread's last error message, in a fixed buffer (setting it
+// allocates nothing)
+thread_local char g_err[512];
 
-kcm_status fail(kcm_status s, const std::string &msg)
+kcm_status fail(kcm_status s, const char *msg)
 {
-    g_err = msg;
+    std::snprintf(g_err, sizeof(g_err), "%s", msg);
     return s;
 }
+kcm_status fail(kcm_status s, const std::string &msg) { return fail(s, msg.c_str()); }
 
 #define HIP_TRY(expr)                                                                         \
     do {                                                                                      \
@@ -588,7 +591,7 @@ void kcm_default_params(kcm_params *p)
     p->cell_size = 0.0;
 }
 
-const char *kcm_last_error(void) { return g_err.c_str(); }
+const char *kcm_last_error(void) { return g_err; }
 
 kcm_status kcm_chain_bytes(const kcm_chain_desc *desc, const kcm_params *params, size_t *bytes)
 {
@@ -894,7 +897,7 @@ kcm_status kcm_step(kcm_chain *const *chains, int n_chains, int n_iter, void *hi
         r.converged = st[i].converged;
         if (st[i].status != 0 && worst == KCM_OK) worst = (kcm_status)st[i].status;
     }
-    if (worst != KCM_OK) g_err = "a chain reported a failure status";
+    if (worst != KCM_OK) fail(worst, "a chain reported a failure status");
     return worst;
 }
 
@@ -994,7 +997,7 @@ kcm_status kcm_mc_minimize(kcm_chain *const *chains, int32_t n_chains, int32_t n
         }
         if (st[i].status != 0 && worst == KCM_OK) worst = (kcm_status)st[i].status;
     }
-    if (worst != KCM_OK) g_err = "a chain reported a failure status";
+    if (worst != KCM_OK) fail(worst, "a chain reported a failure status");
     return worst;
 }
 

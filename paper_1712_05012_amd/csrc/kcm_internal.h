@@ -25,6 +25,8 @@ struct ChainStats {
     double tol;                    // convergence threshold on max|dtheta| (<= 0: none)
     int64_t iterations;            // iterations applied since the chain was built
     int64_t iter_limit;            // stop when iterations reaches this (kcm_fold)
+    double saved_tol;              // tol and iter_limit of before a kcm_fold call, restored at its end
+    int64_t saved_limit;
     int32_t status;                // 0 ok, -4 numeric, -6 neighbour capacity
     int32_t converged;
     int32_t active;                // 0: the chain is stopped (converged, limit or failure)

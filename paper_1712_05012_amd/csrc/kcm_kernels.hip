@@ -712,10 +712,11 @@ __global__ void k_stats_gather(Batch bt, ChainStats *__restrict__ out)
     out[c] = *bt.table[c]->stats;
 }
 
-// k_fold_control: FOLD_BEGIN arms every chain for a fold of at most max_iter
+// k_fold_control: FOLD_BEGIN keeps the chain's own stopping rule
+// (kcm_set_limits) aside and arms every chain for a fold of at most max_iter
 // iterations that stops below tol (a chain with a failure status stays
-// stopped); FOLD_END leaves every chain steppable again unless it converged
-// or failed.
+// stopped); FOLD_END puts the chain's own rule back and leaves every chain
+// steppable again unless it converged, failed or reached its own limit.
 __global__ void k_fold_control(Batch bt, int mode, double tol, int64_t max_iter)
 {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
@@ -723,15 +724,17 @@ __global__ void k_fold_control(Batch bt, int mode, double tol, int64_t max_iter)
     ChainStats *st = bt.table[c]->stats;
     if (mode == FOLD_BEGIN) {
         const int go = st->status == 0 && max_iter > 0 ? 1 : 0;
+        st->saved_tol = st->tol;
+        st->saved_limit = st->iter_limit;
         st->tol = tol;
         st->iter_limit = st->iterations + max_iter;
         st->converged = 0;
         st->active = go;
         st->run = go;
     } else {
-        const int again = st->status == 0 && !st->converged ? 1 : 0;
-        st->tol = 0.0;
-        st->iter_limit = INT64_MAX;
+        st->tol = st->saved_tol;
+        st->iter_limit = st->saved_limit;
+        const int again = st->status == 0 && !st->converged && st->iterations < st->iter_limit ? 1 : 0;
         st->active = again;
         st->run = again;
     }

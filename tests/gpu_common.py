@@ -14,6 +14,14 @@ TYPES = synth.residue_types()
 # largest force, and per-step joint-angle error in each precision form.
 F_TOL = 1e-5
 DTHETA_TOL = {kcm.KCM_FP64: 1e-7, kcm.KCM_MIXED: 1e-5}
+# Joint torques, relative to the largest one: FP64 sums of FP64 forces differ
+# from the oracle's by rounding order only; the mixed form's FP32 pair forces
+# carry a relative error of about 1e-6 each, summed in FP64 along the chain.
+TAU_TOL = {kcm.KCM_FP64: 1e-9, kcm.KCM_MIXED: 1e-5}
+# Solvation forces are sums of integer event counts times a per-atom quantum
+# held in 2^-32 fixed point: equal decisions leave a rounding of at most 2^-33
+# per event, far below this bound for any atom of the tested chains.
+F_CAV_ABS = 1e-8
 
 
 def params(precision=kcm.KCM_FP64, **kw):

@@ -1,0 +1,115 @@
+"""Parity of the ragged batch in its benchmarked launch form: 256 random-coil
+chains of 50-600 residues (the batched workload's generator, per-chain seeds)
+plus one chain whose densest atom has more solvation neighbours than the
+force kernel's LDS list holds, all in one mixed-precision call with a 3.6 A
+cell edge and eight iterations per replayed HIP graph.  Sixteen chains spread
+over the batch (the first, the last, the long chain and others between) are
+compared element by element with the FP64 oracle, per step from shared
+angles: at the start and after eight graph-replayed iterations (needs an
+MI355X)."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle  # noqa: E402
+import synth  # noqa: E402
+from gpu_common import DTHETA_TOL, F_CAV_ABS, F_TOL, TAU_TOL, TYPES, oracle_step, params  # noqa: E402
+from paper_1712_05012_amd import kcm  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+N_BATCH = 256
+CHECKED = [0, 1, 2, 3, 64, 65, 127, 128, 129, 190, 191, 252, 253, 254, 255, 256]
+# job 1792 of the serving stream (304 residues): one atom has 418 solvation
+# neighbours at the start, more than one LDS list of 384
+OVERFLOW_M = 304
+OVERFLOW_SEED = synth.config_seed(5) + 1000 * (1792 + 1)
+
+
+def _log(**kw):
+    print(" ".join(f"{k}={v}" for k, v in kw.items()), flush=True)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    kcm.load_library()
+
+
+def _items():
+    lens = synth.batch_lengths(N_BATCH, synth.config_seed(3))
+    out = []
+    for b, m in enumerate(lens):
+        seed = synth.config_seed(3, b)
+        out.append((synth.sequence(int(m), seed), synth.random_dihedrals(int(m), seed)))
+    out.append((synth.sequence(OVERFLOW_M, OVERFLOW_SEED), synth.random_dihedrals(OVERFLOW_M, OVERFLOW_SEED)))
+    return out
+
+
+def _wrap(x):
+    return np.abs(np.angle(np.exp(1j * x)))
+
+
+def _check(label, chains, refs, starts, reps, p):
+    ties = 0
+    for k in CHECKED:
+        c, ref, th = chains[k], refs[k], starts[k]
+        st = c.state()
+        fp, fc = c.forces()
+        o = oracle_step(ref, th, p)
+        fmax = max(np.abs(o["F"]).max(), 1e-300)
+        err = {
+            "xyz": float(np.abs(st["xyz"] - o["r"]).max()),
+            "F": float(np.abs(st["force"] - o["F"]).max() / fmax),
+            "F_cav_abs": float(np.abs(fc - o["F_cav"]).max()),
+            "tau": float(np.abs(st["tau"] - o["tau"]).max() / max(np.abs(o["tau"]).max(), 1e-300)),
+            "dtheta": float(np.abs(st["dtheta"] - o["dtheta"]).max()),
+            "theta": float(_wrap(st["theta"] - o["theta"]).max()),
+            "E_cav": abs(reps[k].e_cav - o["E_cav"]) / max(abs(o["E_cav"]), 1.0),
+            "margin": o["margin"],
+        }
+        _log(case="batch", at=label, chain=k, atoms=c.n_atoms, **err)
+        assert reps[k].status == 0, k
+        assert err["xyz"] < 1e-9, k
+        assert err["F"] <= F_TOL, k
+        assert err["tau"] <= TAU_TOL[kcm.KCM_MIXED], k
+        assert err["dtheta"] <= DTHETA_TOL[kcm.KCM_MIXED] and err["theta"] <= DTHETA_TOL[kcm.KCM_MIXED], k
+        if err["margin"] > 1e-10:
+            assert err["E_cav"] < 1e-12, k
+            assert err["F_cav_abs"] < F_CAV_ABS, k
+        else:
+            ties += 1
+    assert ties <= 2
+
+
+def test_batch_of_random_coils_in_its_launch_form_matches_oracle():
+    items = _items()
+    p = params(kcm.KCM_MIXED, cell_size=3.6)
+    refs = {k: oracle.OracleChain(items[k][0], TYPES, g_hydro=p.g_hydro) for k in CHECKED}
+    # the long chain's densest atom overflows one LDS list
+    r0 = oracle.fk(refs[N_BATCH], items[N_BATCH][1])[0]
+    roff = refs[N_BATCH].R + p.r_probe
+    d = np.sqrt(((r0[:, None, :] - r0[None, :, :]) ** 2).sum(-1))
+    np.fill_diagonal(d, np.inf)
+    assert int((d <= roff[:, None] + roff[None, :] + p.delta_r).sum(axis=1).max()) > 384
+    chains = []
+    try:
+        kcm.kcm_set_graphs(8)
+        chains = [kcm.Chain(seq, TYPES, p, theta0=th) for seq, th in items]
+        starts = {k: items[k][1] for k in CHECKED}
+        _, reps = kcm.kcm_step(chains, 1)
+        assert chains[0].cells()["cell"] >= 3.6 - 1e-9
+        _check("start", chains, refs, starts, reps, p)
+        # eight iterations replayed as one captured graph, then one more
+        # iteration from the reached angles
+        st, _ = kcm.kcm_step(chains, 8, report=True, check=False)
+        assert st == kcm.KCM_OK
+        starts = {k: chains[k].state()["theta"] for k in CHECKED}
+        _, reps = kcm.kcm_step(chains, 1)
+        _check("after8", chains, refs, starts, reps, p)
+    finally:
+        kcm.kcm_set_graphs(1)
+        for c in chains:
+            c.free()

@@ -8,7 +8,8 @@ torch = pytest.importorskip("torch")
 
 import oracle  # noqa: E402
 import synth  # noqa: E402
-from gpu_common import DTHETA_TOL, F_TOL, TYPES, build_pair, compare_step, oracle_params, oracle_step, params  # noqa: E402
+from gpu_common import (DTHETA_TOL, F_CAV_ABS, F_TOL, TAU_TOL, TYPES, build_pair, compare_step,  # noqa: E402
+                        oracle_params, oracle_step, params)
 from paper_1712_05012_amd import kcm  # noqa: E402
 
 pytestmark = pytest.mark.gpu
@@ -41,6 +42,7 @@ def test_one_iteration_matches_oracle(precision, m, seed):
     assert err["F"] <= F_TOL and err["F_pair"] <= F_TOL and err["F_cav"] <= F_TOL
     assert err["dtheta"] <= DTHETA_TOL[precision]
     assert err["theta"] <= DTHETA_TOL[precision]
+    assert err["tau"] <= TAU_TOL[precision]
     tol_e = 1e-9 if precision == kcm.KCM_FP64 else 1e-5
     assert err["E_elec"] < tol_e and err["E_vdw"] < tol_e
     assert err["E_cav"] < 1e-12  # integer exposure counts: exact
@@ -256,6 +258,8 @@ def test_large_open_chain_matches_oracle():
     _log(case="large_chain", **err)
     assert err["margin"] > 1e-10
     assert err["F"] <= F_TOL and err["dtheta"] <= DTHETA_TOL[kcm.KCM_MIXED]
+    assert err["tau"] <= TAU_TOL[kcm.KCM_MIXED]
+    assert np.abs(gpu.forces()[1] - o["F_cav"]).max() < F_CAV_ABS
     gpu.free()
 
 
@@ -368,14 +372,57 @@ def test_numeric_failure_is_isolated():
 
 
 def test_fold_converges_and_reports():
-    p = params(kcm.KCM_MIXED)
-    gpu, ref, th = build_pair(8, 131, p)
-    st, res = kcm.kcm_fold([gpu], tol=1e-4, max_iter=3000, check_every=50)
-    _log(case="fold", iterations=res[0].iterations, converged=res[0].converged)
-    assert res[0].iterations > 0
-    if res[0].converged:
-        assert gpu.step(1).max_dtheta < 1e-4 * 1.5 or True
+    # a perturbed 8-residue alanine-like helix in vacuum, mixed precision: the
+    # oracle's loop stops below 1e-3 rad after 112 iterations; kcm_fold must
+    # report convergence at (or, with FP32 pair forces, within two iterations
+    # of) the same iteration, with its last step below the tolerance
+    T = synth.alanine_like_types()
+    m, cap, tol = 8, 400, 1e-3
+    p = params(kcm.KCM_MIXED, max_step=1e-2, terms=kcm.KCM_TERM_ELEC | kcm.KCM_TERM_VDW)
+    th = np.radians(np.tile([-68.0, -39.0], m)) + 0.05 * np.random.default_rng(1).standard_normal(2 * m)
+    ref = oracle.OracleChain(np.zeros(m, np.int32), T)
+    t, it = th.copy(), 0
+    while it < cap:
+        o = oracle.iterate(ref, t, terms="elec+vdw", kappa=p.kappa, s=p.max_step)
+        t, it = o["theta"], it + 1
+        if np.abs(o["dtheta"]).max() < tol:
+            break
+    assert it < cap, "the oracle run must converge for this test"
+    gpu = kcm.Chain(np.zeros(m, np.int32), T, p, theta0=th)
+    st, res = kcm.kcm_fold([gpu], tol=tol, max_iter=cap, check_every=9)
+    _, (rep,) = kcm.kcm_step([gpu], 0)
+    _log(case="fold", iterations=res[0].iterations, oracle_iterations=it, converged=res[0].converged,
+         last_dtheta=rep.max_dtheta)
+    assert st == kcm.KCM_OK and res[0].status == 0
+    assert res[0].converged == 1 and rep.converged == 1
+    assert rep.max_dtheta < tol
+    assert abs(res[0].iterations - it) <= 2
+    # a converged chain is skipped by later calls
+    _, (rep2,) = kcm.kcm_step([gpu], 5)
+    assert rep2.iterations == rep.iterations
     gpu.free()
+
+
+def test_fold_keeps_the_chains_own_limits():
+    # kcm_set_limits, then kcm_fold (whose own tolerance and cap apply during
+    # the call), then kcm_step: the chain's own cap of 30 iterations holds
+    # again after the fold
+    p = params(kcm.KCM_MIXED)
+    gpu = build_pair(6, 171, p)[0]
+    kcm.kcm_set_limits(gpu.handle, 0.0, 30)
+    st, res = kcm.kcm_fold([gpu], tol=1e-30, max_iter=10, check_every=5)
+    assert res[0].iterations == 10 and not res[0].converged
+    _, (rep,) = kcm.kcm_step([gpu], 100)
+    assert rep.status == 0 and rep.iterations == 30
+    # a fold longer than the chain's own cap runs its own count
+    gpu2 = build_pair(6, 172, p)[0]
+    kcm.kcm_set_limits(gpu2.handle, 0.0, 5)
+    st, res = kcm.kcm_fold([gpu2], tol=1e-30, max_iter=12, check_every=4)
+    assert res[0].iterations == 12
+    _, (rep,) = kcm.kcm_step([gpu2], 3)
+    assert rep.iterations == 12  # past its own cap: stays stopped
+    gpu.free()
+    gpu2.free()
 
 
 @pytest.mark.parametrize("depth", [1, 4])
@@ -546,8 +593,12 @@ def test_benchmark_workload_in_its_launch_configuration(precision):
             assert err["xyz"] < 1e-9
             assert err["F"] <= F_TOL and err["F_pair"] <= F_TOL and err["F_cav"] <= F_TOL
             assert err["dtheta"] <= DTHETA_TOL[precision]
+            assert err["tau"] <= TAU_TOL[precision]
             if err["margin"] > 1e-10:
+                # equal sample decisions: the solvation force to the event
+                # quantum's rounding, per atom and in absolute terms
                 assert err["E_cav"] < 1e-12
+                assert np.abs(gpu.forces()[1] - o["F_cav"]).max() < F_CAV_ABS
         gpu.free()
     finally:
         kcm.kcm_set_graphs(1)

@@ -7,7 +7,7 @@ import pytest
 
 torch = pytest.importorskip("torch")
 
-from gpu_common import DTHETA_TOL, F_TOL, build_pair, compare_step, params  # noqa: E402
+from gpu_common import DTHETA_TOL, F_TOL, TAU_TOL, build_pair, compare_step, params  # noqa: E402
 from paper_1712_05012_amd import kcm  # noqa: E402
 
 pytestmark = pytest.mark.gpu
@@ -65,6 +65,7 @@ def test_randomised_option_sweep():
         assert err["xyz"] < 1e-9
         assert err["F"] <= F_TOL and err["F_pair"] <= F_TOL and err["F_cav"] <= F_TOL
         assert err["dtheta"] <= DTHETA_TOL[c["precision"]] and err["theta"] <= DTHETA_TOL[c["precision"]]
+        assert err["tau"] <= TAU_TOL[c["precision"]]
         if c["terms"] & kcm.KCM_TERM_CAV:
             assert err["E_cav"] < 1e-12
         if mask is not None:
