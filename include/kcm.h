@@ -161,6 +161,30 @@ kcm_status kcm_build_chain(const kcm_chain_desc *desc, const kcm_params *params,
 kcm_status kcm_step(kcm_chain *const *chains, int n_chains, int n_iter, void *hip_stream,
                     kcm_step_report *reports);
 
+/* kcm_step for callers that cannot allocate memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation.  Same
+ * iterations, results (bit for bit) and reports as kcm_step, with these
+ * differences:
+ *  * the call allocates nothing, on the device or the host: the batch table
+ *    and the gathered report records live in a file-scope device array of
+ *    the library (at most KCM_NOALLOC_SCRATCH_BYTES per device, held until
+ *    the process ends);
+ *  * at most KCM_NOALLOC_MAX_CHAINS chains per call (more: KCM_E_INVAL);
+ *  * kernels are launched directly (no HIP graphs; kcm_set_graphs and
+ *    kcm_set_timing do not apply);
+ *  * every call on one device shares that device's array.  The library
+ *    orders its own calls: a call with a different chain set, or from another
+ *    stream, first waits for the previous call's stream.  Work that the
+ *    caller queues around the calls and that depends on their order is the
+ *    caller's to order; calls from different processes use different arrays.
+ * If reports != NULL the call synchronises hip_stream and fills
+ * reports[n_chains].  Errors: those of kcm_step, KCM_E_INVAL for more than
+ * KCM_NOALLOC_MAX_CHAINS chains or a device index above 63. */
+#define KCM_NOALLOC_MAX_CHAINS 1024
+#define KCM_NOALLOC_SCRATCH_BYTES 262144
+kcm_status kcm_step_noalloc(kcm_chain *const *chains, int n_chains, int n_iter, void *hip_stream,
+                            kcm_step_report *reports);
+
 /* Iterate every chain until max|dtheta| < tol_dtheta or max_iter iterations
  * (Fig. 5 step 9); convergence is polled every check_every iterations (>= 1).
  * For the call, tol_dtheta and max_iter replace each chain's own stopping

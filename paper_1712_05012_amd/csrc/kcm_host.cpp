@@ -901,6 +901,195 @@ kcm_status kcm_step(kcm_chain *const *chains, int n_chains, int n_iter, void *hi
     return worst;
 }
 
+// ---------------------------------------------------------------------------
+// kcm_step_noalloc: kcm_step with the batch table and the report records in a
+// file-scope device array instead of memory the library allocates
+// ---------------------------------------------------------------------------
+}  // extern "C"
+
+namespace {
+
+constexpr size_t kNoallocAlign = 256;
+constexpr size_t noalloc_round(size_t x) { return (x + kNoallocAlign - 1) & ~(kNoallocAlign - 1); }
+constexpr int kNoallocChains = KCM_NOALLOC_MAX_CHAINS;
+constexpr size_t kNaTab = noalloc_round(sizeof(ChainDev *) * kNoallocChains);  // chain descriptors
+constexpr size_t kNaOff = noalloc_round(sizeof(int32_t) * (kNoallocChains + 1));  // one offset array
+constexpr size_t kNaTable = kNaTab + 4 * kNaOff;  // descriptors, atom / block / joint-block / chunk offsets
+constexpr size_t kNaStats = noalloc_round(sizeof(ChainStats) * kNoallocChains);
+constexpr size_t kNoallocBytes = kNaTable + kNaStats;
+static_assert(kNoallocBytes <= KCM_NOALLOC_SCRATCH_BYTES, "scratch size stated in kcm.h");
+constexpr int kNoallocDevices = 64;
+
+// The table and the gathered records of the last kcm_step_noalloc call on
+// each device.  In host code `scratch` names a host-side stand-in: the
+// device address of each device's copy comes from hipGetSymbolAddress.
+static __device__ __align__(256) unsigned char scratch[kNoallocBytes];
+
+struct NoallocDevice {
+    unsigned char *ptr = nullptr;        // this device's copy of scratch
+    hipStream_t last = nullptr;          // stream of the last call that wrote the table
+    bool used = false;
+    int n_chains = 0;                    // the chain set the table holds
+    const kcm_chain *chains[kNoallocChains];
+    Batch batch{};
+};
+NoallocDevice g_noalloc[kNoallocDevices];
+// host images, reused by every call (the calls are serialised by g_mu)
+unsigned char g_noalloc_table[kNaTable];
+ChainStats g_noalloc_stats[kNoallocChains];
+const kcm_chain *g_noalloc_sorted[kNoallocChains];
+
+// The device address of this device's scratch, looked up once per device.
+kcm_status noalloc_device(int dev, NoallocDevice **out)
+{
+    if (dev < 0 || dev >= kNoallocDevices) return fail(KCM_E_INVAL, "kcm_step_noalloc: device index above 63");
+    NoallocDevice &d = g_noalloc[dev];
+    if (!d.ptr) {
+        void *p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) return fail(KCM_E_DEVICE, "kcm_step_noalloc: hipGetSymbolAddress of the scratch array failed");
+        d.ptr = static_cast<unsigned char *>(p);
+    }
+    *out = &d;
+    return KCM_OK;
+}
+
+// The batch table of `chains` in the device's scratch (rewritten only when
+// the chain set differs from the last call's).
+kcm_status noalloc_table(NoallocDevice &d, kcm_chain *const *chains, int n_chains, hipStream_t stream)
+{
+    bool same = d.used && d.n_chains == n_chains;
+    for (int i = 0; same && i < n_chains; ++i) same = d.chains[i] == chains[i];
+    if (same) return KCM_OK;
+    // the previous call's kernels, and its copy of the host image, are done
+    // before either is overwritten
+    if (d.used) {
+        hipError_t e = hipStreamSynchronize(d.last);
+        if (e != hipSuccess) return fail(KCM_E_DEVICE, "kcm_step_noalloc: synchronising the previous call failed");
+    }
+    ChainDev **tab = reinterpret_cast<ChainDev **>(g_noalloc_table);
+    int32_t *off = reinterpret_cast<int32_t *>(g_noalloc_table + kNaTab);
+    int32_t *blk = reinterpret_cast<int32_t *>(g_noalloc_table + kNaTab + kNaOff);
+    int32_t *jblk = reinterpret_cast<int32_t *>(g_noalloc_table + kNaTab + 2 * kNaOff);
+    int32_t *sblk = reinterpret_cast<int32_t *>(g_noalloc_table + kNaTab + 3 * kNaOff);
+    long long total = 0, blocks = 0, jblocks = 0, sblocks = 0;
+    int max_chunks = 1;
+    for (int i = 0; i < n_chains; ++i) {
+        tab[i] = chains[i]->d_desc;
+        off[i] = (int32_t)total;
+        blk[i] = (int32_t)blocks;
+        jblk[i] = (int32_t)jblocks;
+        sblk[i] = (int32_t)sblocks;
+        total += chains[i]->n;
+        blocks += (chains[i]->n + ATOM_BLOCK - 1) / ATOM_BLOCK;
+        jblocks += chains[i]->njb;
+        const int chunks = (chains[i]->h.cap_cells + SCAN_CHUNK - 1) / SCAN_CHUNK;
+        sblocks += chunks;
+        max_chunks = std::max(max_chunks, chunks);
+    }
+    if (total > std::numeric_limits<int32_t>::max() || sblocks > std::numeric_limits<int32_t>::max())
+        return fail(KCM_E_INVAL, "too many atoms in one call");
+    off[n_chains] = (int32_t)total;
+    blk[n_chains] = (int32_t)blocks;
+    jblk[n_chains] = (int32_t)jblocks;
+    sblk[n_chains] = (int32_t)sblocks;
+    d.used = false;  // until the copy below is queued
+    hipError_t e = hipMemcpyAsync(d.ptr, g_noalloc_table, kNaTable, hipMemcpyHostToDevice, stream);
+    if (e != hipSuccess) return fail(KCM_E_DEVICE, "kcm_step_noalloc: copy of the batch table failed");
+    Batch &b = d.batch;
+    b.table = reinterpret_cast<ChainDev *const *>(d.ptr);
+    b.atom_off = reinterpret_cast<const int32_t *>(d.ptr + kNaTab);
+    b.blk_off = reinterpret_cast<const int32_t *>(d.ptr + kNaTab + kNaOff);
+    b.jblk_off = reinterpret_cast<const int32_t *>(d.ptr + kNaTab + 2 * kNaOff);
+    b.scan_off = reinterpret_cast<const int32_t *>(d.ptr + kNaTab + 3 * kNaOff);
+    b.n_chains = n_chains;
+    b.total_atoms = (int)total;
+    b.total_blocks = (int)blocks;
+    b.total_jblocks = (int)jblocks;
+    b.total_scan_blocks = (int)sblocks;
+    b.max_scan_chunks = max_chunks;
+    for (int i = 0; i < n_chains; ++i) d.chains[i] = chains[i];
+    d.n_chains = n_chains;
+    d.used = true;
+    d.last = stream;
+    return KCM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+kcm_status kcm_step_noalloc(kcm_chain *const *chains, int n_chains, int n_iter, void *hip_stream,
+                            kcm_step_report *reports)
+{
+    if (n_iter < 0) return fail(KCM_E_INVAL, "n_iter < 0");
+    if (!chains || n_chains < 1) return fail(KCM_E_INVAL, "no chains");
+    if (n_chains > KCM_NOALLOC_MAX_CHAINS)
+        return fail(KCM_E_INVAL, "kcm_step_noalloc takes at most KCM_NOALLOC_MAX_CHAINS (1024) chains");
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return fail(KCM_E_DEVICE, "hipGetDevice failed");
+    for (int i = 0; i < n_chains; ++i) {
+        if (!chains[i]) return fail(KCM_E_INVAL, "null chain handle");
+        if (chains[i]->device != dev) return fail(KCM_E_INVAL, "chain lives on another device");
+        if (chains[i]->h.precision != chains[0]->h.precision)
+            return fail(KCM_E_INVAL, "chains of one call must share precision");
+    }
+    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    std::lock_guard<std::mutex> lock(g_mu);
+    std::copy(chains, chains + n_chains, g_noalloc_sorted);
+    std::sort(g_noalloc_sorted, g_noalloc_sorted + n_chains);
+    if (std::adjacent_find(g_noalloc_sorted, g_noalloc_sorted + n_chains) != g_noalloc_sorted + n_chains)
+        return fail(KCM_E_INVAL, "a chain appears twice in one call");
+    const int prec = chains[0]->h.precision;
+    NoallocDevice *d = nullptr;
+    kcm_status s = noalloc_device(dev, &d);
+    if (s != KCM_OK) return s;
+    if ((s = noalloc_table(*d, chains, n_chains, stream)) != KCM_OK) return s;
+    if (d->last != stream) {
+        // same chain set from another stream: the table stays, ordered after
+        // the last writer's work
+        hipError_t e = hipStreamSynchronize(d->last);
+        if (e != hipSuccess) return fail(KCM_E_DEVICE, "kcm_step_noalloc: synchronising the previous call failed");
+        d->last = stream;
+    }
+    const Batch &bt = d->batch;
+    hipError_t e = hipSuccess;
+    if (n_iter > 0) {
+        bool boot = false;
+        for (int i = 0; i < n_chains; ++i) boot = boot || chains[i]->boot;
+        if (boot) {
+            if ((e = launch_boot(bt, stream)) != hipSuccess) return fail(KCM_E_DEVICE, "kcm_step_noalloc: launch failed");
+            for (int i = 0; i < n_chains; ++i) chains[i]->boot = false;
+        }
+        for (int it = 0; it < n_iter && e == hipSuccess; ++it) e = launch_iteration(bt, prec, stream);
+        if (e == hipSuccess) e = launch_final(bt, stream);
+        if (e != hipSuccess) return fail(KCM_E_DEVICE, "kcm_step_noalloc: launch failed");
+    }
+    if (!reports) return KCM_OK;
+    ChainStats *dst = reinterpret_cast<ChainStats *>(d->ptr + kNaTable);
+    if ((e = launch_stats_gather(bt, dst, stream)) != hipSuccess ||
+        (e = hipMemcpyAsync(g_noalloc_stats, dst, sizeof(ChainStats) * n_chains, hipMemcpyDeviceToHost, stream)) !=
+            hipSuccess ||
+        (e = hipStreamSynchronize(stream)) != hipSuccess)
+        return fail(KCM_E_DEVICE, "kcm_step_noalloc: reading the chains' records failed");
+    kcm_status worst = KCM_OK;
+    for (int i = 0; i < n_chains; ++i) {
+        const ChainStats &c = g_noalloc_stats[i];
+        kcm_step_report &r = reports[i];
+        r.e_elec = c.e_elec;
+        r.e_vdw = c.e_vdw;
+        r.e_cav = c.e_cav;
+        r.max_tau = c.max_tau;
+        r.max_dtheta = c.max_dtheta;
+        r.iterations = c.iterations;
+        r.status = c.status;
+        r.converged = c.converged;
+        if (c.status != 0 && worst == KCM_OK) worst = (kcm_status)c.status;
+    }
+    if (worst != KCM_OK) fail(worst, "a chain reported a failure status");
+    return worst;
+}
+
 kcm_status kcm_fold(kcm_chain *const *chains, int n_chains, double tol_dtheta, int max_iter, int check_every,
                     void *hip_stream, kcm_fold_result *results)
 {

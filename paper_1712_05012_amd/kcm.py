@@ -24,7 +24,9 @@ KCM_TERM_ELEC, KCM_TERM_VDW, KCM_TERM_CAV, KCM_TERM_ALL = 1, 2, 4, 7
 EXPORTED = ("kcm_default_params", "kcm_chain_bytes", "kcm_build_chain", "kcm_step", "kcm_fold",
             "kcm_get_state", "kcm_get_forces", "kcm_set_theta", "kcm_get_cells", "kcm_chain_info",
             "kcm_set_timing", "kcm_get_timing", "kcm_chain_free", "kcm_last_error", "kcm_get_atom_terms",
-            "kcm_set_limits", "kcm_set_graphs", "kcm_mc_minimize", "kcm_mc_best_theta", "kcm_set_theta_batch")
+            "kcm_set_limits", "kcm_set_graphs", "kcm_mc_minimize", "kcm_mc_best_theta", "kcm_set_theta_batch",
+            "kcm_step_noalloc")
+KCM_NOALLOC_MAX_CHAINS = 1024
 
 
 class KcmError(RuntimeError):
@@ -84,6 +86,7 @@ def load_library(path: str = LIB_PATH):
     lib.kcm_build_chain.argtypes = [C.POINTER(kcm_chain_desc), C.POINTER(kcm_params), vp, C.c_size_t, vp,
                                     C.POINTER(vp)]
     lib.kcm_step.argtypes = [C.POINTER(vp), C.c_int, C.c_int, vp, C.POINTER(kcm_step_report)]
+    lib.kcm_step_noalloc.argtypes = [C.POINTER(vp), C.c_int, C.c_int, vp, C.POINTER(kcm_step_report)]
     lib.kcm_fold.argtypes = [C.POINTER(vp), C.c_int, C.c_double, C.c_int, C.c_int, vp,
                              C.POINTER(kcm_fold_result)]
     lib.kcm_get_state.argtypes = [vp, vp, vp, vp, vp, vp, vp]
@@ -217,6 +220,20 @@ def kcm_step(chains, n_iter: int = 1, stream=None, report=True, check: bool = Tr
         return st, None
     if isinstance(report, str) and report == "array":
         return st, np.ctypeslib.as_array(reps)
+    return st, list(reps)
+
+
+def kcm_step_noalloc(chains, n_iter: int = 1, stream=None, report=True, check: bool = True):
+    """kcm_step through the entry point that allocates nothing (at most
+    KCM_NOALLOC_MAX_CHAINS chains, direct launches); same return values."""
+    arr = _handles(chains)
+    reps = (kcm_step_report * len(chains))() if report else None
+    st = load_library().kcm_step_noalloc(arr, len(chains), int(n_iter), _stream_handle(stream),
+                                         reps if report else None)
+    if check:
+        _check(st)
+    if not report:
+        return st, None
     return st, list(reps)
 
 
