@@ -1026,6 +1026,12 @@ struct NbrEntry {
 };
 
 constexpr int SPL = 4;                              // samples per lane in one pass: passes of 256 samples
+// Neighbours whose cap on the offset sphere is large (cosine of its angular
+// radius, c0/|a|, below CAP_SPLIT) lead the list: step 1 then reaches two
+// overlappers for every sample of a slot early and stops there.
+constexpr double CAP_SPLIT = 0.6;
+constexpr int SAT_CHECK = 8;                        // step 1 checks a slot's saturation every 8 neighbours
+static_assert(SAT_CHECK * (SAT_CHECK - 1) / 2 < 32 && 32 + SAT_CHECK <= 64, "block code of step 1");
 constexpr int NSLOT = (MAX_NBR + WAVE - 1) / WAVE;  // neighbours per lane in step 2
 // Step-1 count of a sample: acc = (covering neighbours << ACC_SHIFT) + (sum of
 // their slots), so acc >> ACC_SHIFT == 1 leaves the single overlapper in the
@@ -1487,9 +1493,10 @@ __global__ __launch_bounds__(WAVE, sizeof(Real) == 4 ? 4 : 3) void k_force(Batch
 
     Real fx = 0, fy = 0, fz = 0;
     double ee = 0.0, evw = 0.0;
-    int nn = 0;
+    int nn = 0, nfront = 0, nback = 0;
     // one candidate: pair terms into (fx, fy, fz, ee, evw); a solvation
-    // neighbour is appended to the list in lane order
+    // neighbour with a large cap is appended at the front of the list, any
+    // other at its back (growing down from MAX_NBR - 1), in lane order
     auto visit = [&](bool valid, const double4 &rj, const double4 &pj) {
         const double ddx = rj.x - ri.x, ddy = rj.y - ri.y, ddz = rj.z - ri.z;
         const double d2 = ddx * ddx + ddy * ddy + ddz * ddz;
@@ -1523,24 +1530,30 @@ __global__ __launch_bounds__(WAVE, sizeof(Real) == 4 ? 4 : 3) void k_force(Batch
                 evw += (double)elj;
             }
         }
-        bool in_cav = false;
+        bool in_cav = false, front = false;
+        double c0 = 0.0;
         if (do_cav) {
-            const double lim = roff_i + pj.w + dr;
+            const double Rj = pj.w;
+            const double lim = roff_i + Rj + dr;
             in_cav = valid && d2 <= lim * lim;
+            c0 = (roff_i * roff_i + d2 - Rj * Rj) * inv_2roff;
+            front = c0 < 0.0 || c0 * c0 < (CAP_SPLIT * CAP_SPLIT) * d2;
         }
-        const unsigned long long m = __ballot(in_cav);
-        if (in_cav) {
-            const int pos = nn + __popcll(m & below);
-            if (pos < MAX_NBR) {
-                const double Rj = pj.w;
-                NbrEntry<Real> e;
-                e.ax = (Real)ddx; e.ay = (Real)ddy; e.az = (Real)ddz;
-                e.c0 = (Real)((roff_i * roff_i + d2 - Rj * Rj) * inv_2roff);
-                s_nbr[pos] = e;
-                s_nbr_a[pos] = aj;
-            }
+        const unsigned long long mf = __ballot(in_cav && front), mb = __ballot(in_cav && !front);
+        const int cf = __popcll(mf), cb = __popcll(mb);
+        // past the list's capacity nothing more is written: the atom then
+        // takes the chunked path, which enumerates its neighbours again
+        if (in_cav && nfront + cf + nback + cb <= MAX_NBR) {
+            const int pos = front ? nfront + __popcll(mf & below) : MAX_NBR - 1 - nback - __popcll(mb & below);
+            NbrEntry<Real> e;
+            e.ax = (Real)ddx; e.ay = (Real)ddy; e.az = (Real)ddz;
+            e.c0 = (Real)c0;
+            s_nbr[pos] = e;
+            s_nbr_a[pos] = aj;
         }
-        nn += __popcll(m);
+        nfront += cf;
+        nback += cb;
+        nn += cf + cb;
     };
 
     // CPT candidates per lane per trip, every load issued before any is used
@@ -1614,11 +1627,33 @@ __global__ __launch_bounds__(WAVE, sizeof(Real) == 4 ? 4 : 3) void k_force(Batch
             own1 = cs.own[1];
             own2 = cs.own[2];
         } else {
+            // the back part of the list, [MAX_NBR - nback, MAX_NBR), moves
+            // down to [nfront, nnc): the list is then contiguous, large caps
+            // first.  Each source lies at or above its destination, and a
+            // chunk's reads are done before its writes.
+            const int nb_back = __builtin_amdgcn_readfirstlane(nback);
+            const int nf = __builtin_amdgcn_readfirstlane(nfront);
+            for (int c = 0; c < nb_back; c += WAVE) {
+                const int v = c + lane;
+                NbrEntry<Real> e;
+                int a = 0;
+                if (v < nb_back) {
+                    e = s_nbr[MAX_NBR - nb_back + v];
+                    a = s_nbr_a[MAX_NBR - nb_back + v];
+                }
+                __syncthreads();
+                if (v < nb_back) {
+                    s_nbr[nf + v] = e;
+                    s_nbr_a[nf + v] = a;
+                }
+                __syncthreads();
+            }
             for (int u = lane; u < nnc; u += WAVE) {
                 s_ev01[u] = EV_INIT;
                 s_ev2[u] = 0;
             }
             __syncthreads();
+            const int nlist = __builtin_amdgcn_readfirstlane(nnc);
             for (int kb = 0; kb < N; kb += WAVE * SPL) {
                 // step 1: coverage counts of SPL samples per lane
                 Real Qx[SPL], Qy[SPL], Qz[SPL], amin[SPL];
@@ -1631,11 +1666,55 @@ __global__ __launch_bounds__(WAVE, sizeof(Real) == 4 ? 4 : 3) void k_force(Batch
                     acc[i] = 0;
                     amin[i] = (Real)1e30;
                 }
-                for (int u = 0; u < nnc; ++u) {
+                // Blocks of 8 neighbours, read once for the four slots.  Once
+                // every sample of a slot has two overlappers (decisions
+                // outside the FP32 band; a sample with a test inside it is
+                // recounted below over the whole list) the rest of the list
+                // cannot change its C, and the slot's tests stop; the block
+                // loop stops when all four slots have.
+                bool live[SPL];
+#pragma unroll
+                for (int i = 0; i < SPL; ++i) {
+                    // a lane past N starts saturated, so that it never holds
+                    // its slot back (its count is not used)
+                    if (kb + lane + WAVE * i >= N) acc[i] = 2 << ACC_SHIFT;
+                    live[i] = kb + WAVE * i < N;
+                }
+                int u = 0;
+                for (; u + SAT_CHECK <= nlist; u += SAT_CHECK) {
+                    NbrEntry<Real> e[SAT_CHECK];
+#pragma unroll
+                    for (int q = 0; q < SAT_CHECK; ++q) e[q] = s_nbr[u + q];
+                    bool any_live = false;
+#pragma unroll
+                    for (int i = 0; i < SPL; ++i) {
+                        if (!live[i]) continue;
+                        // 32 per covering neighbour plus its index in the
+                        // block (both inline constants of the select); its
+                        // count c = blk >> 5 then adds c ((1 << ACC_SHIFT) + u)
+                        // + (blk - 32 c) to acc
+                        int blk = 0;
+#pragma unroll
+                        for (int q = 0; q < SAT_CHECK; ++q) {
+                            const Real t = fma(Qz[i], e[q].az, fma(Qy[i], e[q].ay, fma(Qx[i], e[q].ax, -e[q].c0)));
+                            blk += (t >= (Real)0) ? 32 + q : 0;
+                            if (MIXED) amin[i] = fmin(amin[i], fabs(t));
+                        }
+                        acc[i] += blk + __mul24(blk >> 5, (1 << ACC_SHIFT) + u - 32);
+                        live[i] = __ballot(acc[i] < (2 << ACC_SHIFT)) != 0ull;
+                        any_live = any_live || live[i];
+                    }
+                    if (!any_live) {
+                        u = nlist;
+                        break;
+                    }
+                }
+                for (; u < nlist; ++u) {
                     const NbrEntry<Real> e = s_nbr[u];
                     const int inc = (1 << ACC_SHIFT) + u;
 #pragma unroll
                     for (int i = 0; i < SPL; ++i) {
+                        if (!live[i]) continue;
                         const Real t = fma(Qz[i], e.az, fma(Qy[i], e.ay, fma(Qx[i], e.ax, -e.c0)));
                         acc[i] += (t >= (Real)0) ? inc : 0;
                         if (MIXED) amin[i] = fmin(amin[i], fabs(t));
