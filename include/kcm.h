@@ -50,7 +50,7 @@ typedef enum {
     KCM_E_NUMERIC = -4,  /* NaN/Inf in this chain's forces or torques */
     KCM_E_STATE = -5,    /* call not valid in the handle's current state */
     KCM_E_CAPACITY = -6  /* an atom has 131072 or more solvation neighbours (the force
-                            kernel takes any smaller count, in LDS chunks of 384) */
+                            kernel takes any smaller count, in LDS chunks of 352) */
 } kcm_status;
 
 enum { KCM_STEP_CAPPED = 0, KCM_STEP_PAPER = 1, KCM_STEP_LINEAR = 2 };
