@@ -237,10 +237,12 @@ def run_batch(steps: int, warmup: int, n_chains: int = 256, tune: bool = True, d
                     c.free()
     finally:
         kcm.kcm_set_graphs(0 if direct else 1)
+        kcm.kcm_set_force_variant(0)
         for c in chains:
             c.free()
     out = {"chains": len(items), "atoms": atoms, "steps": steps, "seconds": secs, "ms_per_step": 1e3 * secs / steps,
            "value": atoms * steps / secs, "failed_chains": int(bad), "cell_size": p.cell_size, "graph_depth": depth,
+           "force_variant": tuned.force_variant if tuned else 0,
            "force_ms_mean": force_ms, "iter_ms_mean": iter_ms, "force_samples": samples, "units": units,
            "n_samples": n_samples}
     if full:
@@ -578,6 +580,7 @@ def main():
                 "n_atoms": b["atoms"],
                 "n_chains": b["chains"],
                 "cell_size": b["cell_size"],
+                "force_variant": b["force_variant"],
                 "graph_depth": b["graph_depth"],
             },
             "roofline": roofline(u, b["force_ms_mean"], "mixed", traffic_for("mixed", "batch256")),

@@ -1,12 +1,16 @@
-"""Autotuner for a batch of chains: cell edge and iterations per graph.
+"""Autotuner for a batch of chains: cell edge, force-kernel launch shape and
+iterations per graph.
 
-Two settings change the speed of an iteration but not its results beyond
+Three settings change the speed of an iteration but not its results beyond
 rounding order: the edge of the cells of the grid (``kcm_params.cell_size``;
-0 picks half the reach) and how many iterations one replayed HIP graph holds
-(``kcm_set_graphs``).  ``tune`` builds trial copies of the chains for every
-candidate edge, times a few iterations at every candidate depth on the device,
-and returns the fastest pair together with the whole table it measured.  The
-trial chains are freed; the caller builds its own with the chosen parameters.
+0 picks half the reach), the launch shape of the force kernel
+(``kcm_set_force_variant``: candidates per lane per trip and the block of
+neighbours step 1 reads before its saturation check; identical results) and
+how many iterations one replayed HIP graph holds (``kcm_set_graphs``).
+``tune`` builds trial copies of the chains for every candidate edge, times a
+few iterations at every shape and depth on the device, and returns the
+fastest setting together with the whole table it measured.  The trial chains
+are freed; the caller builds its own with the chosen parameters.
 
 The timing runs through the C ABI only (``kcm_step`` on the given stream),
 with one device synchronisation before and after each timed run.
@@ -22,18 +26,20 @@ class TuneResult:
     cell_size: float                 # 0.0: automatic (half the reach)
     graph_depth: int                 # iterations per replayed graph
     atom_steps_per_s: float
-    table: list = field(default_factory=list)  # (cell_size, depth, grid cell edge, atom-steps/s)
+    force_variant: int = 0           # launch shape of the force kernel
+    table: list = field(default_factory=list)  # (cell_size, variant, depth, grid cell edge, atom-steps/s)
 
     def as_dict(self):
-        return {"cell_size": self.cell_size, "graph_depth": self.graph_depth,
+        return {"cell_size": self.cell_size, "force_variant": self.force_variant, "graph_depth": self.graph_depth,
                 "atom_steps_per_s": self.atom_steps_per_s,
-                "table": [{"cell_size": c, "graph_depth": d, "grid_cell": g, "atom_steps_per_s": r}
-                          for c, d, g, r in self.table]}
+                "table": [{"cell_size": c, "force_variant": v, "graph_depth": d, "grid_cell": g,
+                           "atom_steps_per_s": r} for c, v, d, g, r in self.table]}
 
 
-def tune(residue_types, items, precision, cell_sizes=(0.0, 4.4, 3.6), depths=(1, 4, 8),
+def tune(residue_types, items, precision, cell_sizes=(0.0, 4.4, 3.6), variants=(0, 1, 2), depths=(1, 4, 8),
          iters: int = 8, warmup: int = 2, stream=None) -> TuneResult:
-    """items: [(res_type, theta0)] of the batch; returns the fastest setting."""
+    """items: [(res_type, theta0)] of the batch; returns the fastest setting.
+    Leaves the force variant at the fastest one and graphs at depth 1."""
     import torch
 
     from . import kcm
@@ -47,19 +53,22 @@ def tune(residue_types, items, precision, cell_sizes=(0.0, 4.4, 3.6), depths=(1,
             chains = [kcm.Chain(seq, residue_types, p, theta0=th, stream=stream) for seq, th in items]
             atoms = sum(c.n_atoms for c in chains)
             try:
-                for d in depths:
-                    kcm.kcm_set_graphs(d)
-                    kcm.kcm_step(chains, warmup + d, stream, report=False)  # captures the graphs
-                    torch.cuda.synchronize()
-                    t0 = time.perf_counter()
-                    kcm.kcm_step(chains, iters * d, stream, report=False)
-                    torch.cuda.synchronize()
-                    rate = atoms * iters * d / (time.perf_counter() - t0)
-                    table.append((float(cs), int(d), float(chains[0].cells(stream)["cell"]), rate))
+                for v in variants:
+                    kcm.kcm_set_force_variant(v)
+                    for d in depths:
+                        kcm.kcm_set_graphs(d)
+                        kcm.kcm_step(chains, warmup + d, stream, report=False)  # captures the graphs
+                        torch.cuda.synchronize()
+                        t0 = time.perf_counter()
+                        kcm.kcm_step(chains, iters * d, stream, report=False)
+                        torch.cuda.synchronize()
+                        rate = atoms * iters * d / (time.perf_counter() - t0)
+                        table.append((float(cs), int(v), int(d), float(chains[0].cells(stream)["cell"]), rate))
             finally:
                 for c in chains:
                     c.free()
     finally:
         kcm.kcm_set_graphs(1)
-    cs, d, _, rate = max(table, key=lambda row: row[3])
-    return TuneResult(cell_size=cs, graph_depth=d, atom_steps_per_s=rate, table=table)
+    cs, v, d, _, rate = max(table, key=lambda row: row[4])
+    kcm.kcm_set_force_variant(v)
+    return TuneResult(cell_size=cs, graph_depth=d, atom_steps_per_s=rate, force_variant=v, table=table)

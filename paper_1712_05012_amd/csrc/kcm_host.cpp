@@ -277,6 +277,7 @@ struct Table {
 std::mutex g_mu;
 std::vector<Table> g_tables;
 int g_graphs = 1;                       // iterations per captured graph (0: direct launches)
+int g_force_shape = 0;                  // launch shape of the force kernel (kcm_set_force_variant)
 constexpr int kMaxGraphDepth = 64;
 std::vector<std::pair<int, hipStream_t>> g_capture_streams;  // per device
 
@@ -314,7 +315,7 @@ hipError_t launch_iteration(const Batch &bt, int prec, hipStream_t stream, const
     if ((e = launch_scatter(bt, stream)) != hipSuccess) return e;
     if ((e = launch_rank(bt, stream)) != hipSuccess) return e;
     if (ti && (e = hipEventRecord(ti->f0, stream)) != hipSuccess) return e;
-    if ((e = launch_force(bt, prec, stream)) != hipSuccess) return e;
+    if ((e = launch_force(bt, prec, g_force_shape, stream)) != hipSuccess) return e;
     if (ti && (e = hipEventRecord(ti->f1, stream)) != hipSuccess) return e;
     if ((e = launch_wrench(bt, stream)) != hipSuccess) return e;
     if (ti && (e = hipEventRecord(ti->it1, stream)) != hipSuccess) return e;
@@ -800,23 +801,25 @@ kcm_status iterate_locked(Table *t, kcm_chain *const *chains, int n_chains, int 
 {
     const Batch &bt = t->batch;
     const int depth = g_graphs;
-    if (depth > 0 && n_iter > 0 && (!t->graph || t->graph_prec != prec)) {
+    // a captured graph holds the precision's kernels in the current force shape
+    const int key = prec + 16 * g_force_shape;
+    if (depth > 0 && n_iter > 0 && (!t->graph || t->graph_prec != key)) {
         if (t->graph) {
             HIP_TRY(hipGraphExecDestroy(t->graph));
             t->graph = nullptr;
         }
         hipError_t e = capture_iterations(bt, prec, 1, &t->graph);
         if (e != hipSuccess) return fail(KCM_E_DEVICE, std::string("graph capture: ") + hipGetErrorString(e));
-        t->graph_prec = prec;
+        t->graph_prec = key;
     }
-    if (depth > 1 && n_iter >= depth && (!t->graph_n || t->graph_n_prec != prec || t->graph_n_depth != depth)) {
+    if (depth > 1 && n_iter >= depth && (!t->graph_n || t->graph_n_prec != key || t->graph_n_depth != depth)) {
         if (t->graph_n) {
             HIP_TRY(hipGraphExecDestroy(t->graph_n));
             t->graph_n = nullptr;
         }
         hipError_t e = capture_iterations(bt, prec, depth, &t->graph_n);
         if (e != hipSuccess) return fail(KCM_E_DEVICE, std::string("graph capture: ") + hipGetErrorString(e));
-        t->graph_n_prec = prec;
+        t->graph_n_prec = key;
         t->graph_n_depth = depth;
     }
     if (n_iter > 0) {
@@ -1344,6 +1347,14 @@ kcm_status kcm_set_graphs(int iterations)
     if (iterations < 0 || iterations > kMaxGraphDepth) return fail(KCM_E_INVAL, "iterations per graph must be in 0..64");
     std::lock_guard<std::mutex> lock(g_mu);
     g_graphs = iterations;
+    return KCM_OK;
+}
+
+kcm_status kcm_set_force_variant(int variant)
+{
+    if (variant < 0 || variant >= FORCE_SHAPE_COUNT) return fail(KCM_E_INVAL, "force variant out of range");
+    std::lock_guard<std::mutex> lock(g_mu);
+    g_force_shape = variant;
     return KCM_OK;
 }
 

@@ -1030,8 +1030,15 @@ constexpr int SPL = 4;                              // samples per lane in one p
 // radius, c0/|a|, below CAP_SPLIT) lead the list: step 1 then reaches two
 // overlappers for every sample of a slot early and stops there.
 constexpr double CAP_SPLIT = 0.6;
-constexpr int SAT_CHECK = 8;                        // step 1 checks a slot's saturation every 8 neighbours
-static_assert(SAT_CHECK * (SAT_CHECK - 1) / 2 < 32 && 32 + SAT_CHECK <= 64, "block code of step 1");
+// Launch shapes of the force kernel (kcm_set_force_variant): candidates each
+// lane loads per trip of the candidate loop (CPT), and the neighbours step 1
+// reads as one block before it checks the slots' saturation (SATB).  Every
+// shape visits the candidates and appends the neighbours in the same order,
+// and takes the same decisions: the results are the same bit for bit.
+struct ForceShape {
+    int cpt, satb;
+};
+constexpr ForceShape FORCE_SHAPES[] = {{2, 8}, {4, 8}, {2, 4}};
 constexpr int NSLOT = (MAX_NBR + WAVE - 1) / WAVE;  // neighbours per lane in step 2
 // Step-1 count of a sample: acc = (covering neighbours << ACC_SHIFT) + (sum of
 // their slots), so acc >> ACC_SHIFT == 1 leaves the single overlapper in the
@@ -1398,9 +1405,10 @@ __device__ __noinline__ ChunkedSasa sasa_chunked(const ChainDev *cd, const Chunk
 
 // Mixed form: four waves per SIMD, the register budget (128) it fits in.  The
 // FP64 form's LDS list already limits it to fewer waves.
-template <typename Real>
+template <typename Real, int CPT, int SAT_CHECK>
 __global__ __launch_bounds__(WAVE, sizeof(Real) == 4 ? 4 : 3) void k_force(Batch bt)
 {
+    static_assert(SAT_CHECK * (SAT_CHECK - 1) / 2 < 32 && 32 + SAT_CHECK <= 64, "block code of step 1");
     constexpr bool MIXED = sizeof(Real) == 4;
     __shared__ NbrEntry<Real> s_nbr[MAX_NBR];
     __shared__ int s_nbr_a[MAX_NBR];
@@ -1557,7 +1565,6 @@ __global__ __launch_bounds__(WAVE, sizeof(Real) == 4 ? 4 : 3) void k_force(Batch
     };
 
     // CPT candidates per lane per trip, every load issued before any is used
-    constexpr int CPT = 4;
     for (int kb = 0; kb < T; kb += CPT * WAVE) {
         int sj[CPT];
         bool ok[CPT];
@@ -2047,13 +2054,25 @@ hipError_t launch_wrench(const Batch &b, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_force(const Batch &b, int precision, hipStream_t s)
+template <int V>
+void launch_force_shape(const Batch &b, int precision, hipStream_t s)
+{
+    constexpr int C = FORCE_SHAPES[V].cpt, S = FORCE_SHAPES[V].satb;
+    if (precision == 1)
+        hipLaunchKernelGGL((k_force<float, C, S>), dim3(b.total_atoms), dim3(WAVE), 0, s, b);
+    else
+        hipLaunchKernelGGL((k_force<double, C, S>), dim3(b.total_atoms), dim3(WAVE), 0, s, b);
+}
+
+hipError_t launch_force(const Batch &b, int precision, int shape, hipStream_t s)
 {
     if (b.total_atoms <= 0) return hipSuccess;
-    if (precision == 1)
-        hipLaunchKernelGGL(k_force<float>, dim3(b.total_atoms), dim3(WAVE), 0, s, b);
-    else
-        hipLaunchKernelGGL(k_force<double>, dim3(b.total_atoms), dim3(WAVE), 0, s, b);
+    static_assert(sizeof(FORCE_SHAPES) / sizeof(FORCE_SHAPES[0]) == FORCE_SHAPE_COUNT, "shape table");
+    switch (shape) {
+    case 1: launch_force_shape<1>(b, precision, s); break;
+    case 2: launch_force_shape<2>(b, precision, s); break;
+    default: launch_force_shape<0>(b, precision, s); break;
+    }
     return hipGetLastError();
 }
 

@@ -25,7 +25,8 @@ EXPORTED = ("kcm_default_params", "kcm_chain_bytes", "kcm_build_chain", "kcm_ste
             "kcm_get_state", "kcm_get_forces", "kcm_set_theta", "kcm_get_cells", "kcm_chain_info",
             "kcm_set_timing", "kcm_get_timing", "kcm_chain_free", "kcm_last_error", "kcm_get_atom_terms",
             "kcm_set_limits", "kcm_set_graphs", "kcm_mc_minimize", "kcm_mc_best_theta", "kcm_set_theta_batch",
-            "kcm_step_noalloc")
+            "kcm_step_noalloc", "kcm_set_force_variant")
+KCM_FORCE_VARIANTS = 3
 KCM_NOALLOC_MAX_CHAINS = 1024
 
 
@@ -95,6 +96,7 @@ def load_library(path: str = LIB_PATH):
     lib.kcm_get_atom_terms.argtypes = [vp, vp, vp, vp, vp, vp]
     lib.kcm_set_limits.argtypes = [vp, C.c_double, C.c_int64, vp]
     lib.kcm_set_graphs.argtypes = [C.c_int]
+    lib.kcm_set_force_variant.argtypes = [C.c_int]
     lib.kcm_get_cells.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, C.c_int32]
     lib.kcm_chain_info.argtypes = [vp, vp, vp, vp, vp]
     lib.kcm_set_timing.argtypes = [C.c_int]
@@ -387,6 +389,11 @@ def kcm_set_graphs(iterations):
     if isinstance(iterations, bool):
         iterations = 1 if iterations else 0
     _check(load_library().kcm_set_graphs(int(iterations)))
+
+
+def kcm_set_force_variant(variant: int):
+    """Launch shape of the force kernel (0 .. KCM_FORCE_VARIANTS-1), process-wide."""
+    _check(load_library().kcm_set_force_variant(int(variant)))
 
 
 def kcm_set_timing(every: int):

@@ -453,6 +453,32 @@ def test_graph_replay_equals_direct_launches(depth):
             c.free()
 
 
+def test_force_kernel_shapes_give_identical_results():
+    # every launch shape of the force kernel visits the candidates and lists
+    # the neighbours in the same order and takes the same decisions: the
+    # states after a few graph-replayed iterations are equal bit for bit
+    out = []
+    try:
+        for v in range(kcm.KCM_FORCE_VARIANTS):
+            kcm.kcm_set_force_variant(v)
+            for prec in (kcm.KCM_MIXED, kcm.KCM_FP64):
+                p = params(prec)
+                cs = [build_pair(m, 180 + m, p)[0] for m in (9, 120, 40)]
+                kcm.kcm_step(cs, 5)
+                out.append((v, prec, [c.state() for c in cs]))
+                for c in cs:
+                    c.free()
+    finally:
+        kcm.kcm_set_force_variant(0)
+    ref = {prec: states for v, prec, states in out if v == 0}
+    for v, prec, states in out:
+        for a, b in zip(states, ref[prec]):
+            for key in ("theta", "xyz", "force", "tau"):
+                assert np.array_equal(a[key], b[key]), (v, prec, key)
+    with pytest.raises(kcm.KcmError):
+        kcm.kcm_set_force_variant(kcm.KCM_FORCE_VARIANTS)
+
+
 def test_device_side_limits_stop_chains():
     p = params(kcm.KCM_MIXED)
     c1 = kcm.Chain(synth.sequence(6, 151), TYPES, p, theta0=synth.random_dihedrals(6, 151))
@@ -491,9 +517,13 @@ def test_autotune_picks_a_measured_setting_with_unchanged_results():
     from paper_1712_05012_amd import autotune
 
     items = [(synth.sequence(m, 300 + m), synth.random_dihedrals(m, 300 + m)) for m in (12, 30, 21)]
-    res = autotune.tune(TYPES, items, kcm.KCM_MIXED, cell_sizes=(0.0, 3.6), depths=(1, 2), iters=2, warmup=1)
-    assert len(res.table) == 4
-    assert (res.cell_size, res.graph_depth) in [(c, d) for c, d, _, _ in res.table]
+    try:
+        res = autotune.tune(TYPES, items, kcm.KCM_MIXED, cell_sizes=(0.0, 3.6), variants=(0, 2), depths=(1, 2),
+                            iters=2, warmup=1)
+    finally:
+        kcm.kcm_set_force_variant(0)
+    assert len(res.table) == 8
+    assert (res.cell_size, res.force_variant, res.graph_depth) in [(c, v, d) for c, v, d, _, _ in res.table]
     assert res.atom_steps_per_s == max(r for *_, r in res.table) > 0
     # the chosen cell edge changes only the candidate order: parity holds
     p = params(kcm.KCM_MIXED, cell_size=res.cell_size)
