@@ -184,7 +184,7 @@ def batch_workload(n_chains: int = 256):
 
 
 def run_batch(steps: int, warmup: int, n_chains: int = 256, tune: bool = True, direct: bool = False,
-              full_steps: int = 500):
+              full_steps: int = 500, setting=None):
     """Ragged batch in mixed precision: all chains advanced together by replayed
     HIP graphs, with the cell edge and the iterations per graph picked by the
     autotuner on the same batch first.  Times `steps` iterations (events on
@@ -196,7 +196,14 @@ def run_batch(steps: int, warmup: int, n_chains: int = 256, tune: bool = True, d
 
     T, items = batch_workload(n_chains)
     stream = torch.cuda.current_stream()
-    tuned = autotune.tune(T, items, kcm.KCM_MIXED, stream=stream) if tune and not direct else None
+    if setting is not None:
+        # a fixed (cell edge, force variant, graph depth), e.g. the tuner's
+        # choice taken again under a profiler
+        tuned = autotune.TuneResult(cell_size=setting[0], force_variant=setting[1], graph_depth=setting[2],
+                                    atom_steps_per_s=0.0)
+        kcm.kcm_set_force_variant(tuned.force_variant)
+    else:
+        tuned = autotune.tune(T, items, kcm.KCM_MIXED, stream=stream) if tune and not direct else None
     p = kcm.kcm_default_params(precision=kcm.KCM_MIXED, cell_size=tuned.cell_size if tuned else 0.0)
     depth = 0 if direct else (tuned.graph_depth if tuned else 1)
     chains = [kcm.Chain(seq, T, p, theta0=th) for seq, th in items]
@@ -515,6 +522,8 @@ def main():
     ap.add_argument("--no-graphs", action="store_true",
                     help="launch each iteration's kernels directly instead of replaying a HIP graph")
     ap.add_argument("--no-tune", action="store_true", help="batch leg with the default cell edge, one-deep graphs")
+    ap.add_argument("--batch-setting", default=None, metavar="CELL,VARIANT,DEPTH",
+                    help="batch leg at this cell edge, force variant and graph depth instead of tuning")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="first run a plain device copy of MIB MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -554,8 +563,12 @@ def main():
 
     line = {}
     if "batch" in legs:
+        setting = None
+        if args.batch_setting:
+            cs, v, d = args.batch_setting.split(",")
+            setting = (float(cs), int(v), 0 if args.no_graphs else int(d))
         b = run_batch(args.steps, args.warmup, tune=not args.no_tune, direct=args.no_graphs,
-                      full_steps=args.full_steps)
+                      full_steps=args.full_steps, setting=setting)
         progress(f"batch done: {b['value']:.4g} atom-steps/s")
         u = b.pop("units")
         line = {

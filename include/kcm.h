@@ -305,10 +305,12 @@ kcm_status kcm_set_graphs(int iterations);
  * 0 (default): each lane loads two candidates per trip of the candidate loop,
  * and step 1 reads the solvation neighbours in blocks of 8 before it checks
  * which sample slots are done; 1: four candidates per trip, blocks of 8;
- * 2: two candidates, blocks of 4.  Every shape gives identical results (the
- * same visiting order and decisions).  Graphs captured in another shape are
- * captured again.  KCM_E_INVAL unless 0 <= variant < KCM_FORCE_VARIANTS. */
-#define KCM_FORCE_VARIANTS 3
+ * 2: two candidates, blocks of 4; 3: as 0, with the atoms handed to the 8
+ * XCDs in contiguous eighths (XCD-aware order).  Every shape gives identical
+ * results (the same visiting order and decisions).  Graphs captured in
+ * another shape are captured again.  KCM_E_INVAL unless
+ * 0 <= variant < KCM_FORCE_VARIANTS. */
+#define KCM_FORCE_VARIANTS 4
 kcm_status kcm_set_force_variant(int variant);
 
 kcm_status kcm_get_timing(double *force_ms, int64_t *force_launches, double *iter_ms,

@@ -4,8 +4,9 @@ iterations per graph.
 Three settings change the speed of an iteration but not its results beyond
 rounding order: the edge of the cells of the grid (``kcm_params.cell_size``;
 0 picks half the reach), the launch shape of the force kernel
-(``kcm_set_force_variant``: candidates per lane per trip and the block of
-neighbours step 1 reads before its saturation check; identical results) and
+(``kcm_set_force_variant``: candidates per lane per trip, the block of
+neighbours step 1 reads before its saturation check and the atoms' order
+over the XCDs; identical results) and
 how many iterations one replayed HIP graph holds (``kcm_set_graphs``).
 ``tune`` builds trial copies of the chains for every candidate edge, times a
 few iterations at every shape and depth on the device, and returns the
@@ -36,7 +37,7 @@ class TuneResult:
                            "atom_steps_per_s": r} for c, v, d, g, r in self.table]}
 
 
-def tune(residue_types, items, precision, cell_sizes=(0.0, 4.4, 3.6), variants=(0, 1, 2), depths=(1, 4, 8),
+def tune(residue_types, items, precision, cell_sizes=(0.0, 4.4, 3.6), variants=(0, 1, 2, 3), depths=(1, 4, 8),
          iters: int = 8, warmup: int = 2, stream=None) -> TuneResult:
     """items: [(res_type, theta0)] of the batch; returns the fastest setting.
     Leaves the force variant at the fastest one and graphs at depth 1."""

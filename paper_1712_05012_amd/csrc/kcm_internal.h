@@ -145,7 +145,7 @@ hipError_t launch_finish(const Batch &b, hipStream_t s);
 hipError_t launch_place(const Batch &b, int mode, hipStream_t s);
 hipError_t launch_cellscan(const Batch &b, hipStream_t s);
 hipError_t launch_scatter(const Batch &b, hipStream_t s);
-constexpr int FORCE_SHAPE_COUNT = 3;  // launch shapes of the force kernel (kcm_set_force_variant)
+constexpr int FORCE_SHAPE_COUNT = 4;  // launch shapes of the force kernel (kcm_set_force_variant)
 hipError_t launch_force(const Batch &b, int precision, int shape, hipStream_t s);
 hipError_t launch_rank(const Batch &b, hipStream_t s);
 hipError_t launch_wrench(const Batch &b, hipStream_t s);

@@ -1031,14 +1031,19 @@ constexpr int SPL = 4;                              // samples per lane in one p
 // overlappers for every sample of a slot early and stops there.
 constexpr double CAP_SPLIT = 0.6;
 // Launch shapes of the force kernel (kcm_set_force_variant): candidates each
-// lane loads per trip of the candidate loop (CPT), and the neighbours step 1
-// reads as one block before it checks the slots' saturation (SATB).  Every
-// shape visits the candidates and appends the neighbours in the same order,
-// and takes the same decisions: the results are the same bit for bit.
+// lane loads per trip of the candidate loop (CPT), the neighbours step 1
+// reads as one block before it checks the slots' saturation (SATB), and the
+// order of the atoms over the workgroups: cell order, or XCD-aware (the
+// workgroups go to the 8 XCDs in turn; XCD x takes the x-th contiguous eighth
+// of the cell-ordered atoms, so that its L2 serves one region of space).
+// Every shape visits the candidates and appends the neighbours in the same
+// order, and takes the same decisions: the results are the same bit for bit.
 struct ForceShape {
     int cpt, satb;
+    bool xcd;
 };
-constexpr ForceShape FORCE_SHAPES[] = {{2, 8}, {4, 8}, {2, 4}};
+constexpr ForceShape FORCE_SHAPES[] = {{2, 8, false}, {4, 8, false}, {2, 4, false}, {2, 8, true}};
+constexpr int N_XCD = 8;
 constexpr int NSLOT = (MAX_NBR + WAVE - 1) / WAVE;  // neighbours per lane in step 2
 // Step-1 count of a sample: acc = (covering neighbours << ACC_SHIFT) + (sum of
 // their slots), so acc >> ACC_SHIFT == 1 leaves the single overlapper in the
@@ -1405,7 +1410,7 @@ __device__ __noinline__ ChunkedSasa sasa_chunked(const ChainDev *cd, const Chunk
 
 // Mixed form: four waves per SIMD, the register budget (128) it fits in.  The
 // FP64 form's LDS list already limits it to fewer waves.
-template <typename Real, int CPT, int SAT_CHECK>
+template <typename Real, int CPT, int SAT_CHECK, bool XCD>
 __global__ __launch_bounds__(WAVE, sizeof(Real) == 4 ? 4 : 3) void k_force(Batch bt)
 {
     static_assert(SAT_CHECK * (SAT_CHECK - 1) / 2 < 32 && 32 + SAT_CHECK <= 64, "block code of step 1");
@@ -1415,10 +1420,16 @@ __global__ __launch_bounds__(WAVE, sizeof(Real) == 4 ? 4 : 3) void k_force(Batch
     __shared__ unsigned s_ev01[MAX_NBR];  // net events of each neighbour, axes 0 and 1 (biased halves)
     __shared__ int s_ev2[MAX_NBR];        // and axis 2
 
-    const int c = find_block_owner(bt.atom_off, bt.n_chains, blockIdx.x);
+    int atom = blockIdx.x;
+    if (XCD) {
+        const int nq = bt.total_atoms / N_XCD, nr = bt.total_atoms % N_XCD;
+        const int x = blockIdx.x % N_XCD, k = blockIdx.x / N_XCD;
+        atom = x * nq + min(x, nr) + k;
+    }
+    const int c = find_block_owner(bt.atom_off, bt.n_chains, atom);
     ChainDev *cd = bt.table[c];
     if (!running(cd->stats)) return;
-    const int si = blockIdx.x - bt.atom_off[c];
+    const int si = atom - bt.atom_off[c];
     const int lane = threadIdx.x;
     const unsigned long long below = (1ull << lane) - 1ull;
 
@@ -2058,10 +2069,11 @@ template <int V>
 void launch_force_shape(const Batch &b, int precision, hipStream_t s)
 {
     constexpr int C = FORCE_SHAPES[V].cpt, S = FORCE_SHAPES[V].satb;
+    constexpr bool X = FORCE_SHAPES[V].xcd;
     if (precision == 1)
-        hipLaunchKernelGGL((k_force<float, C, S>), dim3(b.total_atoms), dim3(WAVE), 0, s, b);
+        hipLaunchKernelGGL((k_force<float, C, S, X>), dim3(b.total_atoms), dim3(WAVE), 0, s, b);
     else
-        hipLaunchKernelGGL((k_force<double, C, S>), dim3(b.total_atoms), dim3(WAVE), 0, s, b);
+        hipLaunchKernelGGL((k_force<double, C, S, X>), dim3(b.total_atoms), dim3(WAVE), 0, s, b);
 }
 
 hipError_t launch_force(const Batch &b, int precision, int shape, hipStream_t s)
@@ -2071,6 +2083,7 @@ hipError_t launch_force(const Batch &b, int precision, int shape, hipStream_t s)
     switch (shape) {
     case 1: launch_force_shape<1>(b, precision, s); break;
     case 2: launch_force_shape<2>(b, precision, s); break;
+    case 3: launch_force_shape<3>(b, precision, s); break;
     default: launch_force_shape<0>(b, precision, s); break;
     }
     return hipGetLastError();
