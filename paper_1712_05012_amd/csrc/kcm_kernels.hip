@@ -1069,12 +1069,6 @@ __device__ __forceinline__ double bcast(double x, int l)
     const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(b >> 32), l);
     return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
-__device__ __forceinline__ long long wave_sum_ll(long long v)
-{
-#pragma unroll
-    for (int d = 32; d > 0; d >>= 1) v += __shfl_xor(v, d, WAVE);
-    return v;
-}
 
 // FP64 decision in absolute coordinates: is sample k of atom i covered by the
 // offset sphere of atom aj, shifted by delta_r along axis s (s < 0: not
@@ -1204,7 +1198,7 @@ __device__ __noinline__ PairSums pair_terms_fp64(const ChainDev *cd, int si, int
 // decisions are those of one list, so the results are the same.
 struct ChunkedSasa {
     int ncov;                 // covered samples of this lane
-    long long own[3];         // this lane's share of the atom's own event sums
+    int own[3];               // this lane's share of the atom's own net events per axis
 };
 struct ChunkArgs {
     int si, off, rbase, nrows, T, nn;
@@ -1398,9 +1392,8 @@ __device__ __noinline__ ChunkedSasa sasa_chunked(const ChainDev *cd, const Chunk
 #pragma unroll
                 for (int x = 0; x < 3; ++x) {
                     if (!ev[x]) continue;
-                    const long long f = (long long)ev[x] * a.qf;
-                    out.own[x] += f;
-                    atomicAdd((unsigned long long *)&cd->f_cav[3 * aj + x], (unsigned long long)(-f));
+                    out.own[x] += ev[x];
+                    atomicAdd((unsigned long long *)&cd->f_cav[3 * aj + x], (unsigned long long)(-(long long)ev[x] * a.qf));
                 }
             }
         }
@@ -1635,7 +1628,9 @@ __global__ __launch_bounds__(WAVE, sizeof(Real) == 4 ? 4 : 3) void k_force(Batch
         // the FP32 decision band (mixed) or a rounding pad (FP64).
         const Real guard = MIXED ? (Real)(2.0f * MIXED_BAND) : (Real)1e-9;
         int ncov = 0;
-        long long own0 = 0, own1 = 0, own2 = 0;
+        // net events of the atom itself per axis (the neighbours' reactions go
+        // out at once); times the atom's quantum after the wave sum
+        int own0 = 0, own1 = 0, own2 = 0;
         if (nn > MAX_NBR) {
             // more neighbours than the LDS list holds: chunks, out of line
             const ChunkArgs ca = {si, off, rbase, nrows, T, nn};
@@ -1835,20 +1830,24 @@ __global__ __launch_bounds__(WAVE, sizeof(Real) == 4 ? 4 : 3) void k_force(Batch
                 const int e0 = (int)(w01 & 0xffffu) - EV_BIAS, e1 = (int)(w01 >> 16) - EV_BIAS, e2 = s_ev2[u];
                 if (!(e0 | e1 | e2)) continue;
                 const int aj = s_nbr_a[u];
-                if (e0) { const long long x = (long long)e0 * qf; own0 += x; atomicAdd((unsigned long long *)&cd->f_cav[3 * aj + 0], (unsigned long long)(-x)); }
-                if (e1) { const long long x = (long long)e1 * qf; own1 += x; atomicAdd((unsigned long long *)&cd->f_cav[3 * aj + 1], (unsigned long long)(-x)); }
-                if (e2) { const long long x = (long long)e2 * qf; own2 += x; atomicAdd((unsigned long long *)&cd->f_cav[3 * aj + 2], (unsigned long long)(-x)); }
+                own0 += e0;
+                own1 += e1;
+                own2 += e2;
+                if (e0) atomicAdd((unsigned long long *)&cd->f_cav[3 * aj + 0], (unsigned long long)(-(long long)e0 * qf));
+                if (e1) atomicAdd((unsigned long long *)&cd->f_cav[3 * aj + 1], (unsigned long long)(-(long long)e1 * qf));
+                if (e2) atomicAdd((unsigned long long *)&cd->f_cav[3 * aj + 2], (unsigned long long)(-(long long)e2 * qf));
             }
         }
         __syncthreads();
         ncov = wave_sum_i(ncov);
-        own0 = wave_sum_ll(own0);
-        own1 = wave_sum_ll(own1);
-        own2 = wave_sum_ll(own2);
+        own0 = wave_sum_i(own0);
+        own1 = wave_sum_i(own1);
+        own2 = wave_sum_i(own2);
         if (lane == 0) {
-            if (own0) atomicAdd((unsigned long long *)&cd->f_cav[3 * ai + 0], (unsigned long long)own0);
-            if (own1) atomicAdd((unsigned long long *)&cd->f_cav[3 * ai + 1], (unsigned long long)own1);
-            if (own2) atomicAdd((unsigned long long *)&cd->f_cav[3 * ai + 2], (unsigned long long)own2);
+            const long long qf = cd->qfix[ai];
+            if (own0) atomicAdd((unsigned long long *)&cd->f_cav[3 * ai + 0], (unsigned long long)((long long)own0 * qf));
+            if (own1) atomicAdd((unsigned long long *)&cd->f_cav[3 * ai + 1], (unsigned long long)((long long)own1 * qf));
+            if (own2) atomicAdd((unsigned long long *)&cd->f_cav[3 * ai + 2], (unsigned long long)((long long)own2 * qf));
         }
         e_cav = cd->g0[ai] * (double)(N - ncov) / (double)N;  // eq G_cav_patch
         n_exp = (double)(N - ncov);
