@@ -1014,6 +1014,26 @@ __global__ __launch_bounds__(ATOM_BLOCK) void k_rank(Batch bt)
     place_sorted(cd, cd->s_tmp, a, key, b, e);
 }
 
+// Loads, stores and atomics through a pointer of unknown address space are
+// flat instructions, which count against the LDS counter as well as the
+// vector-memory one: every LDS wait then also waits for them.  The device
+// arrays of the force kernel are all in global memory, and it reaches them
+// through these global-address-space views (plain pointers in the host
+// pass, which only checks the device code).
+#if defined(__HIP_DEVICE_COMPILE__)
+template <typename T> using gptr = __attribute__((address_space(1))) T *;
+#else
+template <typename T> using gptr = T *;
+#endif
+template <typename T> __device__ __forceinline__ gptr<T> glob(T *p) { return (gptr<T>)p; }
+using CDev = gptr<const ChainDev>;
+// fixed-point accumulation of the solvation force
+__device__ __forceinline__ void fix_add(gptr<long long> p, long long v)
+{
+    __hip_atomic_fetch_add((gptr<unsigned long long>)p, (unsigned long long)v, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // ---------------------------------------------------------------------------
 // k_force: Coulomb + LJ + SASA enumeration, one wave per atom
 // ---------------------------------------------------------------------------
@@ -1073,15 +1093,15 @@ __device__ __forceinline__ double bcast(double x, int l)
 // FP64 decision in absolute coordinates: is sample k of atom i covered by the
 // offset sphere of atom aj, shifted by delta_r along axis s (s < 0: not
 // shifted)?
-__device__ __forceinline__ bool cover_exact(const ChainDev *cd, const double4 &ri, double roff_i, int k, int aj, int s)
+__device__ __forceinline__ bool cover_exact(CDev cd, const double4 &ri, double roff_i, int k, int aj, int s)
 {
-    const double4 q = cd->q64[k];
+    const double4 q = glob(cd->q64)[k];
     const double qx = ri.x + roff_i * q.x, qy = ri.y + roff_i * q.y, qz = ri.z + roff_i * q.z;
-    double4 c = cd->r[aj];
+    double4 c = glob(cd->r)[aj];
     if (s == 0) c.x += cd->delta_r;
     if (s == 1) c.y += cd->delta_r;
     if (s == 2) c.z += cd->delta_r;
-    const double rj = cd->aparam[aj].w;
+    const double rj = glob(cd->aparam)[aj].w;
     const double dx = qx - c.x, dy = qy - c.y, dz = qz - c.z;
     return dx * dx + dy * dy + dz * dz - rj * rj <= 0.0;
 }
@@ -1089,7 +1109,7 @@ __device__ __forceinline__ bool cover_exact(const ChainDev *cd, const double4 &r
 // Coverage by a displaced neighbour, v = (tested quantity) with threshold 0;
 // the mixed form decides again in FP64 inside the band.
 template <typename Real, bool MIXED>
-__device__ __forceinline__ bool test_cover(Real v, const ChainDev *cd, const double4 &ri, double roff_i, int k, int aj, int s)
+__device__ __forceinline__ bool test_cover(Real v, CDev cd, const double4 &ri, double roff_i, int k, int aj, int s)
 {
     bool hit = v >= (Real)0;
     if (MIXED) {
@@ -1107,20 +1127,20 @@ __device__ __forceinline__ bool band3(float v0, float v1, float v2)
 {
     return fminf(fabsf(v0), fminf(fabsf(v1), fabsf(v2))) <= MIXED_BAND;
 }
-__device__ __forceinline__ int redo(float v, const ChainDev *cd, const double4 &ri, double roff_i, int k, int aj, int s)
+__device__ __forceinline__ int redo(float v, CDev cd, const double4 &ri, double roff_i, int k, int aj, int s)
 {
     if (fabsf(v) > MIXED_BAND) return 0;
     return (v >= 0.0f ? 1 : 0) - (cover_exact(cd, ri, roff_i, k, aj, s) ? 1 : 0);
 }
 
 template <typename Real>
-__device__ __forceinline__ void load_q(const ChainDev *cd, int k, Real &x, Real &y, Real &z)
+__device__ __forceinline__ void load_q(CDev cd, int k, Real &x, Real &y, Real &z)
 {
     if (sizeof(Real) == 4) {
-        const float4 q = cd->q32[k];
+        const float4 q = glob(cd->q32)[k];
         x = (Real)q.x; y = (Real)q.y; z = (Real)q.z;
     } else {
-        const double4 q = cd->q64[k];
+        const double4 q = glob(cd->q64)[k];
         x = (Real)q.x; y = (Real)q.y; z = (Real)q.z;
     }
 }
@@ -1134,12 +1154,12 @@ struct PairSums {
     double f[3];
     double e[2];
 };
-__device__ __noinline__ PairSums pair_terms_fp64(const ChainDev *cd, int si, int off, int rbase, int T, int nrows,
+__device__ __noinline__ PairSums pair_terms_fp64(CDev cd, int si, int off, int rbase, int T, int nrows,
                                                  int res_i, uint32_t m12, uint32_t m13, uint32_t m14, int terms)
 {
     const int lane = threadIdx.x & (WAVE - 1);
-    const double4 ri = cd->s_r[si];
-    const double4 pa = cd->s_p[si];
+    const double4 ri = glob(cd->s_r)[si];
+    const double4 pa = glob(cd->s_p)[si];
     const double cut2 = cd->cutoff * cd->cutoff;
     const bool do_elec = terms & 1, do_vdw = terms & 2;
     PairSums out = {{0.0, 0.0, 0.0}, {0.0, 0.0}};
@@ -1156,8 +1176,8 @@ __device__ __noinline__ PairSums pair_terms_fp64(const ChainDev *cd, int si, int
         int sj = __shfl(rbase, lo, WAVE) + k;
         const bool ok = k < T && sj != si;
         if (k >= T) sj = si;
-        const double4 rj = cd->s_r[sj];
-        const double4 pj = cd->s_p[sj];
+        const double4 rj = glob(cd->s_r)[sj];
+        const double4 pj = glob(cd->s_p)[sj];
         const double ddx = rj.x - ri.x, ddy = rj.y - ri.y, ddz = rj.z - ri.z;
         const double d2 = ddx * ddx + ddy * ddy + ddz * ddz;
         if (!(ok && d2 <= cut2)) continue;
@@ -1204,7 +1224,7 @@ struct ChunkArgs {
     int si, off, rbase, nrows, T, nn;
 };
 template <typename Real>
-__device__ __noinline__ ChunkedSasa sasa_chunked(const ChainDev *cd, const ChunkArgs c, NbrEntry<Real> *s_nbr,
+__device__ __noinline__ ChunkedSasa sasa_chunked(CDev cd, const ChunkArgs c, NbrEntry<Real> *s_nbr,
                                                  int *s_nbr_a, unsigned *s_ev01, int *s_ev2)
 {
     constexpr bool MIXED = sizeof(Real) == 4;
@@ -1220,11 +1240,11 @@ __device__ __noinline__ ChunkedSasa sasa_chunked(const ChainDev *cd, const Chunk
     } a;
     a.si = c.si; a.off = c.off; a.rbase = c.rbase; a.nrows = c.nrows; a.T = c.T; a.nn = c.nn;
     a.N = cd->n_samples;
-    a.ri = cd->s_r[c.si];
-    a.roff_i = cd->s_p[c.si].w;
+    a.ri = glob(cd->s_r)[c.si];
+    a.roff_i = glob(cd->s_p)[c.si].w;
     a.inv_2roff = 0.5 / a.roff_i;
     a.dr = cd->delta_r;
-    a.qf = cd->qfix[(int)__double_as_longlong(a.ri.w)];
+    a.qf = glob(cd->qfix)[(int)__double_as_longlong(a.ri.w)];
     const Real drr = (Real)a.dr, kq = (Real)(a.dr * a.dr / (2.0 * a.roff_i)), k1 = (Real)(a.dr / a.roff_i);
     const Real guard = MIXED ? (Real)(2.0f * MIXED_BAND) : (Real)1e-9;
     ChunkedSasa out = {0, {0, 0, 0}};
@@ -1245,8 +1265,8 @@ __device__ __noinline__ ChunkedSasa sasa_chunked(const ChainDev *cd, const Chunk
             int sj = __shfl(a.rbase, r, WAVE) + k;
             const bool valid = k < a.T && sj != a.si;
             if (k >= a.T) sj = a.si;
-            const double4 rj = cd->s_r[sj];
-            const double4 pj = cd->s_p[sj];
+            const double4 rj = glob(cd->s_r)[sj];
+            const double4 pj = glob(cd->s_p)[sj];
             const double ddx = rj.x - a.ri.x, ddy = rj.y - a.ri.y, ddz = rj.z - a.ri.z;
             const double d2 = ddx * ddx + ddy * ddy + ddz * ddz;
             const double lim = a.roff_i + pj.w + a.dr;
@@ -1393,7 +1413,7 @@ __device__ __noinline__ ChunkedSasa sasa_chunked(const ChainDev *cd, const Chunk
                 for (int x = 0; x < 3; ++x) {
                     if (!ev[x]) continue;
                     out.own[x] += ev[x];
-                    atomicAdd((unsigned long long *)&cd->f_cav[3 * aj + x], (unsigned long long)(-(long long)ev[x] * a.qf));
+                    fix_add(&glob(cd->f_cav)[3 * aj + x], (-(long long)ev[x] * a.qf));
                 }
             }
         }
@@ -1410,8 +1430,8 @@ __global__ __launch_bounds__(WAVE, sizeof(Real) == 4 ? 4 : 3) void k_force(Batch
     constexpr bool MIXED = sizeof(Real) == 4;
     __shared__ NbrEntry<Real> s_nbr[MAX_NBR];
     __shared__ int s_nbr_a[MAX_NBR];
-    __shared__ unsigned s_ev01[MAX_NBR];  // net events of each neighbour, axes 0 and 1 (biased halves)
-    __shared__ int s_ev2[MAX_NBR];        // and axis 2
+    __shared__ __align__(8) unsigned s_ev01[MAX_NBR];  // net events of each neighbour, axes 0 and 1 (biased halves)
+    __shared__ int s_ev2[MAX_NBR];                     // and axis 2
 
     int atom = blockIdx.x;
     if (XCD) {
@@ -1420,17 +1440,17 @@ __global__ __launch_bounds__(WAVE, sizeof(Real) == 4 ? 4 : 3) void k_force(Batch
         atom = x * nq + min(x, nr) + k;
     }
     const int c = find_block_owner(bt.atom_off, bt.n_chains, atom);
-    ChainDev *cd = bt.table[c];
+    const CDev cd = glob(glob(bt.table)[c]);
     if (!running(cd->stats)) return;
     const int si = atom - bt.atom_off[c];
     const int lane = threadIdx.x;
     const unsigned long long below = (1ull << lane) - 1ull;
 
-    const Grid g = *cd->grid;
-    const double4 ri = cd->s_r[si];
-    const double4 pi = cd->s_p[si];
+    const Grid g = *glob(cd->grid);
+    const double4 ri = glob(cd->s_r)[si];
+    const double4 pi = glob(cd->s_p)[si];
     const int ai = (int)__double_as_longlong(ri.w);
-    const int key = cd->s_cell[si];
+    const int key = glob(cd->s_cell)[si];
     const int dxn = g.dims[0], dyn = g.dims[1], dzn = g.dims[2];
     const int cx = key % dxn, cy = (key / dxn) % dyn, cz = key / (dxn * dyn);
     const int R = g.reach, side = 2 * R + 1, nrows = side * side;
@@ -1462,8 +1482,8 @@ __global__ __launch_bounds__(WAVE, sizeof(Real) == 4 ? 4 : 3) void k_force(Batch
                 const int xh = min(min(dxn - 1, cx + R), max(xb, 0));
                 if (xl <= xh) {
                     const int base = (z * dyn + y) * dxn;
-                    beg = cd->cell_start[base + xl];
-                    cnt = cd->cell_start[base + xh + 1] - beg;
+                    beg = glob(cd->cell_start)[base + xl];
+                    cnt = glob(cd->cell_start)[base + xh + 1] - beg;
                 }
             }
         }
@@ -1491,16 +1511,29 @@ __global__ __launch_bounds__(WAVE, sizeof(Real) == 4 ? 4 : 3) void k_force(Batch
     const Real coul = (Real)cd->coulomb;
     const Real qi = (Real)pi.x, Ri = (Real)pi.y, sei = (Real)pi.z;
 
-    // sorted atom of candidate number k: the row is the last one starting at or before k
-    auto cand_atom = [&](int k) -> int {
-        int lo = 0;
-#pragma unroll
-        for (int step = 32; step >= 1; step >>= 1) {
-            const int t = lo + step;
-            const int o = __shfl(off, t & (WAVE - 1), WAVE);
-            if (t < nrows && o <= k) lo = t;
-        }
-        return __shfl(rbase, lo, WAVE) + k;
+    // Sorted atom of candidate kw + lane, one window of 64 candidates at a
+    // time, windows in increasing order.  Each non-empty row starting inside
+    // the window leaves (its first candidate number, rbase) at that position
+    // of an LDS table; a candidate's row is the last start at or before it,
+    // read from the wave's mask of starts, or else the row running on from
+    // the previous window.  The table lives in the event array, which is
+    // free until the candidates are done; an entry left by an earlier window
+    // never matches, since it holds that window's candidate number.
+    int2 *s_head = reinterpret_cast<int2 *>(s_ev01);
+    s_head[lane] = make_int2(-1, 0);
+    const unsigned long long upto = below | (1ull << lane);
+    int carry = 0;
+    auto window_atom = [&](int kw) -> int {
+        if (cnt > 0 && off >= kw && off < kw + WAVE) s_head[off - kw] = make_int2(off, rbase);
+        __builtin_amdgcn_wave_barrier();
+        const int2 h = s_head[lane];
+        const unsigned long long m = __ballot(h.x == kw + lane) & upto;
+        const int p = m ? 63 - __clzll((long long)m) : lane;
+        const int rb = __shfl(h.y, p, WAVE);
+        const int base = m ? rb : carry;
+        carry = __builtin_amdgcn_readlane(base, WAVE - 1);
+        __builtin_amdgcn_wave_barrier();
+        return base + kw + lane;
     };
 
     Real fx = 0, fy = 0, fz = 0;
@@ -1576,14 +1609,14 @@ __global__ __launch_bounds__(WAVE, sizeof(Real) == 4 ? 4 : 3) void k_force(Batch
 #pragma unroll
         for (int q = 0; q < CPT; ++q) {
             const int k = kb + q * WAVE + lane;
-            sj[q] = cand_atom(k);
+            sj[q] = window_atom(kb + q * WAVE);
             ok[q] = k < T && sj[q] != si;
             if (k >= T) sj[q] = si;
         }
 #pragma unroll
         for (int q = 0; q < CPT; ++q) {
-            rj[q] = cd->s_r[sj[q]];
-            pj[q] = cd->s_p[sj[q]];
+            rj[q] = glob(cd->s_r)[sj[q]];
+            pj[q] = glob(cd->s_p)[sj[q]];
         }
 #pragma unroll
         for (int q = 0; q < CPT; ++q) visit(ok[q], rj[q], pj[q]);
@@ -1603,8 +1636,8 @@ __global__ __launch_bounds__(WAVE, sizeof(Real) == 4 ? 4 : 3) void k_force(Batch
     for (int k = 0; k < 5; ++k) pv[k] = wave_sum(pv[k]);
     // stored now, so that nothing of the pair phase stays live below
     if (lane == 0) {
-        cd->f_pair[ai] = make_double4(pv[0], pv[1], pv[2], 0.0);
-        reinterpret_cast<double2 *>(&cd->e_atom[ai])[0] = make_double2(0.5 * pv[3], 0.5 * pv[4]);
+        glob(cd->f_pair)[ai] = make_double4(pv[0], pv[1], pv[2], 0.0);
+        ((gptr<double2>)&glob(cd->e_atom)[ai])[0] = make_double2(0.5 * pv[3], 0.5 * pv[4]);
     }
 
     double e_cav = 0.0, n_exp = -1.0;
@@ -1824,7 +1857,7 @@ __global__ __launch_bounds__(WAVE, sizeof(Real) == 4 ? 4 : 3) void k_force(Batch
             __syncthreads();
 
             // eq F_cav_patch: atom i gains G0_i ev / (N dr) per axis, neighbour j the opposite
-            const long long qf = cd->qfix[ai];
+            const long long qf = glob(cd->qfix)[ai];
             for (int u = lane; u < nnc; u += WAVE) {
                 const unsigned w01 = s_ev01[u];
                 const int e0 = (int)(w01 & 0xffffu) - EV_BIAS, e1 = (int)(w01 >> 16) - EV_BIAS, e2 = s_ev2[u];
@@ -1833,9 +1866,9 @@ __global__ __launch_bounds__(WAVE, sizeof(Real) == 4 ? 4 : 3) void k_force(Batch
                 own0 += e0;
                 own1 += e1;
                 own2 += e2;
-                if (e0) atomicAdd((unsigned long long *)&cd->f_cav[3 * aj + 0], (unsigned long long)(-(long long)e0 * qf));
-                if (e1) atomicAdd((unsigned long long *)&cd->f_cav[3 * aj + 1], (unsigned long long)(-(long long)e1 * qf));
-                if (e2) atomicAdd((unsigned long long *)&cd->f_cav[3 * aj + 2], (unsigned long long)(-(long long)e2 * qf));
+                if (e0) fix_add(&glob(cd->f_cav)[3 * aj + 0], (-(long long)e0 * qf));
+                if (e1) fix_add(&glob(cd->f_cav)[3 * aj + 1], (-(long long)e1 * qf));
+                if (e2) fix_add(&glob(cd->f_cav)[3 * aj + 2], (-(long long)e2 * qf));
             }
         }
         __syncthreads();
@@ -1844,15 +1877,15 @@ __global__ __launch_bounds__(WAVE, sizeof(Real) == 4 ? 4 : 3) void k_force(Batch
         own1 = wave_sum_i(own1);
         own2 = wave_sum_i(own2);
         if (lane == 0) {
-            const long long qf = cd->qfix[ai];
-            if (own0) atomicAdd((unsigned long long *)&cd->f_cav[3 * ai + 0], (unsigned long long)((long long)own0 * qf));
-            if (own1) atomicAdd((unsigned long long *)&cd->f_cav[3 * ai + 1], (unsigned long long)((long long)own1 * qf));
-            if (own2) atomicAdd((unsigned long long *)&cd->f_cav[3 * ai + 2], (unsigned long long)((long long)own2 * qf));
+            const long long qf = glob(cd->qfix)[ai];
+            if (own0) fix_add(&glob(cd->f_cav)[3 * ai + 0], ((long long)own0 * qf));
+            if (own1) fix_add(&glob(cd->f_cav)[3 * ai + 1], ((long long)own1 * qf));
+            if (own2) fix_add(&glob(cd->f_cav)[3 * ai + 2], ((long long)own2 * qf));
         }
-        e_cav = cd->g0[ai] * (double)(N - ncov) / (double)N;  // eq G_cav_patch
+        e_cav = glob(cd->g0)[ai] * (double)(N - ncov) / (double)N;  // eq G_cav_patch
         n_exp = (double)(N - ncov);
     }
-    if (lane == 0) reinterpret_cast<double2 *>(&cd->e_atom[ai])[1] = make_double2(e_cav, n_exp);
+    if (lane == 0) ((gptr<double2>)&glob(cd->e_atom)[ai])[1] = make_double2(e_cav, n_exp);
 }
 
 // ---------------------------------------------------------------------------
