@@ -1069,6 +1069,17 @@ constexpr int NSLOT = (MAX_NBR + WAVE - 1) / WAVE;  // neighbours per lane in st
 // their slots), so acc >> ACC_SHIFT == 1 leaves the single overlapper in the
 // low bits; slots below MAX_NBR keep the slot sum below 2^ACC_SHIFT.
 constexpr int ACC_SHIFT = 17;
+// After the first COMPACT_AT neighbours of the list, the samples of a pass
+// that can still change (fewer than two overlappers so far, or a test inside
+// the FP32 band) move to the leading slots, in sample order, and the others
+// count as covered; the later blocks test only the slots that hold them.
+// Each moves as one word in the unused end of the neighbour list: acc (below
+// 2^STAGE_K: at most COMPACT_AT overlappers), its sample within the pass, and
+// its band flag.
+constexpr int COMPACT_AT = 16;
+constexpr int STAGE_K = 22;
+static_assert(COMPACT_AT * ((1 << ACC_SHIFT) + COMPACT_AT) < (1 << STAGE_K), "staged count field");
+static_assert(WAVE * SPL <= 256 && STAGE_K + 8 < 31, "staged sample field");
 static_assert(MAX_NBR * (MAX_NBR - 1) / 2 < (1 << ACC_SHIFT), "slot sum must stay below the count field");
 static_assert(MAX_NBR * 2 < (1 << (31 - ACC_SHIFT)), "count field must not overflow");
 static_assert((2 * MAX_REACH + 1) * (2 * MAX_REACH + 1) <= WAVE, "stencil rows must fit one wave");
@@ -1718,23 +1729,25 @@ __global__ __launch_bounds__(WAVE, sizeof(Real) == 4 ? 4 : 3) void k_force(Batch
                 // recounted below over the whole list) the rest of the list
                 // cannot change its C, and the slot's tests stop; the block
                 // loop stops when all four slots have.
-                bool live[SPL];
+                // bit i: slot i holds a sample that can still change (wave-uniform)
+                int livem = 0;
 #pragma unroll
                 for (int i = 0; i < SPL; ++i) {
                     // a lane past N starts saturated, so that it never holds
                     // its slot back (its count is not used)
                     if (kb + lane + WAVE * i >= N) acc[i] = 2 << ACC_SHIFT;
-                    live[i] = kb + WAVE * i < N;
+                    if (kb + WAVE * i < N) livem |= 1 << i;
                 }
-                int u = 0;
-                for (; u + SAT_CHECK <= nlist; u += SAT_CHECK) {
+                // one block of SAT_CHECK neighbours from u for the live slots
+                auto block = [&](int u) {
                     NbrEntry<Real> e[SAT_CHECK];
 #pragma unroll
                     for (int q = 0; q < SAT_CHECK; ++q) e[q] = s_nbr[u + q];
-                    bool any_live = false;
+                    int next = 0;
+                    const int lm = __builtin_amdgcn_readfirstlane(livem);
 #pragma unroll
                     for (int i = 0; i < SPL; ++i) {
-                        if (!live[i]) continue;
+                        if (!((lm >> i) & 1)) continue;
                         // 32 per covering neighbour plus its index in the
                         // block (both inline constants of the select); its
                         // count c = blk >> 5 then adds c ((1 << ACC_SHIFT) + u)
@@ -1747,29 +1760,71 @@ __global__ __launch_bounds__(WAVE, sizeof(Real) == 4 ? 4 : 3) void k_force(Batch
                             if (MIXED) amin[i] = fmin(amin[i], fabs(t));
                         }
                         acc[i] += blk + __mul24(blk >> 5, (1 << ACC_SHIFT) + u - 32);
-                        live[i] = __ballot(acc[i] < (2 << ACC_SHIFT)) != 0ull;
-                        any_live = any_live || live[i];
+                        if (__ballot(acc[i] < (2 << ACC_SHIFT))) next |= 1 << i;
                     }
-                    if (!any_live) {
-                        u = nlist;
-                        break;
+                    livem = __builtin_amdgcn_readfirstlane(next);
+                };
+                // kept < 0: slot i of lane l holds sample kb + l + WAVE i;
+                // else the first `kept` staged samples fill the slots in order
+                int kept = -1;
+                const bool can_stage = (nnc * (int)sizeof(NbrEntry<Real>) + WAVE * SPL * (int)sizeof(int)) <=
+                                       MAX_NBR * (int)sizeof(NbrEntry<Real>);
+                int *s_stage = reinterpret_cast<int *>(s_nbr + nnc);
+                int u = 0;
+                for (; livem && u < COMPACT_AT && u + SAT_CHECK <= nlist; u += SAT_CHECK) block(u);
+                if (livem && u == COMPACT_AT && u + SAT_CHECK <= nlist && can_stage) {
+                    int pos = 0;
+#pragma unroll
+                    for (int i = 0; i < SPL; ++i) {
+                        const int kl = lane + WAVE * i;
+                        const bool valid = kb + kl < N;
+                        const bool band = MIXED && amin[i] <= (Real)MIXED_BAND;
+                        const bool keep = valid && (acc[i] < (2 << ACC_SHIFT) || band);
+                        const unsigned long long m = __ballot(keep);
+                        if (keep) s_stage[pos + __popcll(m & below)] = acc[i] | (kl << STAGE_K) | (band ? 1 << 30 : 0);
+                        if (valid && !keep) ++ncov;
+                        pos += __popcll(m);
                     }
+                    kept = __builtin_amdgcn_readfirstlane(pos);
+                    __builtin_amdgcn_wave_barrier();
+                    int next = 0;
+#pragma unroll
+                    for (int i = 0; i < SPL; ++i) {
+                        const int p = lane + WAVE * i;
+                        acc[i] = 2 << ACC_SHIFT;
+                        amin[i] = (Real)1e30;
+                        Qx[i] = Qy[i] = Qz[i] = (Real)0;
+                        if (p < kept) {
+                            const int w = s_stage[p];
+                            acc[i] = w & ((1 << STAGE_K) - 1);
+                            if (w >> 30) amin[i] = (Real)0;
+                            load_q<Real>(cd, kb + ((w >> STAGE_K) & 255), Qx[i], Qy[i], Qz[i]);
+                        }
+                        if (__ballot(acc[i] < (2 << ACC_SHIFT))) next |= 1 << i;
+                    }
+                    livem = __builtin_amdgcn_readfirstlane(next);
                 }
+                for (; livem && u + SAT_CHECK <= nlist; u += SAT_CHECK) block(u);
+                if (!livem) u = nlist;
+                const int lm = __builtin_amdgcn_readfirstlane(livem);
                 for (; u < nlist; ++u) {
                     const NbrEntry<Real> e = s_nbr[u];
                     const int inc = (1 << ACC_SHIFT) + u;
 #pragma unroll
                     for (int i = 0; i < SPL; ++i) {
-                        if (!live[i]) continue;
+                        if (!((lm >> i) & 1)) continue;
                         const Real t = fma(Qz[i], e.az, fma(Qy[i], e.ay, fma(Qx[i], e.ax, -e.c0)));
                         acc[i] += (t >= (Real)0) ? inc : 0;
                         if (MIXED) amin[i] = fmin(amin[i], fabs(t));
                     }
                 }
+                // sample of lane l in slot i
+                auto sample_of = [&](int i, int l) -> int {
+                    return kept < 0 ? kb + l + WAVE * i : kb + ((s_stage[l + WAVE * i] >> STAGE_K) & 255);
+                };
 #pragma unroll
                 for (int i = 0; i < SPL; ++i) {
-                    const int k = kb + lane + WAVE * i;
-                    const bool valid = k < N;
+                    const bool valid = kept < 0 ? kb + lane + WAVE * i < N : lane + WAVE * i < kept;
                     if (MIXED) {
                         // a test within the band of its threshold: the whole wave
                         // recounts that sample in FP64, one lane per neighbour
@@ -1777,7 +1832,7 @@ __global__ __launch_bounds__(WAVE, sizeof(Real) == 4 ? 4 : 3) void k_force(Batch
                         while (bm) {
                             const int l = __ffsll((long long)bm) - 1;
                             bm &= bm - 1;
-                            const int kl = kb + l + WAVE * i;
+                            const int kl = sample_of(i, l);
                             int part = 0;
                             for (int u = lane; u < nnc; u += WAVE)
                                 if (cover_exact(cd, ri, roff_i, kl, s_nbr_a[u], -1)) part += (1 << ACC_SHIFT) + u;
@@ -1788,6 +1843,7 @@ __global__ __launch_bounds__(WAVE, sizeof(Real) == 4 ? 4 : 3) void k_force(Batch
                     const int C = acc[i] >> ACC_SHIFT;
                     if (valid && C == 1) {
                         // critically overlapped: only the overlapper's shifted copies can expose it
+                        const int k = sample_of(i, lane);
                         const int u = acc[i] & ((1 << ACC_SHIFT) - 1);
                         const NbrEntry<Real> e = s_nbr[u];
                         const int aj = s_nbr_a[u];
@@ -1838,7 +1894,7 @@ __global__ __launch_bounds__(WAVE, sizeof(Real) == 4 ? 4 : 3) void k_force(Batch
                                     d1 -= v1 >= (Real)0;
                                     d2 -= v2 >= (Real)0;
                                     if (MIXED && band3((float)v0, (float)v1, (float)v2)) {
-                                        const int kx = kb + l + WAVE * i;
+                                        const int kx = sample_of(i, l);
                                         d0 += redo((float)v0, cd, ri, roff_i, kx, aj, 0);
                                         d1 += redo((float)v1, cd, ri, roff_i, kx, aj, 1);
                                         d2 += redo((float)v2, cd, ri, roff_i, kx, aj, 2);
