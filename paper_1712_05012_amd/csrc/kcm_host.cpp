@@ -156,7 +156,7 @@ std::vector<V3> sample_directions(int n_orb)
 struct Layout {
     size_t desc, stats, grid, theta, dtheta, tau, mc_theta, mask, joint0, jcur, xform, xform_loc, blk_xf, tmax_part, bad_part;
     size_t r0, r, aparam, g0, qfix;
-    size_t cell_key, cell_count, cell_start, cell_local, scan_part, bbox_part, wrench_part, s_r, s_p, s_tmp, s_idx, s_cell;
+    size_t cell_key, cell_count, cell_start, cell_local, scan_part, bbox_part, wrench_part, s_r, s_p, s_tmp, s_idx;
     size_t f_pair, f_cav;
     size_t e_atom;
     size_t q64, q32;
@@ -221,7 +221,6 @@ Layout make_layout(int m, int n_orb, int side_chains)
     l.s_p = take(32 * n);
     l.s_tmp = take(4 * n);
     l.s_idx = take(4 * n);
-    l.s_cell = take(4 * n);
     l.f_pair = take(32 * n);
     l.f_cav = take(24 * n);
     l.e_atom = take(32 * n);
@@ -745,7 +744,6 @@ kcm_status kcm_build_chain(const kcm_chain_desc *desc, const kcm_params *params,
     PTR(s_p, double4 *);
     PTR(s_tmp, int32_t *);
     PTR(s_idx, int32_t *);
-    PTR(s_cell, int32_t *);
     PTR(f_pair, double4 *);
     PTR(f_cav, long long *);
     PTR(e_atom, double4 *);

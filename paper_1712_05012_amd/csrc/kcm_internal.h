@@ -100,7 +100,6 @@ struct ChainDev {
     double4 *s_p;        // [n] parameters in cell order
     int32_t *s_tmp;      // [n] scatter order (before the stable rank)
     int32_t *s_idx;      // [n] atom of each sorted slot (the cell order)
-    int32_t *s_cell;     // [n] cell of each sorted slot
     double4 *f_pair;     // [n] Coulomb + LJ force
     long long *f_cav;    // [3n] solvation force, fixed point
     double4 *e_atom;     // [n] (elec, vdw, cav, exposed samples) per atom

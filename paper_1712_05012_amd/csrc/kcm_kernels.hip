@@ -918,14 +918,13 @@ __device__ void chunk_offsets(const ChainDev *cd, int nc, int *s_off, int *s_int
 // number of atoms of the cell with a smaller index, so everything downstream
 // is deterministic.  Gathers position (with the atom index in w) and
 // parameters into that slot.
-__device__ __forceinline__ void place_sorted(const ChainDev *cd, const int *ids, int a, int key, int b, int e)
+__device__ __forceinline__ void place_sorted(const ChainDev *cd, const int *ids, int a, int b, int e)
 {
     int rank = 0;
     for (int s = b; s < e; ++s) rank += ids[s] < a ? 1 : 0;
     const int pos = b + rank;
     const double4 r = cd->r[a];
     cd->s_idx[pos] = a;
-    cd->s_cell[pos] = key;
     cd->s_r[pos] = make_double4(r.x, r.y, r.z, __longlong_as_double((long long)a));
     cd->s_p[pos] = cd->aparam[a];
 }
@@ -1011,7 +1010,7 @@ __global__ __launch_bounds__(ATOM_BLOCK) void k_rank(Batch bt)
     const int key = cd->cell_key[a];
     const int b = cd->cell_local[key] + s_off[key / SCAN_CHUNK];
     const int e = key + 1 < nc ? cd->cell_local[key + 1] + s_off[(key + 1) / SCAN_CHUNK] : s_off[nb];
-    place_sorted(cd, cd->s_tmp, a, key, b, e);
+    place_sorted(cd, cd->s_tmp, a, b, e);
 }
 
 // Loads, stores and atomics through a pointer of unknown address space are
@@ -1461,10 +1460,16 @@ __global__ __launch_bounds__(WAVE, sizeof(Real) == 4 ? 4 : 3) void k_force(Batch
     const double4 ri = glob(cd->s_r)[si];
     const double4 pi = glob(cd->s_p)[si];
     const int ai = (int)__double_as_longlong(ri.w);
-    const int key = glob(cd->s_cell)[si];
     const int dxn = g.dims[0], dyn = g.dims[1], dzn = g.dims[2];
-    const int cx = key % dxn, cy = (key / dxn) % dyn, cz = key / (dxn * dyn);
+    // the atom's cell, by the expression that sorted it (no key decoding)
+    const int cx = min(max((int)floor((ri.x - g.origin[0]) * g.inv_cell), 0), dxn - 1);
+    const int cy = min(max((int)floor((ri.y - g.origin[1]) * g.inv_cell), 0), dyn - 1);
+    const int cz = min(max((int)floor((ri.z - g.origin[2]) * g.inv_cell), 0), dzn - 1);
     const int R = g.reach, side = 2 * R + 1, nrows = side * side;
+    // lane = row_z * side + row_y; side <= 8 and lane < 64 keep the FP32
+    // quotient at least 1/16 away from an integer, far above its rounding
+    const int row_z = (int)(((float)lane + 0.5f) * __builtin_amdgcn_rcpf((float)side));
+    const int row_y = lane - row_z * side;
 
     // stencil rows, one per lane: for each (dy, dz) one contiguous run of
     // cells along x, i.e. one contiguous run of the cell-ordered atoms.  The
@@ -1475,7 +1480,7 @@ __global__ __launch_bounds__(WAVE, sizeof(Real) == 4 ? 4 : 3) void k_force(Batch
     // clamped into them); the pad on the reach absorbs rounding.
     int beg = 0, cnt = 0;
     if (lane < nrows) {
-        const int y = cy + (lane % side) - R, z = cz + (lane / side) - R;
+        const int y = cy + row_y - R, z = cz + row_z - R;
         if (y >= 0 && y < dyn && z >= 0 && z < dzn) {
             const double reach = g.reach_len + 1e-6;
             const double ylo = y == 0 ? -DBL_MAX : g.origin[1] + y * g.cell;
