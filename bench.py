@@ -283,11 +283,14 @@ def run_per_chain_fp64(steps: int, n_sample: int = 16, n_chains: int = 256):
             "one chain per call"}
 
 
-def run_serving(n_jobs: int, max_iter: int, budget_gib: float, skip: int):
+def run_serving(n_jobs: int, max_iter: int, budget_gib: float, skip: int, setting=(0.0, 0)):
     """Poisson arrivals at 50 jobs/s, lognormal lengths; continuous batching by HBM budget.
 
     Latency percentiles leave out the first ``skip`` jobs (warm-up); the queue
-    growth rate says whether one GPU keeps up with the offered load."""
+    growth rate says whether one GPU keeps up with the offered load.  The jobs
+    run with ``setting`` = (cell edge, force-kernel shape), by default the
+    automatic cell edge and shape 0; the full run passes the setting the batch
+    leg tuned on random coils of the same kind."""
     import numpy as np
 
     import synth
@@ -302,17 +305,21 @@ def run_serving(n_jobs: int, max_iter: int, budget_gib: float, skip: int):
         js = seed + 1000 * (k + 1)
         jobs.append(Job(job_id=k, res_type=synth.sequence(int(m), js), theta0=synth.random_dihedrals(int(m), js),
                         arrival=float(a), tol=1e-4, max_iter=max_iter))
-    eng = KcmEngine(T, kcm.kcm_default_params(precision=kcm.KCM_MIXED))
+    eng = KcmEngine(T, kcm.kcm_default_params(precision=kcm.KCM_MIXED, cell_size=setting[0]))
     svc = FoldService(eng, hbm_budget=int(budget_gib * (1 << 30)), max_slots=1024, check_every=20)
     def progress(job, n_done):
         if n_done % 250 == 0 or n_done == n_jobs:
             print(f"serving: {n_done} of {n_jobs} jobs done", file=sys.stderr, flush=True)
 
-    st = svc.run(jobs, on_retire=progress)
+    kcm.kcm_set_force_variant(setting[1])
+    try:
+        st = svc.run(jobs, on_retire=progress)
+    finally:
+        kcm.kcm_set_force_variant(0)
     out = st.summary(skip=min(skip, max(0, n_jobs - 1)))
     offered = 50.0 * 10.0 * float(np.mean(lengths)) * max_iter
     out.update({"arrival_rate_per_s": 50.0, "max_iter": max_iter, "tol_dtheta": 1e-4,
-                "hbm_budget_gib": budget_gib,
+                "hbm_budget_gib": budget_gib, "cell_size": setting[0], "force_variant": setting[1],
                 "offered_atom_steps_per_s_at_iteration_cap": offered,
                 "note": "latency is finish minus arrival and includes queueing; a positive queue "
                         "growth means the offered load exceeds what one GPU serves"})
@@ -562,6 +569,7 @@ def main():
         print(f"bench: {msg}", file=sys.stderr, flush=True)
 
     line = {}
+    serve_setting = (0.0, 0)
     if "batch" in legs:
         setting = None
         if args.batch_setting:
@@ -607,6 +615,7 @@ def main():
             line["full_run"] = b["full_run"]
         if "autotune" in b:
             line["autotune"] = b["autotune"]
+        serve_setting = (b["cell_size"], b["force_variant"])
         fp64 = run_per_chain_fp64(10)
         line["plain_fp64_per_chain"] = fp64
         line["speedup_vs_plain_fp64_per_chain"] = b["value"] / fp64["value"]
@@ -624,7 +633,7 @@ def main():
     if sub:
         line["legs"] = sub
     if "serving" in legs:
-        line["serving"] = run_serving(args.serve_jobs, args.serve_max_iter, 64.0, args.serve_warmup)
+        line["serving"] = run_serving(args.serve_jobs, args.serve_max_iter, 64.0, args.serve_warmup, serve_setting)
         progress("serving done")
     if "landscape" in legs:
         line["landscape"] = run_landscape()
