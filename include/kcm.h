@@ -50,8 +50,13 @@ typedef enum {
     KCM_E_NUMERIC = -4,  /* NaN/Inf in this chain's forces or torques */
     KCM_E_STATE = -5,    /* call not valid in the handle's current state */
     KCM_E_CAPACITY = -6  /* an atom has 131072 or more solvation neighbours (the force
-                            kernel takes any smaller count, in LDS chunks of 352) */
+                            kernel takes any smaller count, in LDS chunks of
+                            KCM_NBR_CHUNK) */
 } kcm_status;
+
+/* Solvation neighbours of one atom that the force kernel holds in LDS at once;
+ * an atom with more is processed in chunks of this many (same results). */
+#define KCM_NBR_CHUNK 240
 
 enum { KCM_STEP_CAPPED = 0, KCM_STEP_PAPER = 1, KCM_STEP_LINEAR = 2 };
 enum { KCM_FP64 = 0, KCM_MIXED = 1 };
@@ -303,10 +308,10 @@ kcm_status kcm_set_graphs(int iterations);
 
 /* Launch shape of the force kernel (process-wide), for the autotuner:
  * 0 (default): each lane loads two candidates per trip of the candidate loop,
- * and step 1 reads the solvation neighbours in blocks of 8 before it checks
- * which sample slots are done; 1: four candidates per trip, blocks of 8;
- * 2: two candidates, blocks of 4; 3: as 0, with the atoms handed to the 8
- * XCDs in contiguous eighths (XCD-aware order).  Every shape gives identical
+ * and step 1 reads the solvation neighbours in blocks of 4 before it checks
+ * which sample slots are done; 1: one candidate per trip, blocks of 4;
+ * 2: as 1, and 3: as 0, with the atoms handed to the 8 XCDs in contiguous
+ * eighths (XCD-aware order).  Every shape gives identical
  * results (the same visiting order and decisions).  Graphs captured in
  * another shape are captured again.  KCM_E_INVAL unless
  * 0 <= variant < KCM_FORCE_VARIANTS. */

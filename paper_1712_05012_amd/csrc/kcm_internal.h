@@ -3,6 +3,8 @@
 // (kcm_kernels.hip).  Not part of the public ABI.
 #pragma once
 
+#include "../../include/kcm.h"
+
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -13,8 +15,8 @@ constexpr int CHAIN_THREADS = 1024;  // one workgroup per chain: 16 waves
 constexpr int SCAN_CHUNK = 16384;    // cells per workgroup of the cell-count scan
 constexpr int SCAN_MAX_CHUNKS = 4096;  // chunks per chain the scatter's offset table holds
 constexpr int JOINT_BLOCK = 256;     // joints per workgroup of the torque / step / kinematics kernels
-constexpr int MAX_NBR = 352;         // solvation neighbours of one atom kept in LDS (the list, its atoms
-                                     // and its events, 9,856 bytes, let 16 waves share a CU)
+constexpr int MAX_NBR = KCM_NBR_CHUNK; // solvation neighbours of one atom kept in LDS (the list, its atoms
+                                      // and its events, 6,720 bytes, let 24 waves share a CU)
 constexpr int MAX_REACH = 3;         // cell-stencil half width the force kernel supports (cells >= reach/3)
 constexpr double FIX_SCALE = 4294967296.0;  // fixed-point units per kcal/mol/A (2^32)
 constexpr int WPART = 10;            // doubles per wrench partial: F(3), T(3), E(3), flag

@@ -1044,6 +1044,19 @@ struct NbrEntry {
     Real ax, ay, az, c0;
 };
 
+// Squared distance and cap threshold of a candidate, with the fused steps
+// written out: every path and launch shape that takes them rounds alike.
+__device__ __forceinline__ double dist2(double dx, double dy, double dz)
+{
+#pragma clang fp contract(off)
+    return fma(dz, dz, fma(dy, dy, dx * dx));
+}
+__device__ __forceinline__ double cap_c0(double roff_i, double d2, double rj, double inv_2roff)
+{
+#pragma clang fp contract(off)
+    return fma(-rj, rj, fma(roff_i, roff_i, d2)) * inv_2roff;
+}
+
 constexpr int SPL = 4;                              // samples per lane in one pass: passes of 256 samples
 // Neighbours whose cap on the offset sphere is large (cosine of its angular
 // radius, c0/|a|, below CAP_SPLIT) lead the list: step 1 then reaches two
@@ -1061,7 +1074,7 @@ struct ForceShape {
     int cpt, satb;
     bool xcd;
 };
-constexpr ForceShape FORCE_SHAPES[] = {{2, 8, false}, {4, 8, false}, {2, 4, false}, {2, 8, true}};
+constexpr ForceShape FORCE_SHAPES[] = {{2, 4, false}, {1, 4, false}, {1, 4, true}, {2, 4, true}};
 constexpr int N_XCD = 8;
 constexpr int NSLOT = (MAX_NBR + WAVE - 1) / WAVE;  // neighbours per lane in step 2
 // Step-1 count of a sample: acc = (covering neighbours << ACC_SHIFT) + (sum of
@@ -1189,7 +1202,7 @@ __device__ __noinline__ PairSums pair_terms_fp64(CDev cd, int si, int off, int r
         const double4 rj = glob(cd->s_r)[sj];
         const double4 pj = glob(cd->s_p)[sj];
         const double ddx = rj.x - ri.x, ddy = rj.y - ri.y, ddz = rj.z - ri.z;
-        const double d2 = ddx * ddx + ddy * ddy + ddz * ddz;
+        const double d2 = dist2(ddx, ddy, ddz);
         if (!(ok && d2 <= cut2)) continue;
         const int aj = (int)__double_as_longlong(rj.w);
         const int res_j = aj / APR, dres = res_j - res_i;
@@ -1278,7 +1291,7 @@ __device__ __noinline__ ChunkedSasa sasa_chunked(CDev cd, const ChunkArgs c, Nbr
             const double4 rj = glob(cd->s_r)[sj];
             const double4 pj = glob(cd->s_p)[sj];
             const double ddx = rj.x - a.ri.x, ddy = rj.y - a.ri.y, ddz = rj.z - a.ri.z;
-            const double d2 = ddx * ddx + ddy * ddy + ddz * ddz;
+            const double d2 = dist2(ddx, ddy, ddz);
             const double lim = a.roff_i + pj.w + a.dr;
             const bool in_cav = valid && d2 <= lim * lim;
             const unsigned long long m = __ballot(in_cav);
@@ -1287,7 +1300,7 @@ __device__ __noinline__ ChunkedSasa sasa_chunked(CDev cd, const ChunkArgs c, Nbr
                 if (pos >= 0 && pos < len) {
                     NbrEntry<Real> e;
                     e.ax = (Real)ddx; e.ay = (Real)ddy; e.az = (Real)ddz;
-                    e.c0 = (Real)((a.roff_i * a.roff_i + d2 - pj.w * pj.w) * a.inv_2roff);
+                    e.c0 = (Real)cap_c0(a.roff_i, d2, pj.w, a.inv_2roff);
                     s_nbr[pos] = e;
                     s_nbr_a[pos] = (int)__double_as_longlong(rj.w);
                 }
@@ -1431,10 +1444,12 @@ __device__ __noinline__ ChunkedSasa sasa_chunked(CDev cd, const ChunkArgs c, Nbr
     return out;
 }
 
-// Mixed form: four waves per SIMD, the register budget (128) it fits in.  The
-// FP64 form's LDS list already limits it to fewer waves.
+// Mixed form: six waves per SIMD (80 registers, the 6,720-byte LDS list), which
+// hides the latency of the candidate loads and LDS reads better than four
+// waves with room to spare (3.06 against 3.39 ms on the 256-chain batch);
+// seven spill in the hot loops.  The FP64 form needs 167 registers: three.
 template <typename Real, int CPT, int SAT_CHECK, bool XCD>
-__global__ __launch_bounds__(WAVE, sizeof(Real) == 4 ? 4 : 3) void k_force(Batch bt)
+__global__ __launch_bounds__(WAVE, sizeof(Real) == 4 ? 6 : 3) void k_force(Batch bt)
 {
     static_assert(SAT_CHECK * (SAT_CHECK - 1) / 2 < 32 && 32 + SAT_CHECK <= 64, "block code of step 1");
     constexpr bool MIXED = sizeof(Real) == 4;
@@ -1559,8 +1574,11 @@ __global__ __launch_bounds__(WAVE, sizeof(Real) == 4 ? 4 : 3) void k_force(Batch
     // neighbour with a large cap is appended at the front of the list, any
     // other at its back (growing down from MAX_NBR - 1), in lane order
     auto visit = [&](bool valid, const double4 &rj, const double4 &pj) {
+        // contraction off, the fused steps written out: the loop bodies of
+        // all launch shapes round alike
+#pragma clang fp contract(off)
         const double ddx = rj.x - ri.x, ddy = rj.y - ri.y, ddz = rj.z - ri.z;
-        const double d2 = ddx * ddx + ddy * ddy + ddz * ddz;
+        const double d2 = dist2(ddx, ddy, ddz);
         const int aj = (int)__double_as_longlong(rj.w);
         if (valid && do_pair && d2 <= cut2) {
             const int res_j = aj / APR, dres = res_j - res_i;
@@ -1581,12 +1599,12 @@ __global__ __launch_bounds__(WAVE, sizeof(Real) == 4 ? 4 : 3) void k_force(Batch
                 const Real D = Ri + (Real)pj.y;
                 const Real s2 = D * D * inv2, s6 = s2 * s2 * s2, s12 = s6 * s6;
                 const Real eij = sei * (Real)pj.z;
-                const Real elj = wv * eij * (s12 - (Real)2 * s6);
+                const Real elj = wv * eij * fma((Real)-2, s6, s12);
                 // |F|/d along r_i - r_j: 2 E_elec/d^2 + 12 eps (s12 - s6)/d^2
-                const Real fsc = ((Real)2 * eel + (Real)12 * wv * eij * (s12 - s6)) * inv2;
-                fx -= fsc * rx;
-                fy -= fsc * ry;
-                fz -= fsc * rz;
+                const Real fsc = fma((Real)2, eel, (Real)12 * wv * eij * (s12 - s6)) * inv2;
+                fx = fma(-fsc, rx, fx);
+                fy = fma(-fsc, ry, fy);
+                fz = fma(-fsc, rz, fz);
                 ee += (double)eel;
                 evw += (double)elj;
             }
@@ -1597,7 +1615,7 @@ __global__ __launch_bounds__(WAVE, sizeof(Real) == 4 ? 4 : 3) void k_force(Batch
             const double Rj = pj.w;
             const double lim = roff_i + Rj + dr;
             in_cav = valid && d2 <= lim * lim;
-            c0 = (roff_i * roff_i + d2 - Rj * Rj) * inv_2roff;
+            c0 = cap_c0(roff_i, d2, Rj, inv_2roff);
             front = c0 < 0.0 || c0 * c0 < (CAP_SPLIT * CAP_SPLIT) * d2;
         }
         const unsigned long long mf = __ballot(in_cav && front), mb = __ballot(in_cav && !front);

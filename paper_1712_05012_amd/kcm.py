@@ -27,7 +27,9 @@ EXPORTED = ("kcm_default_params", "kcm_chain_bytes", "kcm_build_chain", "kcm_ste
             "kcm_set_limits", "kcm_set_graphs", "kcm_mc_minimize", "kcm_mc_best_theta", "kcm_set_theta_batch",
             "kcm_step_noalloc", "kcm_set_force_variant")
 KCM_FORCE_VARIANTS = 4
+KCM_NBR_CHUNK = 240
 KCM_NOALLOC_MAX_CHAINS = 1024
+KCM_NOALLOC_SCRATCH_BYTES = 262144
 
 
 class KcmError(RuntimeError):

@@ -28,6 +28,14 @@ def test_every_declared_symbol_is_exported():
     assert set(names) == set(kcm.EXPORTED)
 
 
+def test_header_constants_are_mirrored():
+    src = open(os.path.join(ROOT, "include", "kcm.h")).read()
+    defines = dict(re.findall(r"^#define (KCM_[A-Z0-9_]+) (\d+)\s*$", src, flags=re.M))
+    assert {"KCM_NBR_CHUNK", "KCM_FORCE_VARIANTS", "KCM_NOALLOC_MAX_CHAINS"} <= set(defines)
+    for name, value in defines.items():
+        assert getattr(kcm, name) == int(value), name
+
+
 def test_default_params_match_header():
     p = kcm.kcm_default_params()
     assert (p.cutoff, p.kappa, p.max_step, p.n_orbits) == (10.0, 1e-3, 1e-3, 14)

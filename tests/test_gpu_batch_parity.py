@@ -22,7 +22,7 @@ pytestmark = pytest.mark.gpu
 N_BATCH = 256
 CHECKED = [0, 1, 2, 3, 64, 65, 127, 128, 129, 190, 191, 252, 253, 254, 255, 256]
 # job 1792 of the serving stream (304 residues): one atom has 418 solvation
-# neighbours at the start, more than one LDS list of 352
+# neighbours at the start, more than one LDS list (KCM_NBR_CHUNK)
 OVERFLOW_M = 304
 OVERFLOW_SEED = synth.config_seed(5) + 1000 * (1792 + 1)
 
@@ -93,7 +93,7 @@ def test_batch_of_random_coils_in_its_launch_form_matches_oracle():
     roff = refs[N_BATCH].R + p.r_probe
     d = np.sqrt(((r0[:, None, :] - r0[None, :, :]) ** 2).sum(-1))
     np.fill_diagonal(d, np.inf)
-    assert int((d <= roff[:, None] + roff[None, :] + p.delta_r).sum(axis=1).max()) > 352
+    assert int((d <= roff[:, None] + roff[None, :] + p.delta_r).sum(axis=1).max()) > kcm.KCM_NBR_CHUNK
     chains = []
     try:
         kcm.kcm_set_graphs(8)

@@ -77,9 +77,9 @@ def _max_solvation_neighbours(ref, r, p):
 
 
 # A random-dihedral start with a dense self-overlap: one atom has more
-# solvation neighbours (418) than the kernel's LDS list holds (352), so its
-# neighbours are processed in two chunks.  The chain is job 1792 of the
-# serving stream (304 residues).
+# solvation neighbours (418) than the kernel's LDS list holds
+# (KCM_NBR_CHUNK), so its neighbours are processed in two chunks.  The chain
+# is job 1792 of the serving stream (304 residues).
 OVERFLOW_M = 304
 OVERFLOW_SEED = synth.config_seed(5) + 1000 * (1792 + 1)
 
@@ -90,7 +90,7 @@ def test_neighbour_list_overflow_is_processed_in_chunks(precision):
     gpu, ref, th = build_pair(OVERFLOW_M, OVERFLOW_SEED, p)
     r0 = oracle.fk(ref, th)[0]
     nmax = _max_solvation_neighbours(ref, r0, p)
-    assert nmax > 352
+    assert nmax > kcm.KCM_NBR_CHUNK
     st, o, err = compare_step(gpu, ref, th, p)
     _log(case="nbr_overflow", precision=precision, max_neighbours=nmax, **err)
     assert err["status"] == 0
