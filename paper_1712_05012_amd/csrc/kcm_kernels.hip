@@ -1635,7 +1635,10 @@ __global__ __launch_bounds__(WAVE, sizeof(Real) == 4 ? 6 : 3) void k_force(Batch
         nn += cf + cb;
     };
 
-    // CPT candidates per lane per trip, every load issued before any is used
+    // CPT candidates per lane per trip, every load issued before any is used.
+    // Loads take 32-bit byte offsets from the chain's arrays (n < 2^26 atoms
+    // of 32 bytes).
+    const gptr<const char> sr = (gptr<const char>)glob(cd->s_r), sp = (gptr<const char>)glob(cd->s_p);
     for (int kb = 0; kb < T; kb += CPT * WAVE) {
         int sj[CPT];
         bool ok[CPT];
@@ -1649,8 +1652,9 @@ __global__ __launch_bounds__(WAVE, sizeof(Real) == 4 ? 6 : 3) void k_force(Batch
         }
 #pragma unroll
         for (int q = 0; q < CPT; ++q) {
-            rj[q] = glob(cd->s_r)[sj[q]];
-            pj[q] = glob(cd->s_p)[sj[q]];
+            const unsigned ob = (unsigned)sj[q] * (unsigned)sizeof(double4);
+            rj[q] = *(const gptr<const double4>)(sr + ob);
+            pj[q] = *(const gptr<const double4>)(sp + ob);
         }
 #pragma unroll
         for (int q = 0; q < CPT; ++q) visit(ok[q], rj[q], pj[q]);
