@@ -1447,9 +1447,10 @@ __device__ __noinline__ ChunkedSasa sasa_chunked(CDev cd, const ChunkArgs c, Nbr
 // Mixed form: six waves per SIMD (80 registers, the 6,720-byte LDS list), which
 // hides the latency of the candidate loads and LDS reads better than four
 // waves with room to spare (3.06 against 3.39 ms on the 256-chain batch);
-// seven spill in the hot loops.  The FP64 form needs 167 registers: three.
+// seven spill in the hot loops.  The FP64 form: four (127 registers; its
+// 10,560-byte list allows 15 waves per CU).
 template <typename Real, int CPT, int SAT_CHECK, bool XCD>
-__global__ __launch_bounds__(WAVE, sizeof(Real) == 4 ? 6 : 3) void k_force(Batch bt)
+__global__ __launch_bounds__(WAVE, sizeof(Real) == 4 ? 6 : 4) void k_force(Batch bt)
 {
     static_assert(SAT_CHECK * (SAT_CHECK - 1) / 2 < 32 && 32 + SAT_CHECK <= 64, "block code of step 1");
     constexpr bool MIXED = sizeof(Real) == 4;
