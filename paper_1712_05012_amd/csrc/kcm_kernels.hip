@@ -1051,6 +1051,11 @@ __device__ __forceinline__ double dist2(double dx, double dy, double dz)
 #pragma clang fp contract(off)
     return fma(dz, dz, fma(dy, dy, dx * dx));
 }
+// set bits of m in the lanes below this one (the hardware's masked bit count)
+__device__ __forceinline__ int count_below(unsigned long long m)
+{
+    return (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+}
 __device__ __forceinline__ double cap_c0(double roff_i, double d2, double rj, double inv_2roff)
 {
 #pragma clang fp contract(off)
@@ -1252,7 +1257,6 @@ __device__ __noinline__ ChunkedSasa sasa_chunked(CDev cd, const ChunkArgs c, Nbr
 {
     constexpr bool MIXED = sizeof(Real) == 4;
     const int lane = threadIdx.x & (WAVE - 1);
-    const unsigned long long below = (1ull << lane) - 1ull;
     // the atom's quantities, read again rather than passed (the call then
     // keeps few of the kernel's registers live)
     struct {
@@ -1296,7 +1300,7 @@ __device__ __noinline__ ChunkedSasa sasa_chunked(CDev cd, const ChunkArgs c, Nbr
             const bool in_cav = valid && d2 <= lim * lim;
             const unsigned long long m = __ballot(in_cav);
             if (in_cav) {
-                const int pos = nb + __popcll(m & below) - lo;
+                const int pos = nb + count_below(m) - lo;
                 if (pos >= 0 && pos < len) {
                     NbrEntry<Real> e;
                     e.ax = (Real)ddx; e.ay = (Real)ddy; e.az = (Real)ddz;
@@ -1470,7 +1474,6 @@ __global__ __launch_bounds__(WAVE, sizeof(Real) == 4 ? 6 : 4) void k_force(Batch
     if (!running(cd->stats)) return;
     const int si = atom - bt.atom_off[c];
     const int lane = threadIdx.x;
-    const unsigned long long below = (1ull << lane) - 1ull;
 
     const Grid g = *glob(cd->grid);
     const double4 ri = glob(cd->s_r)[si];
@@ -1553,14 +1556,14 @@ __global__ __launch_bounds__(WAVE, sizeof(Real) == 4 ? 6 : 4) void k_force(Batch
     // never matches, since it holds that window's candidate number.
     int2 *s_head = reinterpret_cast<int2 *>(s_ev01);
     s_head[lane] = make_int2(-1, 0);
-    const unsigned long long upto = below | (1ull << lane);
     int carry = 0;
     auto window_atom = [&](int kw) -> int {
         if (cnt > 0 && off >= kw && off < kw + WAVE) s_head[off - kw] = make_int2(off, rbase);
         __builtin_amdgcn_wave_barrier();
         const int2 h = s_head[lane];
-        const unsigned long long m = __ballot(h.x == kw + lane) & upto;
-        const int p = m ? 63 - __clzll((long long)m) : lane;
+        // the last start at or below this lane: its bit moved to the top
+        const unsigned long long m = __ballot(h.x == kw + lane) << (63 - lane);
+        const int p = m ? lane - __clzll((long long)m) : lane;
         const int rb = __shfl(h.y, p, WAVE);
         const int base = m ? rb : carry;
         carry = __builtin_amdgcn_readlane(base, WAVE - 1);
@@ -1624,7 +1627,7 @@ __global__ __launch_bounds__(WAVE, sizeof(Real) == 4 ? 6 : 4) void k_force(Batch
         // past the list's capacity nothing more is written: the atom then
         // takes the chunked path, which enumerates its neighbours again
         if (in_cav && nfront + cf + nback + cb <= MAX_NBR) {
-            const int pos = front ? nfront + __popcll(mf & below) : MAX_NBR - 1 - nback - __popcll(mb & below);
+            const int pos = front ? nfront + count_below(mf) : MAX_NBR - 1 - nback - count_below(mb);
             NbrEntry<Real> e;
             e.ax = (Real)ddx; e.ay = (Real)ddy; e.az = (Real)ddz;
             e.c0 = (Real)c0;
@@ -1720,15 +1723,23 @@ __global__ __launch_bounds__(WAVE, sizeof(Real) == 4 ? 6 : 4) void k_force(Batch
             const int nf = __builtin_amdgcn_readfirstlane(nfront);
             for (int c = 0; c < nb_back; c += WAVE) {
                 const int v = c + lane;
-                NbrEntry<Real> e;
+                // component by component, so that the entry stays in registers
+                Real ex = 0, ey = 0, ez = 0, ec = 0;
                 int a = 0;
                 if (v < nb_back) {
-                    e = s_nbr[MAX_NBR - nb_back + v];
-                    a = s_nbr_a[MAX_NBR - nb_back + v];
+                    const int src = MAX_NBR - nb_back + v;
+                    ex = s_nbr[src].ax;
+                    ey = s_nbr[src].ay;
+                    ez = s_nbr[src].az;
+                    ec = s_nbr[src].c0;
+                    a = s_nbr_a[src];
                 }
                 __syncthreads();
                 if (v < nb_back) {
-                    s_nbr[nf + v] = e;
+                    s_nbr[nf + v].ax = ex;
+                    s_nbr[nf + v].ay = ey;
+                    s_nbr[nf + v].az = ez;
+                    s_nbr[nf + v].c0 = ec;
                     s_nbr_a[nf + v] = a;
                 }
                 __syncthreads();
@@ -1809,7 +1820,7 @@ __global__ __launch_bounds__(WAVE, sizeof(Real) == 4 ? 6 : 4) void k_force(Batch
                         const bool band = MIXED && amin[i] <= (Real)MIXED_BAND;
                         const bool keep = valid && (acc[i] < (2 << ACC_SHIFT) || band);
                         const unsigned long long m = __ballot(keep);
-                        if (keep) s_stage[pos + __popcll(m & below)] = acc[i] | (kl << STAGE_K) | (band ? 1 << 30 : 0);
+                        if (keep) s_stage[pos + count_below(m)] = acc[i] | (kl << STAGE_K) | (band ? 1 << 30 : 0);
                         if (valid && !keep) ++ncov;
                         pos += __popcll(m);
                     }
@@ -1818,7 +1829,8 @@ __global__ __launch_bounds__(WAVE, sizeof(Real) == 4 ? 6 : 4) void k_force(Batch
                     int next = 0;
 #pragma unroll
                     for (int i = 0; i < SPL; ++i) {
-                        const int p = lane + WAVE * i;
+                        int p = lane + WAVE * i;
+                        asm volatile("" : "+v"(p));  // recomputed here, not kept (and spilled) from the pass start
                         acc[i] = 2 << ACC_SHIFT;
                         amin[i] = (Real)1e30;
                         Qx[i] = Qy[i] = Qz[i] = (Real)0;
@@ -1848,7 +1860,10 @@ __global__ __launch_bounds__(WAVE, sizeof(Real) == 4 ? 6 : 4) void k_force(Batch
                 }
                 // sample of lane l in slot i
                 auto sample_of = [&](int i, int l) -> int {
-                    return kept < 0 ? kb + l + WAVE * i : kb + ((s_stage[l + WAVE * i] >> STAGE_K) & 255);
+                    if (kept < 0) return kb + l + WAVE * i;
+                    int p = l + WAVE * i;
+                    asm volatile("" : "+v"(p));  // computed at the (rare) use, not kept from the pass start
+                    return kb + ((s_stage[p] >> STAGE_K) & 255);
                 };
 #pragma unroll
                 for (int i = 0; i < SPL; ++i) {
@@ -1901,7 +1916,9 @@ __global__ __launch_bounds__(WAVE, sizeof(Real) == 4 ? 6 : 4) void k_force(Batch
 #pragma unroll
                         for (int v = 0; v < NSLOT; ++v) {
                             if (WAVE * v >= nnc) break;
-                            const int u = lane + WAVE * v;
+                            int u = lane + WAVE * v;
+                            // opaque to hoisting: recomputed per pass, not kept (and spilled) across them
+                            asm volatile("" : "+v"(u));
                             const bool own = u < nnc;
                             const NbrEntry<Real> e = s_nbr[own ? u : 0];
                             const int aj = s_nbr_a[own ? u : 0];
