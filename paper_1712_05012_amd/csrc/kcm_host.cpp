@@ -310,6 +310,7 @@ hipError_t launch_iteration(const Batch &bt, int prec, hipStream_t stream, const
     if ((e = launch_tau(bt, stream)) != hipSuccess) return e;
     if ((e = launch_stepfk(bt, MODE_ITER, stream)) != hipSuccess) return e;
     if ((e = launch_place(bt, MODE_ITER, stream)) != hipSuccess) return e;
+    if ((e = launch_cellkey(bt, stream)) != hipSuccess) return e;
     if ((e = launch_cellscan(bt, stream)) != hipSuccess) return e;
     if ((e = launch_scatter(bt, stream)) != hipSuccess) return e;
     if ((e = launch_rank(bt, stream)) != hipSuccess) return e;

@@ -135,8 +135,8 @@ enum : int { MODE_ITER = 0, MODE_FINAL = 1, MODE_BOOT = 2 };
 
 // Launchers (kcm_kernels.hip).  One iteration is
 //   tau, stepfk (post phase of the previous forces if pending, then the
-//   kinematics of each joint block), place, cellscan, scatter, rank, force,
-//   wrench;
+//   kinematics of each joint block), place, cellkey (the grid of the placed
+//   conformation, keys and counts), cellscan, scatter, rank, force, wrench;
 // a call ends with tau, stepfk(MODE_FINAL), finish.  A chain without a grid
 // (new, or new angles) first runs stepfk(MODE_BOOT), place(MODE_BOOT), gridboot.
 hipError_t launch_tau(const Batch &b, hipStream_t s);
@@ -144,6 +144,7 @@ hipError_t launch_stepfk(const Batch &b, int mode, hipStream_t s);
 hipError_t launch_gridboot(const Batch &b, hipStream_t s);
 hipError_t launch_finish(const Batch &b, hipStream_t s);
 hipError_t launch_place(const Batch &b, int mode, hipStream_t s);
+hipError_t launch_cellkey(const Batch &b, hipStream_t s);
 hipError_t launch_cellscan(const Batch &b, hipStream_t s);
 hipError_t launch_scatter(const Batch &b, hipStream_t s);
 constexpr int FORCE_SHAPE_COUNT = 4;  // launch shapes of the force kernel (kcm_set_force_variant)

@@ -220,7 +220,7 @@ __device__ __forceinline__ int cell_of(const Grid &g, const double4 &r)
     return (cz * g.dims[1] + cy) * g.dims[0] + cx;
 }
 
-constexpr double GRID_MARGIN = 2.0;  // A added around the previous bounding box
+constexpr double GRID_MARGIN = 2.0;  // A added around the bounding box of the placed atoms
 constexpr int LINKS_PER_BLOCK = 56;  // links touched by ATOM_BLOCK consecutive atoms (at most 53)
 
 // First atom moved by joint j: the first atom of link j+1 (C-alpha for phi,
@@ -278,6 +278,36 @@ __device__ __forceinline__ Xf joint_xf_of(const double4 &u, const double4 &p, do
 // grows until the grid fits the chain's cell capacity.  Block-wide (any block
 // size); returns false (and a one-cell grid) when the box is not finite or
 // cannot be covered.  s_red: [nw * 6].
+// The grid for the bounding box [lo, hi] of the placed atoms, plus a margin
+// (one thread); *ok stays true iff it could be sized within the capacity.
+__device__ Grid size_grid(const ChainDev *cd, const double lo[3], const double hi[3], bool *ok)
+{
+    double L3[3], H3[3];
+    for (int k = 0; k < 3; ++k) {
+        L3[k] = lo[k] - GRID_MARGIN;
+        H3[k] = hi[k] + GRID_MARGIN;
+        *ok = *ok && isfinite(L3[k]) && isfinite(H3[k]) && H3[k] >= L3[k] && (H3[k] - L3[k]) < 1e7;
+    }
+    const double reach_len = fmax(cd->cutoff, 2.0 * cd->roff_max + cd->delta_r) + 1e-7;
+    double cell = fmax(cd->cell_min, reach_len / MAX_REACH);
+    long long dims[3] = {1, 1, 1};
+    for (int it = 0; *ok && it < 200; ++it) {
+        for (int k = 0; k < 3; ++k) dims[k] = (long long)floor((H3[k] - L3[k]) / cell) + 1;
+        if (dims[0] * dims[1] * dims[2] <= cd->cap_cells) break;
+        cell *= 1.2599210498948732;
+    }
+    *ok = *ok && dims[0] * dims[1] * dims[2] <= cd->cap_cells;
+    Grid g;
+    for (int k = 0; k < 3; ++k) { g.origin[k] = *ok ? L3[k] : 0.0; g.dims[k] = *ok ? (int)dims[k] : 1; }
+    g.cell = cell;
+    g.inv_cell = 1.0 / cell;
+    g.reach = max(1, (int)ceil(reach_len / cell - 1e-9));
+    g.reach_len = reach_len;
+    g.n_cells = *ok ? (int)(dims[0] * dims[1] * dims[2]) : 1;
+    g.pad = 0;
+    return g;
+}
+
 __device__ bool grid_from_parts(const ChainDev *cd, Grid *out, double *s_red, int *s_ok)
 {
     const int n = cd->n_atoms;
@@ -312,31 +342,8 @@ __device__ bool grid_from_parts(const ChainDev *cd, Grid *out, double *s_red, in
         }
     }
     if (tid == 0) {
-        double L3[3], H3[3];
         bool ok = *s_ok != 0;
-        for (int k = 0; k < 3; ++k) {
-            L3[k] = lo[k] - GRID_MARGIN;
-            H3[k] = hi[k] + GRID_MARGIN;
-            ok = ok && isfinite(L3[k]) && isfinite(H3[k]) && H3[k] >= L3[k] && (H3[k] - L3[k]) < 1e7;
-        }
-        const double reach_len = fmax(cd->cutoff, 2.0 * cd->roff_max + cd->delta_r) + 1e-7;
-        double cell = fmax(cd->cell_min, reach_len / MAX_REACH);
-        long long dims[3] = {1, 1, 1};
-        for (int it = 0; ok && it < 200; ++it) {
-            for (int k = 0; k < 3; ++k) dims[k] = (long long)floor((H3[k] - L3[k]) / cell) + 1;
-            if (dims[0] * dims[1] * dims[2] <= cd->cap_cells) break;
-            cell *= 1.2599210498948732;
-        }
-        ok = ok && dims[0] * dims[1] * dims[2] <= cd->cap_cells;
-        Grid g;
-        for (int k = 0; k < 3; ++k) { g.origin[k] = ok ? L3[k] : 0.0; g.dims[k] = ok ? (int)dims[k] : 1; }
-        g.cell = cell;
-        g.inv_cell = 1.0 / cell;
-        g.reach = max(1, (int)ceil(reach_len / cell - 1e-9));
-        g.reach_len = reach_len;
-        g.n_cells = ok ? (int)(dims[0] * dims[1] * dims[2]) : 1;
-        g.pad = 0;
-        *out = g;
+        *out = size_grid(cd, lo, hi, &ok);
         *s_ok = ok ? 1 : 0;
     }
     __syncthreads();
@@ -446,21 +453,6 @@ __global__ __launch_bounds__(JOINT_BLOCK) void k_tau(Batch bt)
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(JOINT_BLOCK) void k_stepfk(Batch bt, int mode)
 {
-    if (blockIdx.x >= bt.total_jblocks) {
-        // one workgroup per chain: this iteration's grid of Sec. 3.2, sized
-        // from the bounding box of the last placement plus a margin, while
-        // the other workgroups step and scan the joints
-        const ChainDev *cg = bt.table[blockIdx.x - bt.total_jblocks];
-        ChainStats *sg = cg->stats;
-        if (mode != MODE_ITER || !sg->active) return;
-        __shared__ double s_gred[JOINT_BLOCK / WAVE * 6];
-        __shared__ int s_ok;
-        if (!grid_from_parts(cg, cg->grid, s_gred, &s_ok) && threadIdx.x == 0) {
-            sg->status = -4;
-            sg->grid_bad = 1;
-        }
-        return;
-    }
     const int c = find_block_owner(bt.jblk_off, bt.n_chains, blockIdx.x);
     const ChainDev *cd = bt.table[c];
     ChainStats *st = cd->stats;
@@ -640,10 +632,6 @@ __global__ __launch_bounds__(ATOM_BLOCK) void k_place(Batch bt, int mode)
         cd->r[a] = r;
         fin = isfinite(r.x) && isfinite(r.y) && isfinite(r.z);
         if (mode == MODE_ITER) {
-            const Grid g = *cd->grid;
-            const int key = cell_of(g, r);
-            cd->cell_key[a] = key;
-            atomicAdd(&cd->cell_count[key], 1);
             cd->f_cav[3 * a] = 0;
             cd->f_cav[3 * a + 1] = 0;
             cd->f_cav[3 * a + 2] = 0;
@@ -669,6 +657,56 @@ __global__ __launch_bounds__(ATOM_BLOCK) void k_place(Batch bt, int mode)
         }
         cd->bbox_part[6 * lb + k] = bad ? NAN : v;
     }
+}
+
+// ---------------------------------------------------------------------------
+// k_grid and k_cellkey: this iteration's grid of Sec. 3.2, sized by one wave
+// per chain from the bounding box of the positions just placed plus a margin,
+// then every atom's cell key and the cell counts.  The grid is a function of
+// the current conformation alone, so a chain rebuilt from saved angles
+// continues exactly as the original.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(WAVE) void k_grid(Batch bt)
+{
+    ChainDev *cd = bt.table[blockIdx.x];
+    ChainStats *st = cd->stats;
+    if (!running(st)) return;
+    const int lane = threadIdx.x, nblk = (cd->n_atoms + ATOM_BLOCK - 1) / ATOM_BLOCK;
+    double lo[3] = {DBL_MAX, DBL_MAX, DBL_MAX}, hi[3] = {-DBL_MAX, -DBL_MAX, -DBL_MAX};
+    bool fin = true;
+    for (int b = lane; b < nblk; b += WAVE)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const double l = cd->bbox_part[6 * b + k], h = cd->bbox_part[6 * b + 3 + k];
+            fin = fin && isfinite(l) && isfinite(h);
+            lo[k] = fmin(lo[k], l);
+            hi[k] = fmax(hi[k], h);
+        }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) { lo[k] = wave_min(lo[k]); hi[k] = wave_max(hi[k]); }
+    bool ok = !__any(!fin);
+    if (lane == 0) {
+        const Grid g = size_grid(cd, lo, hi, &ok);
+        if (ok) {
+            *cd->grid = g;
+        } else {
+            st->status = -4;
+            st->grid_bad = 1;
+        }
+    }
+}
+
+__global__ __launch_bounds__(ATOM_BLOCK) void k_cellkey(Batch bt)
+{
+    const int c = find_block_owner(bt.blk_off, bt.n_chains, blockIdx.x);
+    const ChainDev *cd = bt.table[c];
+    if (!running(cd->stats)) return;
+    const int a = (blockIdx.x - bt.blk_off[c]) * ATOM_BLOCK + threadIdx.x;
+    if (a >= cd->n_atoms) return;
+    const Grid g = *cd->grid;
+    const int key = cell_of(g, cd->r[a]);
+    cd->cell_key[a] = key;
+    atomicAdd(&cd->cell_count[key], 1);
 }
 
 // ---------------------------------------------------------------------------
@@ -2098,7 +2136,7 @@ hipError_t launch_tau(const Batch &b, hipStream_t s)
 hipError_t launch_stepfk(const Batch &b, int mode, hipStream_t s)
 {
     if (b.total_jblocks <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_stepfk, dim3(b.total_jblocks + b.n_chains), dim3(JOINT_BLOCK), 0, s, b, mode);
+    hipLaunchKernelGGL(k_stepfk, dim3(b.total_jblocks), dim3(JOINT_BLOCK), 0, s, b, mode);
     return hipGetLastError();
 }
 
@@ -2166,6 +2204,14 @@ hipError_t launch_place(const Batch &b, int mode, hipStream_t s)
 {
     if (b.total_blocks <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_place, dim3(b.total_blocks), dim3(ATOM_BLOCK), 0, s, b, mode);
+    return hipGetLastError();
+}
+
+hipError_t launch_cellkey(const Batch &b, hipStream_t s)
+{
+    if (b.total_blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_grid, dim3(b.n_chains), dim3(WAVE), 0, s, b);
+    hipLaunchKernelGGL(k_cellkey, dim3(b.total_blocks), dim3(ATOM_BLOCK), 0, s, b);
     return hipGetLastError();
 }
 

@@ -328,26 +328,28 @@ def test_free_trajectory_100_iterations(precision):
     gpu.free()
 
 
-@pytest.mark.parametrize("precision,tol", [(kcm.KCM_MIXED, 1e-9), (kcm.KCM_FP64, 1e-13)])
-def test_checkpoint_resume(precision, tol):
-    # a chain rebuilt from the angles of iteration 3 continues the trajectory.
-    # Its first grid is sized from its own positions rather than from the
-    # previous iteration's, so the candidate order (and with it the rounding
-    # of the pair sums) may differ: agreement to rounding, not bitwise.
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_checkpoint_resume(precision):
+    # A chain rebuilt from the angles after iteration 3 continues the
+    # trajectory bit for bit: each iteration's grid is sized from the
+    # conformation it places, so nothing but the angles carries over.  One
+    # call of 6 iterations, two calls of 3, and a rebuilt chain all agree.
     p = params(precision)
     seq = synth.sequence(30, 111)
     th = synth.random_dihedrals(30, 111)
     a = kcm.Chain(seq, TYPES, p, theta0=th)
     a.step(6)
-    ref = a.state()["theta"]
+    ref = a.state()
     b = kcm.Chain(seq, TYPES, p, theta0=th)
     b.step(3)
     mid = b.state()["theta"]
+    b.step(3)
     c = kcm.Chain(seq, TYPES, p, theta0=mid)
     c.step(3)
-    diff = float(np.abs(np.angle(np.exp(1j * (c.state()["theta"] - ref)))).max())
-    _log(case="resume", precision=precision, dtheta=diff)
-    assert diff <= tol
+    for other in (b.state(), c.state()):
+        for key in ("theta", "xyz", "force", "tau"):
+            assert np.array_equal(other[key], ref[key]), key
+    _log(case="resume", precision=precision, identical=True)
     for x in (a, b, c):
         x.free()
 
