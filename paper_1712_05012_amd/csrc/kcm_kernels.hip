@@ -706,7 +706,9 @@ __global__ __launch_bounds__(ATOM_BLOCK) void k_cellkey(Batch bt)
     const Grid g = *cd->grid;
     const int key = cell_of(g, cd->r[a]);
     cd->cell_key[a] = key;
-    atomicAdd(&cd->cell_count[key], 1);
+    // the atom's place among its cell's arrivals, kept for the scatter in
+    // the sorted-index array (free until the rank kernel fills it)
+    cd->s_idx[a] = atomicAdd(&cd->cell_count[key], 1);
 }
 
 // ---------------------------------------------------------------------------
@@ -951,12 +953,12 @@ __device__ void chunk_offsets(const ChainDev *cd, int nc, int *s_off, int *s_int
     __syncthreads();
 }
 
-// Slot of atom a in the cell-ordered arrays: the counting-sort scatter took
-// slots from the count (order left to the atomics); the stable slot is the
-// number of atoms of the cell with a smaller index, so everything downstream
-// is deterministic.  Gathers position (with the atom index in w) and
-// parameters into that slot.
-__device__ __forceinline__ void place_sorted(const ChainDev *cd, const int *ids, int a, int b, int e)
+// Slot of atom a in the cell-ordered arrays: the counting-sort scatter placed
+// the atoms of a cell in the order of their count atomics; the stable slot is
+// the number of atoms of the cell with a smaller index, so everything
+// downstream is deterministic.  Gathers position (with the atom index in w)
+// and parameters into that slot; returns the rank.
+__device__ __forceinline__ int place_sorted(const ChainDev *cd, const int *ids, int a, int b, int e)
 {
     int rank = 0;
     for (int s = b; s < e; ++s) rank += ids[s] < a ? 1 : 0;
@@ -965,6 +967,7 @@ __device__ __forceinline__ void place_sorted(const ChainDev *cd, const int *ids,
     cd->s_idx[pos] = a;
     cd->s_r[pos] = make_double4(r.x, r.y, r.z, __longlong_as_double((long long)a));
     cd->s_p[pos] = cd->aparam[a];
+    return rank;
 }
 
 // k_cellscan: one workgroup per chunk of SCAN_CHUNK cells of each chain's
@@ -1026,7 +1029,7 @@ __global__ __launch_bounds__(ATOM_BLOCK) void k_scatter(Batch bt)
     if (a >= cd->n_atoms) return;
     const int key = cd->cell_key[a];
     const int start = cd->cell_local[key] + s_off[key / SCAN_CHUNK];
-    cd->s_tmp[start + atomicSub(&cd->cell_count[key], 1) - 1] = a;
+    cd->s_tmp[start + cd->s_idx[a]] = a;
 }
 
 __global__ __launch_bounds__(ATOM_BLOCK) void k_rank(Batch bt)
@@ -1048,7 +1051,8 @@ __global__ __launch_bounds__(ATOM_BLOCK) void k_rank(Batch bt)
     const int key = cd->cell_key[a];
     const int b = cd->cell_local[key] + s_off[key / SCAN_CHUNK];
     const int e = key + 1 < nc ? cd->cell_local[key + 1] + s_off[(key + 1) / SCAN_CHUNK] : s_off[nb];
-    place_sorted(cd, cd->s_tmp, a, b, e);
+    // the first atom of each cell returns its count to zero for the next iteration
+    if (place_sorted(cd, cd->s_tmp, a, b, e) == 0) cd->cell_count[key] = 0;
 }
 
 // Loads, stores and atomics through a pointer of unknown address space are
