@@ -660,18 +660,19 @@ __global__ __launch_bounds__(ATOM_BLOCK) void k_place(Batch bt, int mode)
 }
 
 // ---------------------------------------------------------------------------
-// k_grid and k_cellkey: this iteration's grid of Sec. 3.2, sized by one wave
-// per chain from the bounding box of the positions just placed plus a margin,
-// then every atom's cell key and the cell counts.  The grid is a function of
-// the current conformation alone, so a chain rebuilt from saved angles
-// continues exactly as the original.
+// k_grid and k_cellkey: this iteration's grid of Sec. 3.2, sized from the
+// bounding box of the positions just placed plus a margin, then every atom's
+// cell key and the cell counts.  The grid is a function of the current
+// conformation alone, so a chain rebuilt from saved angles continues exactly
+// as the original.  Two launch forms with the same grid and keys: for large
+// batches one wave per chain sizes the grid (k_grid) and the key workgroups
+// read it; for small ones, where a launch costs more than the redundant work,
+// wave 0 of every key workgroup sizes it and the first one stores it.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(WAVE) void k_grid(Batch bt)
+// the grid from the chain's bounding-box partials (one wave; lane 0 gets it)
+__device__ __forceinline__ Grid wave_grid(const ChainDev *cd, bool *ok)
 {
-    ChainDev *cd = bt.table[blockIdx.x];
-    ChainStats *st = cd->stats;
-    if (!running(st)) return;
-    const int lane = threadIdx.x, nblk = (cd->n_atoms + ATOM_BLOCK - 1) / ATOM_BLOCK;
+    const int lane = (int)threadIdx.x & (WAVE - 1), nblk = (cd->n_atoms + ATOM_BLOCK - 1) / ATOM_BLOCK;
     double lo[3] = {DBL_MAX, DBL_MAX, DBL_MAX}, hi[3] = {-DBL_MAX, -DBL_MAX, -DBL_MAX};
     bool fin = true;
     for (int b = lane; b < nblk; b += WAVE)
@@ -684,27 +685,63 @@ __global__ __launch_bounds__(WAVE) void k_grid(Batch bt)
         }
 #pragma unroll
     for (int k = 0; k < 3; ++k) { lo[k] = wave_min(lo[k]); hi[k] = wave_max(hi[k]); }
-    bool ok = !__any(!fin);
-    if (lane == 0) {
-        const Grid g = size_grid(cd, lo, hi, &ok);
-        if (ok) {
-            *cd->grid = g;
-        } else {
-            st->status = -4;
-            st->grid_bad = 1;
-        }
+    *ok = !__any(!fin);
+    Grid g{};
+    if (lane == 0) g = size_grid(cd, lo, hi, ok);
+    return g;
+}
+
+__device__ __forceinline__ void store_grid(ChainDev *cd, ChainStats *st, const Grid &g, bool ok)
+{
+    if (ok) {
+        *cd->grid = g;
+    } else {
+        st->status = -4;
+        st->grid_bad = 1;
     }
 }
 
+__global__ __launch_bounds__(WAVE) void k_grid(Batch bt)
+{
+    ChainDev *cd = bt.table[blockIdx.x];
+    ChainStats *st = cd->stats;
+    if (!running(st)) return;
+    bool ok;
+    const Grid g = wave_grid(cd, &ok);
+    if (threadIdx.x == 0) store_grid(cd, st, g, ok);
+}
+
+template <bool OWN_GRID>
 __global__ __launch_bounds__(ATOM_BLOCK) void k_cellkey(Batch bt)
 {
     const int c = find_block_owner(bt.blk_off, bt.n_chains, blockIdx.x);
-    const ChainDev *cd = bt.table[c];
-    if (!running(cd->stats)) return;
-    const int a = (blockIdx.x - bt.blk_off[c]) * ATOM_BLOCK + threadIdx.x;
+    ChainDev *cd = bt.table[c];
+    ChainStats *st = cd->stats;
+    // with OWN_GRID, grid_bad is set by this kernel: a workgroup that sees it
+    // set by the first one would have found the same failure itself
+    if (!running(st)) return;
+    __shared__ int s_ok;
+    __shared__ Grid s_g;
+    const int lb = blockIdx.x - bt.blk_off[c];
+    if (OWN_GRID) {
+        if (threadIdx.x < WAVE) {
+            bool ok;
+            const Grid g = wave_grid(cd, &ok);
+            if (threadIdx.x == 0) {
+                s_g = g;
+                s_ok = ok ? 1 : 0;
+                if (lb == 0) store_grid(cd, st, g, ok);
+            }
+        }
+        __syncthreads();
+        if (!s_ok) return;
+    } else if (threadIdx.x == 0) {
+        s_g = *cd->grid;
+    }
+    if (!OWN_GRID) __syncthreads();
+    const int a = lb * ATOM_BLOCK + threadIdx.x;
     if (a >= cd->n_atoms) return;
-    const Grid g = *cd->grid;
-    const int key = cell_of(g, cd->r[a]);
+    const int key = cell_of(s_g, cd->r[a]);
     cd->cell_key[a] = key;
     // the atom's place among its cell's arrivals, kept for the scatter in
     // the sorted-index array (free until the rank kernel fills it)
@@ -2211,11 +2248,21 @@ hipError_t launch_place(const Batch &b, int mode, hipStream_t s)
     return hipGetLastError();
 }
 
+// Key workgroups (atoms / 256) from which the grid gets a launch of its own:
+// the 256-chain batch (3,196) runs faster split, the 1000-residue globule (40)
+// with the grid sized in every key workgroup.
+constexpr int CELLKEY_SPLIT_BLOCKS = 512;
+
 hipError_t launch_cellkey(const Batch &b, hipStream_t s)
 {
     if (b.total_blocks <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_grid, dim3(b.n_chains), dim3(WAVE), 0, s, b);
-    hipLaunchKernelGGL(k_cellkey, dim3(b.total_blocks), dim3(ATOM_BLOCK), 0, s, b);
+    // the separate sizing launch pays off once the key workgroups are many
+    if (b.total_blocks >= CELLKEY_SPLIT_BLOCKS) {
+        hipLaunchKernelGGL(k_grid, dim3(b.n_chains), dim3(WAVE), 0, s, b);
+        hipLaunchKernelGGL(k_cellkey<false>, dim3(b.total_blocks), dim3(ATOM_BLOCK), 0, s, b);
+    } else {
+        hipLaunchKernelGGL(k_cellkey<true>, dim3(b.total_blocks), dim3(ATOM_BLOCK), 0, s, b);
+    }
     return hipGetLastError();
 }
 
