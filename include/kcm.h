@@ -20,9 +20,18 @@
  *    position (ZP) of the paper's ZRPD convention is phi = psi = 180 degrees.
  *  * Host pointers are read during the call and not kept.  Device memory is
  *    owned by the caller: kcm_build_chain lays a chain out inside the block it
- *    is given and never frees it.  Host-side handles are owned by the library
- *    (kcm_chain_free).  hip_stream is a hipStream_t (NULL = default stream);
- *    work is queued asynchronously unless a function says it synchronises.
+ *    is given and never frees it.  The one exception is per-call bookkeeping:
+ *    kcm_step, kcm_fold, kcm_mc_minimize and kcm_set_theta_batch keep, per
+ *    (device, stream), a device table of the chain set (descriptor pointers
+ *    and four offset arrays, about 24 bytes per chain), the gathered per-chain
+ *    records (device and pinned host) and the captured HIP graphs; these are
+ *    allocated when a larger set first arrives, reused while the set is
+ *    unchanged (graphs are dropped when one of their chains is freed) and
+ *    kept until the process ends.  kcm_step_noalloc takes the same
+ *    bookkeeping from static device memory and allocates nothing.
+ *    Host-side handles are owned by the library (kcm_chain_free).  hip_stream
+ *    is a hipStream_t (NULL = default stream); work is queued asynchronously
+ *    unless a function says it synchronises.
  *  * Every function returns a kcm_status; no exception crosses the ABI.  The
  *    calling thread's last error message is available from kcm_last_error().
  *  * The entry points that launch work (kcm_step, kcm_fold, kcm_mc_minimize)
@@ -138,8 +147,13 @@ typedef struct kcm_chain kcm_chain;
 /* Fill *p with the defaults above. */
 void kcm_default_params(kcm_params *p);
 
-/* Bytes of caller-owned device memory a chain needs (256-byte aligned block).
- * Depends on n_res, desc->side_chains and params->n_orbits only. */
+/* Bytes of caller-owned device memory a chain needs (256-byte aligned block):
+ * the per-joint state of the kinematic chain (Sec. 2.1, Fig. 5), per-atom
+ * positions, parameters and forces (Secs. 2.2 and 3.4), the cell grid of
+ * Sec. 3.2 (capacity max(8192, 8n) cells) and the offset-sphere samples of
+ * Sec. 3.4.  Depends on n_res, desc->side_chains and params->n_orbits only.
+ * KCM_E_INVAL for a NULL argument or inputs kcm_build_chain would reject
+ * (n_res outside 1 .. 524288, bad parameters). */
 kcm_status kcm_chain_bytes(const kcm_chain_desc *desc, const kcm_params *params, size_t *bytes);
 
 /* Build a chain (Fig. 5 steps 1-3): zero-position geometry from the residue
@@ -234,9 +248,11 @@ kcm_status kcm_mc_minimize(kcm_chain *const *chains, int32_t n_chains, int32_t n
 kcm_status kcm_mc_best_theta(const kcm_chain *chain, void *hip_stream, double *theta);
 
 /* Copy a chain's state to host arrays (any pointer may be NULL); synchronises
- * hip_stream.  theta[J] and dtheta[J] (last applied step); xyz[n][3] and
- * force[n][3] (total) at the conformation of the last force evaluation;
- * tau[J]. */
+ * hip_stream.  theta[J] and dtheta[J] (the angles and the last applied step of
+ * eq KCM_07); xyz[n][3] and force[n][3] (total, eqs 02, 03 and F_cav_patch) at
+ * the conformation of the last force evaluation; tau[J] (eqs KCM_01-KCM_06).
+ * The angles are the whole state a chain carries from one iteration to the
+ * next: a chain built from them continues bit for bit. */
 kcm_status kcm_get_state(const kcm_chain *chain, void *hip_stream, double *theta, double *xyz,
                          double *force, double *tau, double *dtheta);
 
