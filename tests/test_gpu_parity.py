@@ -283,6 +283,37 @@ def test_batched_call_equals_separate_calls_bitwise():
         c.free()
 
 
+def test_large_batch_equals_separate_calls_bitwise():
+    # 48 chains of 260 residues make 528 atom workgroups: the batched call
+    # sizes each chain's grid in a launch of its own before the key pass,
+    # while a chain stepped alone (11 workgroups) sizes it inside the key
+    # workgroups.  Both forms must give the same grid, keys and results.
+    p = params(kcm.KCM_MIXED)
+    n, m = 48, 260
+    assert n * ((10 * m + 255) // 256) >= 512
+    alone, batch = [], []
+    for k in range(n):
+        seq = synth.sequence(m, 300 + k)
+        th = synth.random_dihedrals(m, 300 + k)
+        alone.append(kcm.Chain(seq, TYPES, p, theta0=th))
+        batch.append(kcm.Chain(seq, TYPES, p, theta0=th))
+    try:
+        for c in alone:
+            kcm.kcm_step([c], 2)
+        kcm.kcm_step(batch, 2)
+        for a, b in zip(alone, batch):
+            sa, sb = a.state(), b.state()
+            for key in ("theta", "xyz", "force", "tau"):
+                assert np.array_equal(sa[key], sb[key]), key
+            ga, gb = kcm.kcm_get_cells(a.handle), kcm.kcm_get_cells(b.handle)
+            assert np.array_equal(ga["dims"], gb["dims"]) and ga["cell"] == gb["cell"]
+            assert np.array_equal(ga["origin"], gb["origin"])
+            assert np.array_equal(ga["order"], gb["order"])
+    finally:
+        for c in alone + batch:
+            c.free()
+
+
 def test_runs_are_deterministic():
     p = params(kcm.KCM_MIXED)
     out = []
