@@ -47,9 +47,11 @@ struct ChainStats {
     int32_t mc_acc, mc_best;
 };
 // active is read by the torque and step kernels and written only at the end of
-// an iteration (or call); run (set by the step) and grid_bad (set by the grid
-// workgroups of the step kernel) are read by every later kernel.  So no kernel
-// reads a flag that another workgroup of the same kernel may change.
+// an iteration (or call); run (set by the step) and grid_bad (set where the
+// iteration's grid is sized, after the placement) are read by every later
+// kernel.  So no kernel reads a flag that another workgroup of the same kernel
+// may change, except grid_bad in the key kernel that sizes the grid in every
+// workgroup: all of them reach the same decision.
 
 // The cell grid of the current iteration (sized at its start from the last
 // bounding box).
