@@ -12,8 +12,8 @@ namespace kcm {
 
 constexpr int APR = 10;              // atoms per residue
 constexpr int CHAIN_THREADS = 1024;  // one workgroup per chain: 16 waves
-constexpr int SCAN_CHUNK = 16384;    // cells per workgroup of the cell-count scan
-constexpr int SCAN_MAX_CHUNKS = 4096;  // chunks per chain the scatter's offset table holds
+constexpr int SCAN_CHUNK = 4096;     // cells per workgroup of the cell-count scan
+constexpr int SCAN_MAX_CHUNKS = 16384; // chunks per chain the scatter's offset table holds
 constexpr int JOINT_BLOCK = 256;     // joints per workgroup of the torque / step / kinematics kernels
 constexpr int MAX_NBR = KCM_NBR_CHUNK; // solvation neighbours of one atom kept in LDS (the list, its atoms
                                       // and its events, 6,720 bytes, let 24 waves share a CU)

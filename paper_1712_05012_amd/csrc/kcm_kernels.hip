@@ -8,15 +8,15 @@
 //               forward kinematics of the new angles as an ordered prefix
 //               scan of rigid transforms inside each joint block (eqs
 //               kin_02-kin_04, r1; prefix computation item 1 of Sec. 3.5).
-//               One more workgroup per chain sizes the iteration's cell grid
-//               (Sec. 3.2) from the last bounding box plus a margin; atoms
-//               outside it are clamped to the border cells, which keeps every
-//               neighbour within the stencil.
 //   k_place     one thread per atom: link transforms (products of the
 //               earlier joint blocks composed in front of the block-local
-//               ones), r_a = G_link(a) r0_a, cell key on the grid of Sec. 3.2,
-//               cell count, bounding box of the new positions.
-//   k_cellscan  one workgroup per 16384 cells: exclusive scan of the counts
+//               ones), r_a = G_link(a) r0_a, per-workgroup bounding box of
+//               the new positions.
+//   k_cellkey   one thread per atom: the cell grid of Sec. 3.2 sized from
+//               that bounding box (in every workgroup of a small chain, in
+//               k_grid before it for a large one), cell key, count and the
+//               atom's place among its cell's arrivals.
+//   k_cellscan  one workgroup per 4096 cells: exclusive scan of the counts
 //               inside the chunk, and its total.
 //   (k_scatter and k_rank add the chunk offsets; k_rank writes the starts.)
 //   k_scatter   one thread per atom: counting-sort scatter by cell key.
