@@ -1197,6 +1197,32 @@ __device__ __forceinline__ double bcast(double x, int l)
     return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
+// a * b + c for a, b below 2^24 (b wave-uniform) as one full-rate 24-bit
+// multiply-add; the compiler otherwise may pick the quarter-rate 32-bit
+// multiply when it cannot bound b.
+__device__ __forceinline__ int mad_u24(int a, int b, int c)
+{
+    int r;
+    asm("v_mad_u32_u24 %0, %1, %2, %3" : "=v"(r) : "v"(a), "s"(b), "v"(c));
+    return r;
+}
+
+// Step-1 code of four FP32 tests t0..t3 of one sample against the neighbours
+// of a block: the sum of 32 + q over the tests with t_q >= 0.  Two byte
+// permutes gather the four sign bits as bytes (0xff for a negative test,
+// selectors 9 and 11 replicate the top bit of the low and the high source
+// word), and a signed dot product with the bytes 32..35 subtracts 32 + q for
+// each negative test from the sum over all four (134).  A test of exactly -0
+// counts as uncovered here; |t| = 0 lies in the FP32 band, so its sample is
+// decided again in FP64.
+__device__ __forceinline__ int block_code(float t0, float t1, float t2, float t3)
+{
+    const unsigned lo = __builtin_amdgcn_perm(__float_as_uint(t1), __float_as_uint(t0), 0x0c0c0b09u);
+    const unsigned hi = __builtin_amdgcn_perm(__float_as_uint(t3), __float_as_uint(t2), 0x0b090c0cu);
+    constexpr int ALL = 4 * 32 + 0 + 1 + 2 + 3;
+    return __builtin_amdgcn_sdot4((int)(lo | hi), 0x23222120, ALL, false);
+}
+
 // FP64 decision in absolute coordinates: is sample k of atom i covered by the
 // offset sphere of atom aj, shifted by delta_r along axis s (s < 0: not
 // shifted)?
@@ -1863,24 +1889,32 @@ __global__ __launch_bounds__(WAVE, sizeof(Real) == 4 ? 6 : 4) void k_force(Batch
                     for (int q = 0; q < SAT_CHECK; ++q) e[q] = s_nbr[u + q];
                     int next = 0;
                     const int lm = __builtin_amdgcn_readfirstlane(livem);
+                    const int kmul = (1 << ACC_SHIFT) + u - 32;
 #pragma unroll
                     for (int i = 0; i < SPL; ++i) {
                         if (!((lm >> i) & 1)) continue;
-                        // 32 per covering neighbour plus its index in the
-                        // block (both inline constants of the select); its
-                        // count c = blk >> 5 then adds c ((1 << ACC_SHIFT) + u)
-                        // + (blk - 32 c) to acc
-                        int blk = 0;
+                        // blk: 32 per covering neighbour plus its index in
+                        // the block; its count c = blk >> 5 then adds
+                        // c ((1 << ACC_SHIFT) + u) + (blk - 32 c) to acc
+                        Real t[SAT_CHECK];
 #pragma unroll
                         for (int q = 0; q < SAT_CHECK; ++q) {
-                            const Real t = fma(Qz[i], e[q].az, fma(Qy[i], e[q].ay, fma(Qx[i], e[q].ax, -e[q].c0)));
-                            blk += (t >= (Real)0) ? 32 + q : 0;
-                            if (MIXED) amin[i] = fmin(amin[i], fabs(t));
+                            t[q] = fma(Qz[i], e[q].az, fma(Qy[i], e[q].ay, fma(Qx[i], e[q].ax, -e[q].c0)));
+                            if (MIXED) amin[i] = fmin(amin[i], fabs(t[q]));
                         }
-                        acc[i] += blk + __mul24(blk >> 5, (1 << ACC_SHIFT) + u - 32);
+                        int blk;
+                        if constexpr (MIXED) {
+                            static_assert(SAT_CHECK == 4, "four sign bytes per word");
+                            blk = block_code(t[0], t[1], t[2], t[3]);
+                        } else {
+                            blk = 0;
+#pragma unroll
+                            for (int q = 0; q < SAT_CHECK; ++q) blk += (t[q] >= (Real)0) ? 32 + q : 0;
+                        }
+                        acc[i] = mad_u24(blk >> 5, kmul, acc[i] + blk);
                         if (__ballot(acc[i] < (2 << ACC_SHIFT))) next |= 1 << i;
                     }
-                    livem = __builtin_amdgcn_readfirstlane(next);
+                    livem = next;
                 };
                 // kept < 0: slot i of lane l holds sample kb + l + WAVE i;
                 // else the first `kept` staged samples fill the slots in order
