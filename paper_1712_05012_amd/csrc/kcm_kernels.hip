@@ -993,8 +993,9 @@ __device__ void chunk_offsets(const ChainDev *cd, int nc, int *s_off, int *s_int
 // Slot of atom a in the cell-ordered arrays: the counting-sort scatter placed
 // the atoms of a cell in the order of their count atomics; the stable slot is
 // the number of atoms of the cell with a smaller index, so everything
-// downstream is deterministic.  Gathers position (with the atom index in w)
-// and parameters into that slot; returns the rank.
+// downstream is deterministic.  Gathers position and parameters into that
+// slot; w holds the atom index in its low and the atom's residue in its high
+// 32 bits (read as integers only).  Returns the rank.
 __device__ __forceinline__ int place_sorted(const ChainDev *cd, const int *ids, int a, int b, int e)
 {
     int rank = 0;
@@ -1002,7 +1003,7 @@ __device__ __forceinline__ int place_sorted(const ChainDev *cd, const int *ids, 
     const int pos = b + rank;
     const double4 r = cd->r[a];
     cd->s_idx[pos] = a;
-    cd->s_r[pos] = make_double4(r.x, r.y, r.z, __longlong_as_double((long long)a));
+    cd->s_r[pos] = make_double4(r.x, r.y, r.z, __longlong_as_double((long long)a | ((long long)(a / APR) << 32)));
     cd->s_p[pos] = cd->aparam[a];
     return rank;
 }
@@ -1314,8 +1315,8 @@ __device__ __noinline__ PairSums pair_terms_fp64(CDev cd, int si, int off, int r
         const double ddx = rj.x - ri.x, ddy = rj.y - ri.y, ddz = rj.z - ri.z;
         const double d2 = dist2(ddx, ddy, ddz);
         if (!(ok && d2 <= cut2)) continue;
-        const int aj = (int)__double_as_longlong(rj.w);
-        const int res_j = aj / APR, dres = res_j - res_i;
+        const long long wj = __double_as_longlong(rj.w);
+        const int aj = (int)wj, res_j = (int)(wj >> 32), dres = res_j - res_i;
         double we = do_elec ? 1.0 : 0.0, wv = do_vdw ? 1.0 : 0.0;
         if (dres >= -1 && dres <= 1) {
             const uint32_t bit = 1u << ((dres + 1) * APR + (aj - res_j * APR));
@@ -1688,9 +1689,10 @@ __global__ __launch_bounds__(WAVE, sizeof(Real) == 4 ? 6 : 4) void k_force(Batch
 #pragma clang fp contract(off)
         const double ddx = rj.x - ri.x, ddy = rj.y - ri.y, ddz = rj.z - ri.z;
         const double d2 = dist2(ddx, ddy, ddz);
-        const int aj = (int)__double_as_longlong(rj.w);
+        const long long wj = __double_as_longlong(rj.w);
+        const int aj = (int)wj;
         if (valid && do_pair && d2 <= cut2) {
-            const int res_j = aj / APR, dres = res_j - res_i;
+            const int res_j = (int)(wj >> 32), dres = res_j - res_i;
             Real we = do_elec ? (Real)1 : (Real)0, wv = do_vdw ? (Real)1 : (Real)0;
             if (dres >= -1 && dres <= 1) {
                 const uint32_t bit = 1u << ((dres + 1) * APR + (aj - res_j * APR));
@@ -2036,18 +2038,22 @@ __global__ __launch_bounds__(WAVE, sizeof(Real) == 4 ? 6 : 4) void k_force(Batch
                             const NbrEntry<Real> e = s_nbr[own ? u : 0];
                             const int aj = s_nbr_a[own ? u : 0];
                             const Real lim = -(drr + k1 * fmax(fabs(e.ax), fmax(fabs(e.ay), fabs(e.az)))) - guard;
+                            // the neighbour's constants: base = q . a - (c0 + kq),
+                            // copy d tests base + drr q_d - k1 a_d
+                            Real cb = e.c0 + kq, sx = k1 * e.ax, sy = k1 * e.ay, sz = k1 * e.az;
+                            asm volatile("" : "+v"(sx), "+v"(sy), "+v"(sz));  // kept, not recomputed per sample
                             int d0 = 0, d1 = 0, d2 = 0;
                             unsigned long long em = em0;
                             while (em) {
                                 const int l = __ffsll((long long)em) - 1;
                                 em &= em - 1;
                                 const Real qx = bcast(Qx[i], l), qy = bcast(Qy[i], l), qz = bcast(Qz[i], l);
-                                const Real base = qx * e.ax + qy * e.ay + qz * e.az - e.c0 - kq;
+                                const Real base = fma(qz, e.az, fma(qy, e.ay, qx * e.ax)) - cb;
                                 if (own && base >= lim) {
                                     // events: the shifted copies that now cover the sample
-                                    const Real v0 = base + drr * qx - k1 * e.ax;
-                                    const Real v1 = base + drr * qy - k1 * e.ay;
-                                    const Real v2 = base + drr * qz - k1 * e.az;
+                                    const Real v0 = fma(drr, qx, base) - sx;
+                                    const Real v1 = fma(drr, qy, base) - sy;
+                                    const Real v2 = fma(drr, qz, base) - sz;
                                     d0 -= v0 >= (Real)0;
                                     d1 -= v1 >= (Real)0;
                                     d2 -= v2 >= (Real)0;
