@@ -133,6 +133,42 @@ void bond_class_masks(uint32_t m12[APR], uint32_t m13[APR], uint32_t m14[APR])
     }
 }
 
+// The bond classes of each slot as one word (two bits per atom of the
+// three-residue window), and the pair weights of each class in both
+// precisions, taken exactly as the force kernel applies them: the term flag
+// (1 or 0) times the class factor.
+template <typename Real>
+static int class_weights(const ChainDev &h, Real *tab)
+{
+    const Real we0 = (h.terms & KCM_TERM_ELEC) ? (Real)1 : (Real)0, wv0 = (h.terms & KCM_TERM_VDW) ? (Real)1 : (Real)0;
+    int skip = 0;
+    for (int c = 0; c < 4; ++c) {
+        Real we = we0, wv = wv0;
+        if (c == 1) { we = 0; wv = 0; }
+        else if (c == 2) { we *= (Real)h.w13; wv *= (Real)h.w13; }
+        else if (c == 3) { we *= (Real)h.w14e; wv *= (Real)h.w14v; }
+        tab[2 * c] = we;
+        tab[2 * c + 1] = wv;
+        if (we == (Real)0 && wv == (Real)0) skip |= 1 << c;
+    }
+    return skip;
+}
+
+void bond_class_table(ChainDev &h)
+{
+    for (int s = 0; s < APR; ++s) {
+        uint64_t w = 0;
+        for (int t = 0; t < 3 * APR; ++t) {
+            const uint32_t bit = 1u << t;
+            const uint64_t c = (h.m12[s] & bit) ? 1 : (h.m13[s] & bit) ? 2 : (h.m14[s] & bit) ? 3 : 0;
+            w |= c << (2 * t);
+        }
+        h.cls_word[s] = w;
+    }
+    h.skip_cls32 = class_weights<float>(h, h.wtab32);
+    h.skip_cls64 = class_weights<double>(h, h.wtab64);
+}
+
 // Polar geodesic samples (Sec. 3.4): n_orb orbits at polar angles pi (o + 1/2) / n_orb,
 // round(2 n_orb sin) points on each (at least one), evenly spaced in azimuth,
 // odd orbits offset by half a step.
@@ -651,6 +687,7 @@ kcm_status kcm_build_chain(const kcm_chain_desc *desc, const kcm_params *params,
     h.delta_r = params->delta_r;
     h.r_probe = params->r_probe;
     bond_class_masks(h.m12, h.m13, h.m14);
+    bond_class_table(h);
 
     // per-atom inputs
     const double k6 = std::pow(2.0, 1.0 / 6.0);

@@ -77,6 +77,14 @@ struct ChainDev {
     double w13, w14e, w14v, delta_r, r_probe, cell_min, roff_max;
     uint32_t m12[APR], m13[APR], m14[APR];  // bond classes per slot, bit (dres+1)*10 + slot_j
     uint32_t pad_masks[2];
+    // the same classes as one word per slot: two bits at bit 2 ((dres+1)*10 + slot_j),
+    // 0 none, 1 1-2, 2 1-3, 3 1-4 (m12 before m13 before m14); the (elec, vdw)
+    // pair weights of each class in FP32 and FP64, and bit c set when both
+    // weights of class c are zero
+    uint64_t cls_word[APR];
+    float wtab32[8];
+    double wtab64[8];
+    int32_t skip_cls32, skip_cls64;
 
     double *theta, *dtheta, *tau;
     double *mc_theta;    // [2][J]: accepted, then lowest angles of Monte Carlo minimization

@@ -1647,10 +1647,18 @@ __global__ __launch_bounds__(WAVE, sizeof(Real) == 4 ? 6 : 4) void k_force(Batch
     const double inv_2roff = 0.5 / roff_i;
     const double dr = cd->delta_r;
     const int res_i = ai / APR, slot_i = ai - res_i * APR;
-    const uint32_t m12 = cd->m12[slot_i], m13 = cd->m13[slot_i], m14 = cd->m14[slot_i];
-    const Real w13 = (Real)cd->w13, w14e = (Real)cd->w14e, w14v = (Real)cd->w14v;
     const Real coul = (Real)cd->coulomb;
     const Real qi = (Real)pi.x, Ri = (Real)pi.y, sei = (Real)pi.z;
+
+    // Bond class of each atom of residues res_i - 1 .. res_i + 1 relative to
+    // atom i, two bits per atom (0 none, 1 1-2, 2 1-3, 3 1-4), and the pair
+    // weights (elec, vdw) of each class, copied to LDS after the window table
+    // below in the event array (free until the candidates are done).
+    const unsigned long long cls_word = cd->cls_word[slot_i];
+    const int skip_cls = MIXED ? cd->skip_cls32 : cd->skip_cls64;  // bit c: class c adds nothing
+    Real *s_wtab = reinterpret_cast<Real *>(s_ev01 + 2 * WAVE);
+    if (lane < 8) s_wtab[lane] = MIXED ? (Real)cd->wtab32[lane] : (Real)cd->wtab64[lane];
+    __builtin_amdgcn_wave_barrier();
 
     // Sorted atom of candidate kw + lane, one window of 64 candidates at a
     // time, windows in increasing order.  Each non-empty row starting inside
@@ -1689,18 +1697,13 @@ __global__ __launch_bounds__(WAVE, sizeof(Real) == 4 ? 6 : 4) void k_force(Batch
 #pragma clang fp contract(off)
         const double ddx = rj.x - ri.x, ddy = rj.y - ri.y, ddz = rj.z - ri.z;
         const double d2 = dist2(ddx, ddy, ddz);
-        const long long wj = __double_as_longlong(rj.w);
-        const int aj = (int)wj;
+        const int aj = (int)__double_as_longlong(rj.w);
         if (valid && do_pair && d2 <= cut2) {
-            const int res_j = (int)(wj >> 32), dres = res_j - res_i;
-            Real we = do_elec ? (Real)1 : (Real)0, wv = do_vdw ? (Real)1 : (Real)0;
-            if (dres >= -1 && dres <= 1) {
-                const uint32_t bit = 1u << ((dres + 1) * APR + (aj - res_j * APR));
-                if (m12 & bit) { we = 0; wv = 0; }
-                else if (m13 & bit) { we *= w13; wv *= w13; }
-                else if (m14 & bit) { we *= w14e; wv *= w14v; }
-            }
-            if (we != (Real)0 || wv != (Real)0) {
+            // (dres + 1) APR + slot_j, in [0, 3 APR) iff |dres| <= 1
+            const int idx = aj - APR * res_i + APR;
+            const int cls = (unsigned)idx < 3u * APR ? (int)((cls_word >> (2 * idx)) & 3) : 0;
+            if (!((skip_cls >> cls) & 1)) {
+                const Real we = s_wtab[2 * cls], wv = s_wtab[2 * cls + 1];
                 const Real rx = (Real)ddx, ry = (Real)ddy, rz = (Real)ddz;
                 // mixed form: hardware reciprocal (1 ulp), far inside the force tolerance
                 const Real inv2 = MIXED ? (Real)__builtin_amdgcn_rcpf((float)d2) : (Real)1 / (Real)d2;
@@ -1778,7 +1781,8 @@ __global__ __launch_bounds__(WAVE, sizeof(Real) == 4 ? 6 : 4) void k_force(Batch
         // Atoms a few thousandths of an angstrom apart drive (D/d)^12 and the
         // force past the FP32 range: this atom's pair terms are taken again,
         // all in FP64 (a non-finite result then is a true one)
-        const PairSums ps = pair_terms_fp64(cd, si, off, rbase, T, nrows, res_i, m12, m13, m14, terms);
+        const PairSums ps = pair_terms_fp64(cd, si, off, rbase, T, nrows, res_i, cd->m12[slot_i], cd->m13[slot_i],
+                                            cd->m14[slot_i], terms);
         pv[0] = ps.f[0]; pv[1] = ps.f[1]; pv[2] = ps.f[2]; pv[3] = ps.e[0]; pv[4] = ps.e[1];
     }
 #pragma unroll
