@@ -1753,23 +1753,28 @@ __global__ __launch_bounds__(WAVE, sizeof(Real) == 4 ? 6 : 4) void k_force(Batch
     // Loads take 32-bit byte offsets from the chain's arrays (n < 2^26 atoms
     // of 32 bytes).
     const gptr<const char> sr = (gptr<const char>)glob(cd->s_r), sp = (gptr<const char>)glob(cd->s_p);
+    // The sorted atoms of the next trip are found while this trip's loads are
+    // in flight.
+    int sj[CPT];
+    auto map_trip = [&](int kb) {
+#pragma unroll
+        for (int q = 0; q < CPT; ++q) {
+            const int w = window_atom(kb + q * WAVE);  // wave-wide: every lane takes part
+            sj[q] = kb + q * WAVE + lane < T ? w : si;
+        }
+    };
+    if (T > 0) map_trip(0);
     for (int kb = 0; kb < T; kb += CPT * WAVE) {
-        int sj[CPT];
         bool ok[CPT];
         double4 rj[CPT], pj[CPT];
 #pragma unroll
         for (int q = 0; q < CPT; ++q) {
-            const int k = kb + q * WAVE + lane;
-            sj[q] = window_atom(kb + q * WAVE);
-            ok[q] = k < T && sj[q] != si;
-            if (k >= T) sj[q] = si;
-        }
-#pragma unroll
-        for (int q = 0; q < CPT; ++q) {
+            ok[q] = sj[q] != si;
             const unsigned ob = (unsigned)sj[q] * (unsigned)sizeof(double4);
             rj[q] = *(const gptr<const double4>)(sr + ob);
             pj[q] = *(const gptr<const double4>)(sp + ob);
         }
+        if (kb + CPT * WAVE < T) map_trip(kb + CPT * WAVE);
 #pragma unroll
         for (int q = 0; q < CPT; ++q) visit(ok[q], rj[q], pj[q]);
     }
