@@ -173,6 +173,42 @@ def test_pair_only_and_newton_third_law(precision):
     gpu.free()
 
 
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_bond_class_weights_and_single_pair_terms(precision):
+    """Scaled 1-3 and 1-4 pairs (eq 03_2) against the oracle with factors that
+    are neither 0 nor the defaults, so that every bond class takes its own
+    weights; then each pair term alone: its energy equals the combined run's,
+    the other term's is zero, and the two forces add up to the combined one."""
+    both = kcm.KCM_TERM_ELEC | kcm.KCM_TERM_VDW
+    tol_e = 1e-9 if precision == kcm.KCM_FP64 else 1e-5
+    w = dict(w13=0.4, w14_elec=0.7, w14_vdw=0.3)
+    p = params(precision, terms=both, **w)
+    gpu, ref, th = build_pair(24, 61, p)
+    st, o, err = compare_step(gpu, ref, th, p)
+    _log(case="bond_class_weights", precision=precision, **err)
+    assert err["status"] == 0
+    assert err["F"] <= F_TOL and err["F_pair"] <= F_TOL
+    assert err["E_elec"] < tol_e and err["E_vdw"] < tol_e
+    assert err["tau"] <= TAU_TOL[precision]
+    gpu.set_theta(th)
+    rep = gpu.step(1)
+    f_both = gpu.forces()[0]
+    e_both = (rep.e_elec, rep.e_vdw)
+    gpu.free()
+    f_one, e_one = [], []
+    for t in (kcm.KCM_TERM_ELEC, kcm.KCM_TERM_VDW):
+        g, _, _ = build_pair(24, 61, params(precision, terms=t, **w), theta=th)
+        r = g.step(1)
+        f_one.append(g.forces()[0])
+        e_one.append((r.e_elec, r.e_vdw))
+        g.free()
+    assert e_one[0][1] == 0.0 and e_one[1][0] == 0.0
+    assert abs(e_one[0][0] - e_both[0]) <= tol_e * max(abs(e_both[0]), 1.0)
+    assert abs(e_one[1][1] - e_both[1]) <= tol_e * max(abs(e_both[1]), 1.0)
+    fmax = np.abs(f_both).max()
+    assert np.abs(f_one[0] + f_one[1] - f_both).max() <= F_TOL * fmax
+
+
 @pytest.mark.parametrize("rule", [kcm.KCM_STEP_CAPPED, kcm.KCM_STEP_PAPER, kcm.KCM_STEP_LINEAR])
 def test_step_rules_and_masks(rule):
     p = params(kcm.KCM_FP64, step_rule=rule, kappa=1e-6 if rule == kcm.KCM_STEP_LINEAR else 1e-3)
