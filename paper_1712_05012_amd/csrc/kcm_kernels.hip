@@ -1878,7 +1878,7 @@ __global__ __launch_bounds__(WAVE, sizeof(Real) == 4 ? 6 : 4) void k_force(Batch
                     acc[i] = 0;
                     amin[i] = (Real)1e30;
                 }
-                // Blocks of 8 neighbours, read once for the four slots.  Once
+                // Blocks of SAT_CHECK neighbours, read once for the four slots.  Once
                 // every sample of a slot has two overlappers (decisions
                 // outside the FP32 band; a sample with a test inside it is
                 // recounted below over the whole list) the rest of the list
