@@ -960,11 +960,6 @@ __global__ __launch_bounds__(JOINT_BLOCK) void k_set_theta(Batch bt, const doubl
 // cell list: exclusive scan of the counts, counting-sort scatter, stable
 // order inside each cell, gather into cell order
 // ---------------------------------------------------------------------------
-// LDS index of scan element i: one pad word per 32 elements, so the threads of
-// a wave reading their runs of consecutive elements hit different banks
-__device__ __forceinline__ int scan_pad(int i) { return i + (i >> 5); }
-constexpr int SCAN_LDS = SCAN_CHUNK + SCAN_CHUNK / 32;
-
 // Chunk offsets of the chain's current grid, block-wide: s_off[b] = number of
 // atoms in the cells of the chunks before chunk b, for b = 0 .. nb (s_off[nb]:
 // all atoms).  The cell start of cell c is cell_local[c] + s_off[c / SCAN_CHUNK].
@@ -1010,47 +1005,42 @@ __device__ __forceinline__ int place_sorted(const ChainDev *cd, const int *ids, 
 
 // k_cellscan: one workgroup per chunk of SCAN_CHUNK cells of each chain's
 // capacity (chunks past the current grid return at once): the exclusive scan
-// of the counts inside the chunk, and the chunk's total.  The chunk offsets
-// are added by the scatter and rank kernels; k_rank writes the final starts.
+// of the counts inside the chunk, and the chunk's total.  Each thread takes
+// four consecutive cells as one 16-byte load (the capacity is a multiple of
+// 8 cells, so a load that starts inside the grid stays inside the array),
+// scans them in registers, and the block scans the thread totals.  The chunk
+// offsets are added by the scatter and rank kernels; k_rank writes the final
+// starts.
 __global__ __launch_bounds__(CHAIN_THREADS) void k_cellscan(Batch bt)
 {
+    static_assert(SCAN_CHUNK == 4 * CHAIN_THREADS, "four cells per thread");
     const int c = find_block_owner(bt.scan_off, bt.n_chains, blockIdx.x);
     const ChainDev *cd = bt.table[c];
     if (!running(cd->stats)) return;
     const int b = blockIdx.x - bt.scan_off[c];
     const int nc = cd->grid->n_cells, c0 = b * SCAN_CHUNK;
     if (c0 >= nc) return;
-    __shared__ int s_buf[SCAN_LDS];
     __shared__ int s_int[CHAIN_THREADS / WAVE];
-    const int *__restrict__ count = cd->cell_count;
-    int *__restrict__ local = cd->cell_local;
-    const int tid = threadIdx.x, nt = blockDim.x;
-    constexpr int PER = SCAN_CHUNK / CHAIN_THREADS;
-    const int m = min(SCAN_CHUNK, nc - c0);
-#pragma unroll
-    for (int k = 0; k < PER; ++k) {
-        const int i = k * nt + tid;
-        s_buf[scan_pad(i)] = i < m ? count[c0 + i] : 0;
+    const int m = min(SCAN_CHUNK, nc - c0), i0 = 4 * (int)threadIdx.x;
+    int4 v = make_int4(0, 0, 0, 0);
+    if (i0 < m) {
+        v = *reinterpret_cast<const int4 *>(cd->cell_count + c0 + i0);
+        if (i0 + 1 >= m) v.y = 0;
+        if (i0 + 2 >= m) v.z = 0;
+        if (i0 + 3 >= m) v.w = 0;
     }
-    __syncthreads();
-    int loc = 0;
-#pragma unroll
-    for (int k = 0; k < PER; ++k) loc += s_buf[scan_pad(tid * PER + k)];
     int total = 0;
-    int run = block_excl_scan(loc, s_int, &total);
-#pragma unroll
-    for (int k = 0; k < PER; ++k) {
-        const int v = s_buf[scan_pad(tid * PER + k)];
-        s_buf[scan_pad(tid * PER + k)] = run;
-        run += v;
+    const int run = block_excl_scan(v.x + v.y + v.z + v.w, s_int, &total);
+    const int4 o = make_int4(run, run + v.x, run + v.x + v.y, run + v.x + v.y + v.z);
+    int *__restrict__ local = cd->cell_local + c0 + i0;
+    if (i0 + 3 < m) {
+        *reinterpret_cast<int4 *>(local) = o;
+    } else if (i0 < m) {
+        local[0] = o.x;
+        if (i0 + 1 < m) local[1] = o.y;
+        if (i0 + 2 < m) local[2] = o.z;
     }
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < PER; ++k) {
-        const int i = k * nt + tid;
-        if (i < m) local[c0 + i] = s_buf[scan_pad(i)];
-    }
-    if (tid == 0) cd->scan_part[b] = total;
+    if (threadIdx.x == 0) cd->scan_part[b] = total;
 }
 
 // k_scatter and k_rank: one thread per atom; the dynamic LDS holds the chunk
