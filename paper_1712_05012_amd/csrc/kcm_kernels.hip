@@ -738,14 +738,38 @@ __global__ __launch_bounds__(ATOM_BLOCK) void k_cellkey(Batch bt)
     } else if (threadIdx.x == 0) {
         s_g = *cd->grid;
     }
-    if (!OWN_GRID) __syncthreads();
+    // Atoms of the workgroup that share a cell take one count atomic between
+    // them: an LDS table (open addressing on the key, twice as many slots as
+    // atoms, so a probe always ends) gives each atom its rank among them, the
+    // first adds their number to the cell's count, and each atom's place among
+    // the cell's arrivals is the returned base plus its rank.
+    constexpr int HSLOTS = 2 * ATOM_BLOCK;
+    __shared__ int s_hkey[HSLOTS], s_hcnt[HSLOTS], s_hbase[HSLOTS];
+    for (int h = threadIdx.x; h < HSLOTS; h += ATOM_BLOCK) {
+        s_hkey[h] = -1;
+        s_hcnt[h] = 0;
+    }
+    __syncthreads();
     const int a = lb * ATOM_BLOCK + threadIdx.x;
-    if (a >= cd->n_atoms) return;
-    const int key = cell_of(s_g, cd->r[a]);
-    cd->cell_key[a] = key;
-    // the atom's place among its cell's arrivals, kept for the scatter in
-    // the sorted-index array (free until the rank kernel fills it)
-    cd->s_idx[a] = atomicAdd(&cd->cell_count[key], 1);
+    const bool valid = a < cd->n_atoms;
+    int key = 0, slot = 0, rank = 0;
+    if (valid) {
+        key = cell_of(s_g, cd->r[a]);
+        cd->cell_key[a] = key;
+        slot = (int)(((unsigned)key * 2654435761u) >> 23) & (HSLOTS - 1);
+        for (;;) {
+            const int prev = atomicCAS(&s_hkey[slot], -1, key);
+            if (prev == -1 || prev == key) break;
+            slot = (slot + 1) & (HSLOTS - 1);
+        }
+        rank = atomicAdd(&s_hcnt[slot], 1);
+    }
+    __syncthreads();
+    if (valid && rank == 0) s_hbase[slot] = atomicAdd(&cd->cell_count[key], s_hcnt[slot]);
+    __syncthreads();
+    // kept for the scatter in the sorted-index array (free until the rank
+    // kernel fills it)
+    if (valid) cd->s_idx[a] = s_hbase[slot] + rank;
 }
 
 // ---------------------------------------------------------------------------
