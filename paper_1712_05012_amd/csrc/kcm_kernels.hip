@@ -1017,8 +1017,16 @@ __device__ void chunk_offsets(const ChainDev *cd, int nc, int *s_off, int *s_int
 // 32 bits (read as integers only).  Returns the rank.
 __device__ __forceinline__ int place_sorted(const ChainDev *cd, const int *ids, int a, int b, int e)
 {
+    // the cell's members four at a time, every load issued before any is
+    // compared (indices clamped into the cell, which holds a itself, e > b)
     int rank = 0;
-    for (int s = b; s < e; ++s) rank += ids[s] < a ? 1 : 0;
+    for (int s = b; s < e; s += 4) {
+        int v[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) v[k] = ids[min(s + k, e - 1)];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) rank += (s + k < e && v[k] < a) ? 1 : 0;
+    }
     const int pos = b + rank;
     const double4 r = cd->r[a];
     cd->s_idx[pos] = a;
@@ -1096,8 +1104,22 @@ __global__ __launch_bounds__(ATOM_BLOCK) void k_rank(Batch bt)
     // the final cell starts (nc + 1 of them), a slice per workgroup of the chain
     const int lb = blockIdx.x - bt.blk_off[c], nblk = bt.blk_off[c + 1] - bt.blk_off[c];
     const int per = (nc + 1 + nblk - 1) / nblk, i1 = min(nc + 1, (lb + 1) * per);
-    for (int i = lb * per + (int)threadIdx.x; i < i1; i += ATOM_BLOCK)
-        cd->cell_start[i] = i < nc ? cd->cell_local[i] + s_off[i / SCAN_CHUNK] : s_off[nb];
+    {
+        // four cells per thread per step, the loads issued before the stores
+        // (indices clamped into the grid, which has at least one cell)
+        const int *__restrict__ loc = cd->cell_local;
+        int *__restrict__ start = cd->cell_start;
+        for (int i = lb * per + (int)threadIdx.x; i < i1; i += 4 * ATOM_BLOCK) {
+            int v[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) v[k] = loc[min(i + k * ATOM_BLOCK, nc - 1)];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int j = i + k * ATOM_BLOCK;
+                if (j < i1) start[j] = j < nc ? v[k] + s_off[j / SCAN_CHUNK] : s_off[nb];
+            }
+        }
+    }
     const int a = lb * ATOM_BLOCK + threadIdx.x;
     if (a >= cd->n_atoms) return;
     const int key = cd->cell_key[a];
